@@ -1,0 +1,162 @@
+/*
+ * librf -- ratio-filter reconstruction of matched-filter SNR series on one
+ * MI355X (gfx950).  C ABI; every pointer argument is a plain host or device
+ * pointer as stated per argument; no C++ types cross this boundary.
+ *
+ * Method: Murakami, Ghosh, Morisaki, "Efficient Reconstruction of
+ * Matched-Filter Signal-to-Noise Ratio Time Series from Nearby Templates for
+ * Compact Binary Coalescences Searches", arXiv 2511.12894.
+ *
+ * Conventions (section II): a~(f) = int a(t) exp(-2 pi i f t) dt.  A data
+ * segment holds n samples at rate fs (n a power of two, 2^8 <= n <= 2^24);
+ * frequency series hold bins j = 0..n/2 at f_j = j fs / n.  The analysis band
+ * is B = { j : f_low <= f_j <= f_high } (the S_n = +inf convention of
+ * section II.A).  Complex values are interleaved (re, im).
+ *
+ * Streams: every call enqueues its work on the stream given to
+ * rf_ctx_create.  A call that returns host data (sigma, counts, supports)
+ * synchronises that stream before it returns; the others do not.
+ *
+ * Errors: every call returns an rf_status and never aborts; RF_E_INVAL is
+ * returned for null pointers, sizes out of range or an inconsistent grid,
+ * before any work is enqueued.  After an error the outputs are undefined and
+ * the context stays usable; rf_last_error gives a message.
+ */
+#ifndef RF_H
+#define RF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RF_OK = 0,
+  RF_E_INVAL = 1,        /* bad argument                                      */
+  RF_E_NOMEM = 2,        /* device or host allocation failed                  */
+  RF_E_HIP = 3,          /* a HIP runtime call failed                         */
+  RF_E_UNSUPPORTED = 4,  /* valid request this build does not implement       */
+  RF_E_OVERFLOW = 5      /* trigger buffer too small; true count is returned  */
+} rf_status;
+
+typedef struct rf_ctx rf_ctx;           /* device, borrowed stream, workspace */
+typedef struct rf_kernels rf_kernels;   /* truncated ratio kernels on device  */
+
+/* Non-spinning template in detector-frame solar masses; TaylorF2 phase to
+ * 3.5PN with Newtonian amplitude, coalescence time and phase zero. */
+typedef struct { double m1, m2; } rf_tmpl;
+
+/* Segment sampling and analysis band (section II.A), taper widths (section
+ * II.C: df_high = 53 Hz, df_low capped at df_low_max = 5 Hz).  Requirements:
+ * n a power of two in [2^8, 2^24]; 0 < f_low - df_low_max;
+ * f_low < f_high; f_high + df_high <= fs / 2. */
+typedef struct {
+  double fs;
+  int64_t n;
+  double f_low, f_high;
+  double df_high, df_low_max;
+} rf_grid;
+
+/* Unit of the truncation threshold (section II.D): the paper's 1/s on
+ * r(t) = fs * w, or a bare value on the tap w itself. */
+typedef enum { RF_THR_PER_SECOND = 0, RF_THR_PER_TAP = 1 } rf_thr_unit;
+
+/* Arithmetic of the reconstruction: plain FP32 (FP32 matrix cores), or
+ * z = z_hi + z_lo, w = w_hi + w_lo in FP16 with the three products
+ * hi*hi + hi*lo + lo*hi accumulated in FP32. */
+typedef enum { RF_PREC_FP32 = 0, RF_PREC_SPLIT_FP16 = 1 } rf_prec;
+
+/* Peak of one series: max_m |z[m]| and the smallest m attaining it.  The
+ * comparison is made on |z|^2 = re*re + im*im in FP32 (no fused multiply-add). */
+typedef struct { float max_absz; int32_t argmax; } rf_peak;
+
+/* One threshold crossing |z[idx]| > thr of series `tmpl` of segment `seg`. */
+typedef struct { int32_t tmpl, seg, idx; float absz, argz; } rf_trigger;
+
+/* Fused read-out for snr_reconstruct (all pointers device except ntrig). */
+typedef struct {
+  float thr;              /* trigger threshold on |z| (> thr)                 */
+  rf_peak* peaks;         /* device [nk]: peak of each reconstructed series   */
+  rf_trigger* trig;       /* device [cap]: triggers, unspecified order         */
+  int64_t cap;            /* capacity of trig (>= 0)                          */
+  int64_t* ntrig;         /* host: number of triggers found (may exceed cap)  */
+} rf_peak_args;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream; borrowed, not destroyed).
+ * *out receives the context; free it with rf_ctx_destroy. */
+rf_status rf_ctx_create(int device, void* hip_stream, rf_ctx** out);
+rf_status rf_ctx_destroy(rf_ctx* ctx);
+/* Message of the last failed call on ctx (static storage owned by ctx). */
+const char* rf_last_error(const rf_ctx* ctx);
+
+/* Complex matched-filter SNR series of nt templates (section II.A, equation
+ * matched_filter; for the reference template, equation snr_ref):
+ *   N_h^2 = 4 df sum_B |h~_j|^2 / S_j,
+ *   z[m]  = sum_{j in B} (4 df / N_h) x~_j conj(h~_j) / S_j exp(2 pi i j m / n),
+ * i.e. the SNR for coalescence time m / fs, circular in the segment.
+ *   xf    device complex128 [n/2+1]: data x~(f_j) (read only)
+ *   psd   device double [n/2+1]: one-sided S_n(f_j) > 0 on B (read only)
+ *   tmpl  host [nt] templates; nt >= 1
+ *   z     device complex64 [nt][n] (written)
+ *   sigma host double [nt] or NULL: N_h of each template (then the call syncs)
+ * FP64 template phase and spectrum, FP32 FFT. */
+rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
+                     const rf_tmpl* tmpl, int32_t nt, void* z, double* sigma);
+
+/* Exact truncated ratio kernels of nk targets against one reference
+ * (sections II.B-II.D):
+ *   R~_j = W(f_j) (B_k/B_ref)(f_j) exp(-i (Psi_k - Psi_ref)(f_j)), j = 0..nb/2,
+ *   w    = inverse real DFT of R~ over nb = n_build points (FP64),
+ *   kept taps: signed indices [m_lo, m_hi] spanning every |w| >= thr/fs
+ *   (RF_THR_PER_SECOND) or |w| >= thr (RF_THR_PER_TAP), all taps in between kept;
+ *   norm_ratio = N_ref / N_k.
+ * W is equation (window) with df_high from the grid and
+ * df_low = min(df_low_max, |dtau'(f_low)|^(-1/2)) per target.
+ *   psd     device double [n/2+1] (for the norms)
+ *   ref     reference template; nbr host [nk] targets, nk >= 1
+ *   n_build power of two, 2^8 <= n_build <= n (0 means n)
+ *   *out    receives the kernel set (device memory owned by the set).
+ * Synchronises the stream. */
+rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd, rf_tmpl ref,
+                             const rf_tmpl* nbr, int32_t nk, double thr, rf_thr_unit unit,
+                             int64_t n_build, rf_kernels** out);
+
+/* Host copies of the kernel-set layout: any pointer may be NULL.
+ * nk: count; m_lo[nk], len[nk] (len = m_hi - m_lo + 1, 0 if nothing reaches
+ * the threshold); norm_ratio[nk] = N_ref / N_k; df_low[nk] taper widths. */
+rf_status rf_kernels_info(const rf_kernels* k, int32_t* nk, int64_t* m_lo, int32_t* len,
+                          double* norm_ratio, double* df_low);
+/* FP64 taps of kernel idx into host_out[len[idx]]. */
+rf_status rf_kernels_taps_fp64(const rf_kernels* k, int32_t idx, double* host_out);
+rf_status rf_kernels_free(rf_kernels* k);
+
+/* Reconstructed SNR series of every kernel's target (section II.B, equation
+ * convolution, on the circular segment):
+ *   z_k[m] = (N_ref / N_k) sum_{s = m_lo}^{m_hi} z_ref[(m + s) mod n] w_k[s].
+ *   z_ref  device complex64 [n] (from mf_ref_snr of the reference)
+ *   n      segment length (power of two, >= the kernels' n_build)
+ *   prec   RF_PREC_FP32 or RF_PREC_SPLIT_FP16
+ *   z_out  device complex64 [nk][n], or NULL to skip the series
+ *   fused  NULL, or peak/trigger read-out of every series (then the call syncs);
+ *          at least one of z_out and fused must be non-NULL.
+ * Returns RF_E_OVERFLOW when fused->cap is exceeded (counts still valid). */
+rf_status snr_reconstruct(rf_ctx* ctx, const rf_kernels* k, const void* z_ref, int64_t n,
+                          rf_prec prec, void* z_out, const rf_peak_args* fused);
+
+/* Peak and threshold read-out of nt series of n samples (section IV reads
+ * the peak SNR of each series):
+ *   z      device complex64 [nt][n]
+ *   peaks  device rf_peak [nt]
+ *   trig   device rf_trigger [cap] (seg = 0), unspecified order
+ *   ntrig  host: number of crossings |z| > thr (may exceed cap).
+ * Synchronises; RF_E_OVERFLOW when the count exceeds cap. */
+rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr, rf_peak* peaks,
+                    rf_trigger* trig, int64_t cap, int64_t* ntrig);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RF_H */

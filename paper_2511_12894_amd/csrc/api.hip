@@ -1,0 +1,491 @@
+// C-ABI entry points of librf: argument checks, workspace, scheduling of the
+// kernels in fft.hip, spectra.hip and recon.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "recon.h"
+
+namespace rf {
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void* DevBuf::ensure(size_t n) {
+  if (n <= bytes && p) return p;
+  release();
+  if (hipMalloc(&p, n) != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error{RF_E_NOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+  }
+  bytes = n;
+  return p;
+}
+
+void validate_grid(const rf_grid* g) {
+  RF_CHECK(g != nullptr, "grid is NULL");
+  RF_CHECK(is_pow2(g->n) && g->n >= 256 && g->n <= (int64_t(1) << 24),
+           "grid.n must be a power of two in [2^8, 2^24]");
+  RF_CHECK(std::isfinite(g->fs) && g->fs > 0, "grid.fs must be positive");
+  RF_CHECK(g->df_high > 0 && g->df_low_max > 0, "taper widths must be positive");
+  RF_CHECK(g->f_low - g->df_low_max > 0, "need f_low - df_low_max > 0");
+  RF_CHECK(g->f_high > g->f_low, "need f_high > f_low");
+  RF_CHECK(g->f_high + g->df_high <= 0.5 * g->fs * (1 + 1e-15), "need f_high + df_high <= fs / 2");
+}
+
+namespace {
+
+void validate_tmpl(const rf_tmpl& t) {
+  RF_CHECK(std::isfinite(t.m1) && std::isfinite(t.m2) && t.m1 > 0 && t.m2 > 0,
+           "template masses must be positive");
+}
+
+template <typename F>
+rf_status guarded(rf_ctx* ctx, F&& f) {
+  try {
+    if (ctx) {
+      hipError_t e = hipSetDevice(ctx->device);
+      if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e)};
+    }
+    f();
+    return RF_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return RF_E_NOMEM;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unexpected exception";
+    return RF_E_HIP;
+  }
+}
+
+// Small per-call tables: staged in a host copy owned by the context (so the
+// source outlives an asynchronous copy), then copied on the context stream.
+template <typename T>
+T* upload(rf_ctx* ctx, int slot, const T* host, size_t count) {
+  T* d = static_cast<T*>(ctx->ws[slot].ensure(sizeof(T) * std::max<size_t>(count, 1)));
+  std::vector<char>& stage = ctx->host_stage[slot];
+  stage.assign(reinterpret_cast<const char*>(host), reinterpret_cast<const char*>(host + count));
+  RF_HIP(hipMemcpyAsync(d, stage.data(), sizeof(T) * count, hipMemcpyHostToDevice, ctx->stream));
+  return d;
+}
+
+template <typename T>
+T* dev_alloc(size_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{RF_E_NOMEM, "device allocation failed"};
+  }
+  return static_cast<T*>(p);
+}
+
+void sync(rf_ctx* ctx) { RF_HIP(hipStreamSynchronize(ctx->stream)); }
+
+double pow2_scale_for(double maxabs) {
+  if (!(maxabs > 0)) return 1.0;
+  int ex = 0;
+  std::frexp(maxabs, &ex);
+  return std::ldexp(1.0, 14 - ex);   // maxabs * s in [2^13, 2^14)
+}
+
+void free_kernels(rf_kernels* k) {
+  if (!k) return;
+  for (void* p : {(void*)k->taps64, (void*)k->tiles_dev, (void*)k->b32, (void*)k->b16,
+                  (void*)k->colscale32, (void*)k->colscale16, (void*)k->slot_kernel})
+    if (p) (void)hipFree(p);
+  delete k;
+}
+
+}  // namespace
+}  // namespace rf
+
+using namespace rf;
+
+extern "C" {
+
+rf_status rf_ctx_create(int device, void* hip_stream, rf_ctx** out) {
+  if (!out) return RF_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RF_E_INVAL;
+  rf_ctx* c = new (std::nothrow) rf_ctx();
+  if (!c) return RF_E_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return RF_E_HIP;
+  }
+  *out = c;
+  return RF_OK;
+}
+
+rf_status rf_ctx_destroy(rf_ctx* ctx) {
+  if (!ctx) return RF_E_INVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->ws) b.release();
+  delete ctx;
+  return RF_OK;
+}
+
+const char* rf_last_error(const rf_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
+                     const rf_tmpl* tmpl, int32_t nt, void* z, double* sigma) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    validate_grid(grid);
+    RF_CHECK(xf && psd && tmpl && z, "mf_ref_snr: null pointer");
+    RF_CHECK(nt >= 1, "mf_ref_snr: nt must be >= 1");
+    const int64_t n = grid->n;
+    std::vector<Tf2Coef> coef(nt);
+    for (int i = 0; i < nt; ++i) {
+      validate_tmpl(tmpl[i]);
+      coef[i] = tf2_coef(tmpl[i]);
+    }
+    Tf2Coef* coef_dev = upload(ctx, WS_COEF, coef.data(), coef.size());
+    double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
+    band_moment(ctx, grid, psd, moment);
+    // templates in batches so the spectrum + FFT scratch stays near 512 MiB
+    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 26) / n)));
+    float2* Y = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(n) * per));
+    float2* zo = static_cast<float2*>(z);
+    for (int t0 = 0; t0 < nt; t0 += per) {
+      const int cnt = std::min(per, nt - t0);
+      mf_spectrum(ctx, grid, static_cast<const double2*>(xf), psd, coef_dev + t0, moment, Y, cnt);
+      fft_inverse_f32(ctx, Y, zo + int64_t(t0) * n, n, cnt);
+    }
+    if (sigma) {
+      double mom = 0;
+      RF_HIP(hipMemcpyAsync(&mom, moment, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      sync(ctx);
+      const double df = grid->fs / double(n);
+      for (int i = 0; i < nt; ++i) sigma[i] = coef[i].amp * std::sqrt(4.0 * df * mom);
+    }
+  });
+}
+
+rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd, rf_tmpl ref,
+                             const rf_tmpl* nbr, int32_t nk, double thr, rf_thr_unit unit,
+                             int64_t n_build, rf_kernels** out) {
+  if (!ctx) return RF_E_INVAL;
+  rf_kernels* K = nullptr;
+  rf_status st = guarded(ctx, [&] {
+    validate_grid(grid);
+    RF_CHECK(psd && nbr && out, "ratio_kernel_build: null pointer");
+    RF_CHECK(nk >= 1, "ratio_kernel_build: nk must be >= 1");
+    RF_CHECK(std::isfinite(thr) && thr > 0, "ratio_kernel_build: threshold must be positive");
+    RF_CHECK(unit == RF_THR_PER_SECOND || unit == RF_THR_PER_TAP, "ratio_kernel_build: bad unit");
+    const int64_t nb = n_build == 0 ? grid->n : n_build;
+    RF_CHECK(is_pow2(nb) && nb >= 256 && nb <= grid->n, "ratio_kernel_build: n_build must be a power of two in [2^8, n]");
+    validate_tmpl(ref);
+    *out = nullptr;
+    K = new rf_kernels();
+    K->device = ctx->device;
+    K->nk = nk;
+    K->n_build = nb;
+    K->fs = grid->fs;
+
+    // host scalars: taper widths (section II.C) and amplitude ratios
+    const Tf2Coef cref = tf2_coef(ref);
+    const double tpr = tf2_dtdf(cref, grid->f_low);
+    std::vector<Tf2Coef> ct(nk);
+    std::vector<RatioParam> par(nk);
+    K->df_low.resize(nk);
+    for (int k = 0; k < nk; ++k) {
+      validate_tmpl(nbr[k]);
+      ct[k] = tf2_coef(nbr[k]);
+      const double d = std::fabs(tf2_dtdf(ct[k], grid->f_low) - tpr);
+      double dfl = d > 0 ? 1.0 / std::sqrt(d) : grid->df_low_max;
+      if (dfl > grid->df_low_max) dfl = grid->df_low_max;
+      K->df_low[k] = dfl;
+      par[k].amp_ratio = ct[k].amp / cref.amp;
+      par[k].df_low = dfl;
+    }
+    // template norms through the band moment (section II.A normalisation)
+    double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
+    band_moment(ctx, grid, psd, moment);
+    double mom = 0;
+    RF_HIP(hipMemcpyAsync(&mom, moment, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    const double df = grid->fs / double(grid->n);
+    RF_CHECK(std::isfinite(mom) && mom > 0, "ratio_kernel_build: PSD band moment is not positive");
+    const double nref = cref.amp * std::sqrt(4.0 * df * mom);
+    K->norm_ratio.resize(nk);
+    for (int k = 0; k < nk; ++k) K->norm_ratio[k] = nref / (ct[k].amp * std::sqrt(4.0 * df * mom));
+
+    const double thr_tap = unit == RF_THR_PER_SECOND ? thr / grid->fs : thr;
+    Tf2Coef* ref_dev = upload(ctx, WS_COEF, &cref, 1);
+    // neighbours in batches bounded by ~512 MiB of FP64 spectra
+    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nk, (int64_t(1) << 25) / nb)));
+    double2* spec = static_cast<double2*>(ctx->ws[WS_BUILD].ensure(sizeof(double2) * size_t(nb) * per));
+    double2* wout = static_cast<double2*>(ctx->ws[WS_Y].ensure(sizeof(double2) * size_t(nb) * per));
+    char* scan = static_cast<char*>(ctx->ws[WS_SCAN].ensure(size_t(per) * 64 + 4096));
+    int32_t* lo_d = reinterpret_cast<int32_t*>(scan);
+    int32_t* hi_d = lo_d + per;
+    uint32_t* mx_d = reinterpret_cast<uint32_t*>(hi_d + per);
+    Tf2Coef* tgt_dev = static_cast<Tf2Coef*>(ctx->ws[WS_TGT].ensure(sizeof(Tf2Coef) * per + sizeof(RatioParam) * per));
+    RatioParam* par_dev = reinterpret_cast<RatioParam*>(tgt_dev + per);
+    std::vector<double> taps_host;
+    K->m_lo.resize(nk);
+    K->len.resize(nk);
+    K->off.resize(nk);
+    K->kscale.resize(nk);
+    std::vector<int32_t> lo_h(per), hi_h(per);
+    std::vector<uint32_t> mx_h(per);
+    std::vector<int64_t> offc(per);
+    std::vector<double> chunk_taps;
+    for (int k0 = 0; k0 < nk; k0 += per) {
+      const int cnt = std::min(per, nk - k0);
+      RF_HIP(hipMemcpyAsync(tgt_dev, ct.data() + k0, sizeof(Tf2Coef) * cnt, hipMemcpyHostToDevice, ctx->stream));
+      RF_HIP(hipMemcpyAsync(par_dev, par.data() + k0, sizeof(RatioParam) * cnt, hipMemcpyHostToDevice, ctx->stream));
+      // (the host vectors live until the synchronisation below)
+      ratio_spectrum(ctx, grid, nb, ref_dev, tgt_dev, par_dev, spec, cnt);
+      fft_inverse_f64(ctx, spec, wout, nb, cnt);
+      fill_u32(ctx, reinterpret_cast<uint32_t*>(lo_d), 0x7FFFFFFFu, cnt);
+      fill_u32(ctx, reinterpret_cast<uint32_t*>(hi_d), 0x80000000u, cnt);
+      fill_u32(ctx, mx_d, 0u, cnt);
+      support_scan(ctx, wout, nb, cnt, thr_tap, lo_d, hi_d, mx_d);
+      RF_HIP(hipMemcpyAsync(lo_h.data(), lo_d, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, ctx->stream));
+      RF_HIP(hipMemcpyAsync(hi_h.data(), hi_d, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, ctx->stream));
+      RF_HIP(hipMemcpyAsync(mx_h.data(), mx_d, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost, ctx->stream));
+      sync(ctx);
+      int64_t tot = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const int k = k0 + i;
+        if (lo_h[i] == 0x7FFFFFFF) {
+          K->m_lo[k] = 0;
+          K->len[k] = 0;
+        } else {
+          K->m_lo[k] = lo_h[i];
+          K->len[k] = hi_h[i] - lo_h[i] + 1;
+        }
+        float mxf;
+        std::memcpy(&mxf, &mx_h[i], 4);
+        K->kscale[k] = pow2_scale_for(double(mxf));
+        offc[i] = tot;
+        tot += K->len[k];
+      }
+      if (tot > 0) {
+        double* dst = static_cast<double*>(ctx->ws[WS_SPLIT].ensure(sizeof(double) * size_t(tot)));
+        std::vector<int32_t> mlo32(cnt), len32(cnt);
+        for (int i = 0; i < cnt; ++i) {
+          mlo32[i] = int32_t(K->m_lo[k0 + i]);
+          len32[i] = K->len[k0 + i];
+        }
+        int64_t* off_d = reinterpret_cast<int64_t*>(ctx->ws[WS_PEAK].ensure(size_t(cnt) * 16 + 64));
+        int32_t* mlo_d = reinterpret_cast<int32_t*>(off_d + cnt);
+        int32_t* len_d = mlo_d + cnt;
+        RF_HIP(hipMemcpyAsync(off_d, offc.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, ctx->stream));
+        RF_HIP(hipMemcpyAsync(mlo_d, mlo32.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, ctx->stream));
+        RF_HIP(hipMemcpyAsync(len_d, len32.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, ctx->stream));
+        gather_taps(ctx, wout, nb, cnt, off_d, mlo_d, len_d, dst);
+        chunk_taps.resize(size_t(tot));
+        RF_HIP(hipMemcpyAsync(chunk_taps.data(), dst, sizeof(double) * size_t(tot), hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+      }
+      const int64_t base = int64_t(taps_host.size());
+      for (int i = 0; i < cnt; ++i) K->off[k0 + i] = base + offc[i];
+      taps_host.insert(taps_host.end(), chunk_taps.begin(), chunk_taps.begin() + tot);
+    }
+    K->total_taps = int64_t(taps_host.size());
+    K->taps64 = dev_alloc<double>(size_t(K->total_taps));
+    if (K->total_taps)
+      RF_HIP(hipMemcpy(K->taps64, taps_host.data(), sizeof(double) * taps_host.size(), hipMemcpyHostToDevice));
+
+    // tiles: kernels sorted by first tap, 128 per tile, union support per tile
+    std::vector<int32_t> order(nk);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return K->m_lo[a] < K->m_lo[b]; });
+    const int ntiles = (nk + kTileKernels - 1) / kTileKernels;
+    std::vector<int32_t> slot(size_t(ntiles) * kTileKernels, -1);
+    std::vector<float> cs32(slot.size(), 0.f), cs16(slot.size(), 0.f);
+    int64_t b32_total = 0, b16_total = 0;
+    K->tiles.clear();
+    K->max_ksteps = 0;
+    for (int t = 0; t < ntiles; ++t) {
+      TileDev T{};
+      T.first = t * kTileKernels;
+      T.count = std::min(kTileKernels, nk - t * kTileKernels);
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+      for (int i = 0; i < T.count; ++i) {
+        const int k = order[T.first + i];
+        slot[T.first + i] = k;
+        cs32[T.first + i] = float(K->norm_ratio[k]);
+        cs16[T.first + i] = float(K->norm_ratio[k] / K->kscale[k]);
+        if (K->len[k] > 0) {
+          lo = std::min(lo, K->m_lo[k]);
+          hi = std::max(hi, K->m_lo[k] + K->len[k]);
+        }
+      }
+      if (lo == INT64_MAX) {
+        T.m0 = 0;
+        T.ksteps = 0;
+      } else {
+        T.m0 = lo;
+        T.ksteps = (hi - lo + 15) / 16;
+      }
+      T.b32_off = b32_total;
+      T.b16_off = b16_total;
+      b32_total += T.ksteps * 2048;
+      b16_total += T.ksteps * 4096;
+      K->max_ksteps = std::max(K->max_ksteps, T.ksteps);
+      K->tiles.push_back(T);
+    }
+    K->tiles_dev = dev_alloc<TileDev>(K->tiles.size());
+    K->slot_kernel = dev_alloc<int32_t>(slot.size());
+    K->colscale32 = dev_alloc<float>(slot.size());
+    K->colscale16 = dev_alloc<float>(slot.size());
+    K->b32 = dev_alloc<float>(size_t(b32_total));
+    K->b16 = dev_alloc<__half>(size_t(b16_total));
+    RF_HIP(hipMemcpy(K->tiles_dev, K->tiles.data(), sizeof(TileDev) * K->tiles.size(), hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(K->slot_kernel, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(K->colscale32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(K->colscale16, cs16.data(), sizeof(float) * cs16.size(), hipMemcpyHostToDevice));
+    if (K->max_ksteps > 0) {
+      int64_t* off_d = dev_alloc<int64_t>(size_t(nk) * 2);
+      int64_t* mlo_d = off_d + nk;
+      int32_t* len_d = dev_alloc<int32_t>(size_t(nk));
+      double* ks_d = dev_alloc<double>(size_t(nk));
+      RF_HIP(hipMemcpy(off_d, K->off.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
+      RF_HIP(hipMemcpy(mlo_d, K->m_lo.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
+      RF_HIP(hipMemcpy(len_d, K->len.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice));
+      RF_HIP(hipMemcpy(ks_d, K->kscale.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+      pack_launch(ctx, K, off_d, mlo_d, len_d, ks_d, K->tiles_dev, ntiles, K->max_ksteps);
+      sync(ctx);
+      (void)hipFree(off_d);
+      (void)hipFree(len_d);
+      (void)hipFree(ks_d);
+    }
+    *out = K;
+  });
+  if (st != RF_OK && K) {
+    free_kernels(K);
+    if (out) *out = nullptr;
+  }
+  return st;
+}
+
+rf_status rf_kernels_info(const rf_kernels* k, int32_t* nk, int64_t* m_lo, int32_t* len,
+                          double* norm_ratio, double* df_low) {
+  if (!k) return RF_E_INVAL;
+  if (nk) *nk = k->nk;
+  for (int i = 0; i < k->nk; ++i) {
+    if (m_lo) m_lo[i] = k->m_lo[i];
+    if (len) len[i] = k->len[i];
+    if (norm_ratio) norm_ratio[i] = k->norm_ratio[i];
+    if (df_low) df_low[i] = k->df_low[i];
+  }
+  return RF_OK;
+}
+
+rf_status rf_kernels_taps_fp64(const rf_kernels* k, int32_t idx, double* host_out) {
+  if (!k || idx < 0 || idx >= k->nk || (!host_out && k->len[idx] > 0)) return RF_E_INVAL;
+  if (k->len[idx] == 0) return RF_OK;
+  if (hipSetDevice(k->device) != hipSuccess) return RF_E_HIP;
+  if (hipMemcpy(host_out, k->taps64 + k->off[idx], sizeof(double) * size_t(k->len[idx]),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return RF_E_HIP;
+  return RF_OK;
+}
+
+rf_status rf_kernels_free(rf_kernels* k) {
+  if (!k) return RF_E_INVAL;
+  (void)hipSetDevice(k->device);
+  (void)hipDeviceSynchronize();
+  free_kernels(k);
+  return RF_OK;
+}
+
+rf_status snr_reconstruct(rf_ctx* ctx, const rf_kernels* K, const void* z_ref, int64_t n,
+                          rf_prec prec, void* z_out, const rf_peak_args* fused) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    RF_CHECK(K && z_ref, "snr_reconstruct: null pointer");
+    RF_CHECK(z_out || fused, "snr_reconstruct: need z_out or fused read-out");
+    RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct: bad precision");
+    RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24),
+             "snr_reconstruct: n must be a power of two in [2^8, 2^24]");
+    for (const TileDev& T : K->tiles)
+      RF_CHECK(T.ksteps * 16 <= n, "snr_reconstruct: kernel support longer than the segment");
+    if (fused) {
+      RF_CHECK(fused->peaks && fused->ntrig && fused->cap >= 0 && (fused->cap == 0 || fused->trig),
+               "snr_reconstruct: bad fused read-out arguments");
+      RF_CHECK(std::isfinite(fused->thr) && fused->thr >= 0, "snr_reconstruct: bad threshold");
+    }
+    PeakOut po{};
+    uint64_t* packed = nullptr;
+    if (fused) {
+      packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * (K->nk + 1)));
+      fill_u64(ctx, packed, 0ull, K->nk + 1);
+      po.packed = packed;
+      po.count = reinterpret_cast<unsigned long long*>(packed + K->nk);
+      po.trig = fused->trig;
+      po.cap = fused->cap;
+      po.thr2 = fused->thr * fused->thr;
+      po.seg = 0;
+      po.nk = K->nk;
+    }
+    const void* src = z_ref;
+    const float* zinv = nullptr;
+    if (prec == RF_PREC_SPLIT_FP16) {
+      char* sp = static_cast<char*>(ctx->ws[WS_SPLIT].ensure(sizeof(__half) * 4 * size_t(n) + 256));
+      uint32_t* mx = reinterpret_cast<uint32_t*>(sp + sizeof(__half) * 4 * size_t(n));
+      float* inv = reinterpret_cast<float*>(mx + 16);
+      split_launch(ctx, static_cast<const float2*>(z_ref), n, mx, reinterpret_cast<__half*>(sp), inv);
+      src = sp;
+      zinv = inv;
+    }
+    if (!K->tiles.empty())
+      recon_launch(ctx, prec, src, n, K->tiles_dev, int(K->tiles.size()), K, zinv,
+                   static_cast<float2*>(z_out), po, fused != nullptr);
+    if (fused) {
+      peaks_finalize(ctx, packed, K->nk, fused->peaks);
+      unsigned long long cnt = 0;
+      RF_HIP(hipMemcpyAsync(&cnt, po.count, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+      sync(ctx);
+      *fused->ntrig = int64_t(cnt);
+      if (int64_t(cnt) > fused->cap) throw Error{RF_E_OVERFLOW, "snr_reconstruct: trigger buffer overflow"};
+    }
+  });
+}
+
+rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr, rf_peak* peaks,
+                    rf_trigger* trig, int64_t cap, int64_t* ntrig) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    RF_CHECK(z && peaks && ntrig, "snr_peaks: null pointer");
+    RF_CHECK(nt >= 1 && n >= 1 && n <= (int64_t(1) << 30), "snr_peaks: bad sizes");
+    RF_CHECK(cap >= 0 && (cap == 0 || trig), "snr_peaks: bad trigger buffer");
+    RF_CHECK(std::isfinite(thr) && thr >= 0, "snr_peaks: bad threshold");
+    uint64_t* packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * (nt + 1)));
+    fill_u64(ctx, packed, 0ull, nt + 1);
+    PeakOut po{};
+    po.packed = packed;
+    po.count = reinterpret_cast<unsigned long long*>(packed + nt);
+    po.trig = trig;
+    po.cap = cap;
+    po.thr2 = thr * thr;
+    po.seg = 0;
+    po.nk = nt;
+    peaks_launch(ctx, static_cast<const float2*>(z), nt, n, po);
+    peaks_finalize(ctx, packed, nt, peaks);
+    unsigned long long cnt = 0;
+    RF_HIP(hipMemcpyAsync(&cnt, po.count, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    *ntrig = int64_t(cnt);
+    if (int64_t(cnt) > cap) throw Error{RF_E_OVERFLOW, "snr_peaks: trigger buffer overflow"};
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Internal interface of the reconstruction and read-out kernels.
+#pragma once
+
+#include "rf_internal.h"
+
+namespace rf {
+
+constexpr int kTileKernels = 128;  // kernels per tile (4 blocks of 32)
+constexpr int kTimes = 128;        // output times per workgroup
+constexpr int kChunk = 512;        // taps per accumulation chunk
+
+
+// Read-out target of a launch.  packed[seg * nk + k] holds the running peak
+// key (|z|^2 float bits << 32 | ~index); triggers append at *count.
+struct PeakOut {
+  uint64_t* packed;
+  rf_trigger* trig;
+  unsigned long long* count;
+  int64_t cap;
+  float thr2;
+  int32_t seg;
+  int32_t nk;
+};
+
+void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const TileDev* tiles,
+                  int ntiles, const rf_kernels* K, const float* zinv, float2* zout, const PeakOut& po,
+                  bool fused);
+void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __half* zs,
+                  float* inv_scale);
+void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const int64_t* mlo_dev,
+                 const int32_t* len_dev, const double* kscale_dev, const TileDev* tiles_dev,
+                 int ntiles, int64_t max_ksteps);
+void peaks_launch(rf_ctx* ctx, const float2* z, int nt, int64_t n, const PeakOut& po);
+void peaks_finalize(rf_ctx* ctx, const uint64_t* packed, int64_t count, rf_peak* out);
+
+}  // namespace rf

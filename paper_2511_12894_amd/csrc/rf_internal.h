@@ -1,0 +1,154 @@
+// Internal declarations of librf (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rf.h"
+
+namespace rf {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  rf_status code;
+  std::string msg;
+};
+
+#define RF_HIP(call)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw ::rf::Error{RF_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define RF_CHECK(cond, msg)                                                     \
+  do {                                                                          \
+    if (!(cond)) throw ::rf::Error{RF_E_INVAL, (msg)};                          \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void release();
+  void* ensure(size_t n);  // grows, contents not preserved
+};
+
+}  // namespace rf
+
+struct rf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // workspace slots
+  rf::DevBuf ws[16];
+  std::vector<char> host_stage[16];
+  hipEvent_t ev = nullptr;
+};
+
+namespace rf {
+
+enum WsSlot {
+  WS_FFT_A = 0, WS_FFT_B = 1, WS_RED = 2, WS_SPLIT = 3, WS_PEAK = 4, WS_COEF = 5, WS_BUILD = 6,
+  WS_Y = 7, WS_SCALAR = 8, WS_SCAN = 9, WS_TGT = 10
+};
+
+inline bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+inline int ilog2(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+void validate_grid(const rf_grid* g);
+
+// ------------------------------------------------------------------ TaylorF2 (host)
+// Per-template constants of the stationary-phase phase series, in the form
+// Psi(f) = -pi/4 + pref * v^-5 * [1 + v^2 (a2 + v (a3 + v (a4 + v ((a5c + a5l ln v)
+//          + v ((a6c + a6l ln v) + v a7)))))],  v = (pi M f)^(1/3).
+struct Tf2Coef {
+  double piM;      // pi * M  [s]
+  double pref;     // 3 / (128 eta)
+  double a2, a3, a4, a5c, a5l, a6c, a6l, a7;
+  double amp;      // Mc^(5/6)
+  double cbrt_piM; // (pi M)^(1/3)
+};
+Tf2Coef tf2_coef(const rf_tmpl& t);
+double tf2_dtdf(const Tf2Coef& c, double f);   // t'(f) = Psi''(f) / (2 pi)
+double tf2_t(const Tf2Coef& c, double f);      // t(f)  = Psi'(f) / (2 pi)
+
+// ------------------------------------------------------------------ launchers
+// Inverse (exp +) unnormalised complex DFT of `batch` contiguous series of n
+// points, in -> out (out may not alias in).  Uses ctx workspace slots A/B.
+void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch);
+void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch);
+
+// sum over the band of f^(-7/3) / S(f) -> *moment (device double), FP64, fixed order
+void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment);
+
+// Y[t][j] for the nt templates (FP64 arithmetic, complex64 store), using *moment
+void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
+                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt);
+
+// One-sided ratio spectra for nb-point kernels, nk targets (FP64), scaled by c_j / nb.
+struct RatioParam {
+  double amp_ratio;   // (Mc_k / Mc_ref)^(5/6)
+  double df_low;      // lower taper width
+};
+void ratio_spectrum(rf_ctx* ctx, const rf_grid* g, int64_t nb, const Tf2Coef* ref_dev,
+                    const Tf2Coef* tgt_dev, const RatioParam* par_dev, double2* out, int nk);
+
+// support scan on the real parts of nk complex series of nb points
+void support_scan(rf_ctx* ctx, const double2* w, int64_t nb, int nk, double thr_tap,
+                  int32_t* lo, int32_t* hi, uint32_t* maxabs_bits);
+
+// copy taps Re(w[(m_lo + l) mod nb]), l < len, into dst (contiguous per kernel)
+void gather_taps(rf_ctx* ctx, const double2* w, int64_t nb, int nk, const int64_t* off_dev,
+                 const int32_t* mlo_dev, const int32_t* len_dev, double* dst);
+
+// generic fill (graph-safe replacement for memset)
+void fill_u64(rf_ctx* ctx, uint64_t* p, uint64_t v, int64_t n);
+void fill_u32(rf_ctx* ctx, uint32_t* p, uint32_t v, int64_t n);
+
+}  // namespace rf
+
+// ------------------------------------------------------------------ kernel set
+namespace rf {
+struct TileDev {
+  int64_t m0;       // first tap (signed) of the tile's union support
+  int64_t ksteps;   // 16-tap steps covering it
+  int64_t b32_off;  // offsets of the tile in the packed operand buffers
+  int64_t b16_off;
+  int32_t first;    // first slot of the tile in the slot arrays
+  int32_t count;    // live kernels in the tile
+};
+}  // namespace rf
+
+struct rf_kernels {
+  int device = 0;
+  int32_t nk = 0;
+  int64_t n_build = 0;
+  double fs = 0;
+  std::vector<int64_t> m_lo;         // signed first tap of each kernel
+  std::vector<int32_t> len;          // taps kept
+  std::vector<int64_t> off;          // offset of each kernel's taps in taps64
+  std::vector<double> norm_ratio;    // N_ref / N_k
+  std::vector<double> df_low;        // lower taper width used
+  std::vector<double> kscale;        // power-of-two FP16 scale s_k
+  double* taps64 = nullptr;          // device, concatenated FP64 taps
+  int64_t total_taps = 0;
+  // reconstruction tiles (kernels sorted by support, 128 per tile)
+  std::vector<rf::TileDev> tiles;
+  int64_t max_ksteps = 0;
+  rf::TileDev* tiles_dev = nullptr;
+  float* b32 = nullptr;              // FP32 operand fragments
+  __half* b16 = nullptr;             // FP16 hi/lo operand fragments
+  float* colscale32 = nullptr;       // per slot: N_ref / N_k
+  float* colscale16 = nullptr;       // per slot: N_ref / N_k / s_k
+  int32_t* slot_kernel = nullptr;    // per slot: kernel index (-1 empty)
+};

@@ -1,0 +1,329 @@
+// FP64 frequency-domain work: TaylorF2 template spectra fused with the
+// matched-filter weighting (section II.A), band moment for the template norms,
+// windowed ratio spectra (sections II.B-II.C), and the kernel support scan and
+// tap gather of the truncation (section II.D).
+#include <cmath>
+
+#include "rf_internal.h"
+
+namespace rf {
+
+// ---------------------------------------------------------------- host side
+
+namespace {
+constexpr double kTsun = 4.925490947641267e-6;  // G M_sun / c^3 [s]
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kEuler = 0.57721566490153286061;
+}  // namespace
+
+// Non-spinning TaylorF2 phase series to 3.5PN (the paper's TaylorF2 model,
+// sections II.B and III.B; stationary-phase form of appendix A), coefficients
+// written as rationals in eta with t_c = phi_c = 0.
+Tf2Coef tf2_coef(const rf_tmpl& t) {
+  Tf2Coef c{};
+  const double m = (t.m1 + t.m2) * kTsun;
+  const double eta = t.m1 * t.m2 / ((t.m1 + t.m2) * (t.m1 + t.m2));
+  const double mc = m * std::pow(eta, 0.6);
+  const double e2 = eta * eta, e3 = e2 * eta;
+  c.piM = kPi * m;
+  c.pref = 3.0 / (128.0 * eta);
+  c.a2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  c.a3 = -16.0 * kPi;
+  c.a4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * e2;
+  const double a5 = kPi * (38645.0 / 756.0 - 65.0 / 9.0 * eta);
+  // a5 (1 + 3 ln(v / v_lso)), v_lso = 6^(-1/2)
+  c.a5c = a5 * (1.0 + 1.5 * std::log(6.0));
+  c.a5l = 3.0 * a5;
+  // psi_6 = const - 6848/21 ln(4 v)
+  c.a6l = -6848.0 / 21.0;
+  c.a6c = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * kPi * kPi - 6848.0 / 21.0 * kEuler +
+          (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * kPi * kPi) * eta + 76055.0 / 1728.0 * e2 -
+          127825.0 / 1296.0 * e3 + c.a6l * std::log(4.0);
+  c.a7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2);
+  c.amp = std::pow(mc, 5.0 / 6.0);
+  c.cbrt_piM = std::cbrt(c.piM);
+  return c;
+}
+
+namespace {
+// P(v) = pref [v^-5 + a2 v^-3 + a3 v^-2 + a4 v^-1 + (a5c + a5l ln v) + (a6c + a6l ln v) v + a7 v^2]
+void series_derivs(const Tf2Coef& c, double v, double* d1, double* d2) {
+  const double lv = std::log(v);
+  const double iv = 1.0 / v;
+  const double iv2 = iv * iv, iv3 = iv2 * iv, iv4 = iv3 * iv, iv5 = iv4 * iv, iv6 = iv5 * iv,
+               iv7 = iv6 * iv;
+  *d1 = c.pref * (-5.0 * iv6 - 3.0 * c.a2 * iv4 - 2.0 * c.a3 * iv3 - c.a4 * iv2 + c.a5l * iv +
+                  (c.a6c + c.a6l * lv + c.a6l) + 2.0 * c.a7 * v);
+  *d2 = c.pref * (30.0 * iv7 + 12.0 * c.a2 * iv5 + 6.0 * c.a3 * iv4 + 2.0 * c.a4 * iv3 -
+                  c.a5l * iv2 + c.a6l * iv + 2.0 * c.a7);
+}
+}  // namespace
+
+double tf2_t(const Tf2Coef& c, double f) {
+  const double v = std::cbrt(c.piM * f);
+  double d1, d2;
+  series_derivs(c, v, &d1, &d2);
+  return d1 * (v / (3.0 * f)) / (2.0 * kPi);
+}
+
+double tf2_dtdf(const Tf2Coef& c, double f) {
+  const double v = std::cbrt(c.piM * f);
+  double d1, d2;
+  series_derivs(c, v, &d1, &d2);
+  const double dv = v / (3.0 * f);
+  const double d2v = -2.0 * v / (9.0 * f * f);
+  return (d2 * dv * dv + d1 * d2v) / (2.0 * kPi);
+}
+
+// ---------------------------------------------------------------- device side
+
+namespace {
+
+__device__ inline double tf2_phase(const Tf2Coef& c, double v) {
+  const double lv = log(v);
+  const double v2 = v * v;
+  const double iv = 1.0 / v;
+  const double iv5 = iv * iv * iv * iv * iv;
+  const double poly =
+      1.0 + v2 * (c.a2 + v * (c.a3 + v * (c.a4 + v * ((c.a5c + c.a5l * lv) +
+                                                       v * ((c.a6c + c.a6l * lv) + v * c.a7)))));
+  return -0.25 * 3.14159265358979323846 + c.pref * poly * iv5;
+}
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+
+// Partial sums of f^(-7/3) / S(f) over the band, one per block (grid-stride),
+// then a single-block fixed-order sum: deterministic.
+__global__ __launch_bounds__(kRedThreads) void k_moment_partial(const double* __restrict__ psd,
+                                                                int64_t jlo, int64_t jhi,
+                                                                double df, double* partial) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int64_t j = jlo + int64_t(blockIdx.x) * kRedThreads + threadIdx.x; j <= jhi;
+       j += int64_t(gridDim.x) * kRedThreads) {
+    const double f = double(j) * df;
+    const double cf = cbrt(f);
+    acc += 1.0 / (f * f * cf * psd[j]);   // f^(-7/3) / S
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_sum_partials(const double* __restrict__ partial,
+                                                              int np, double* out) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kRedThreads) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// Y[t][j] = (4 df / N_t) x~_j conj(h~_t(f_j)) / S_j on the band, 0 elsewhere,
+// with N_t = amp_t sqrt(4 df I) and h~ = amp f^(-7/6) exp(-i Psi).
+__global__ __launch_bounds__(256) void k_mf_spectrum(const double2* __restrict__ xf,
+                                                     const double* __restrict__ psd,
+                                                     const Tf2Coef* __restrict__ coef,
+                                                     const double* __restrict__ moment, float2* Y,
+                                                     int64_t n, int64_t jlo, int64_t jhi, double df) {
+  const Tf2Coef c = coef[blockIdx.y];
+  float2* y = Y + int64_t(blockIdx.y) * n;
+  const double nh = c.amp * sqrt(4.0 * df * (*moment));
+  const double g = 4.0 * df / nh * c.amp;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    float2 out = make_float2(0.f, 0.f);
+    if (j >= jlo && j <= jhi) {
+      const double f = double(j) * df;
+      const double v = c.cbrt_piM * cbrt(f);
+      const double psi = tf2_phase(c, v);
+      double sn, cs;
+      sincos(psi, &sn, &cs);
+      // f^(-7/6) = 1 / (f * sqrt(cbrt(f)))
+      const double a = g / (f * sqrt(v / c.cbrt_piM) * psd[j]);
+      const double2 x = xf[j];
+      // x * conj(h) = x * amp f^-7/6 * exp(+i psi)
+      out.x = float(a * (x.x * cs - x.y * sn));
+      out.y = float(a * (x.x * sn + x.y * cs));
+    }
+    y[j] = out;
+  }
+}
+
+// One-sided ratio spectrum on nb points: A_j = c_j / nb * W(f_j) R e^{-i dPsi(f_j)}
+// for j <= nb/2 (c_0 = c_{nb/2} = 1, else 2), 0 for j > nb/2; Re of its
+// exp(+) DFT is the inverse real DFT of R~.
+__global__ __launch_bounds__(256) void k_ratio_spectrum(const Tf2Coef* __restrict__ refc,
+                                                        const Tf2Coef* __restrict__ tgtc,
+                                                        const RatioParam* __restrict__ par,
+                                                        double2* out, int64_t nb, double dfb,
+                                                        double f_low, double f_high, double df_high) {
+  const Tf2Coef cr = *refc;
+  const Tf2Coef ct = tgtc[blockIdx.y];
+  const RatioParam p = par[blockIdx.y];
+  double2* o = out + int64_t(blockIdx.y) * nb;
+  const double lo_edge = f_low - p.df_low, hi_edge = f_high + df_high;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < nb;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    double2 r = make_double2(0.0, 0.0);
+    const double f = double(j) * dfb;
+    if (j <= nb / 2 && f > lo_edge && f < hi_edge) {
+      double w;
+      if (f < f_low)
+        w = 0.5 * (1.0 + cospi((f - f_low) / p.df_low));
+      else if (f <= f_high)
+        w = 1.0;
+      else
+        w = 0.5 * (1.0 - cospi((f - hi_edge) / df_high));
+      const double cbf = cbrt(f);
+      const double dpsi = tf2_phase(ct, ct.cbrt_piM * cbf) - tf2_phase(cr, cr.cbrt_piM * cbf);
+      double sn, cs;
+      sincos(dpsi, &sn, &cs);
+      const double cj = (j == 0 || j == nb / 2) ? 1.0 : 2.0;
+      const double a = cj / double(nb) * w * p.amp_ratio;
+      r.x = a * cs;
+      r.y = -a * sn;
+    }
+    o[j] = r;
+  }
+}
+
+// Signed support of |Re w| >= thr and max |Re w| per series (blockIdx.y).
+__global__ __launch_bounds__(256) void k_support_scan(const double2* __restrict__ w, int64_t nb,
+                                                      double thr, int32_t* lo, int32_t* hi,
+                                                      uint32_t* maxbits) {
+  const double2* x = w + int64_t(blockIdx.y) * nb;
+  int32_t mlo = INT32_MAX, mhi = INT32_MIN;
+  float mx = 0.f;
+  for (int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; m < nb;
+       m += int64_t(gridDim.x) * blockDim.x) {
+    const double a = fabs(x[m].x);
+    mx = fmaxf(mx, float(a));
+    if (a >= thr) {
+      const int32_t s = int32_t(m > nb / 2 ? m - nb : m);
+      mlo = min(mlo, s);
+      mhi = max(mhi, s);
+    }
+  }
+  // wave reduction, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    mlo = min(mlo, __shfl_xor(mlo, o));
+    mhi = max(mhi, __shfl_xor(mhi, o));
+    mx = fmaxf(mx, __shfl_xor(mx, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (mlo != INT32_MAX) {
+      atomicMin(&lo[blockIdx.y], mlo);
+      atomicMax(&hi[blockIdx.y], mhi);
+    }
+    atomicMax(&maxbits[blockIdx.y], __float_as_uint(mx));
+  }
+}
+
+__global__ void k_gather_taps(const double2* __restrict__ w, int64_t nb, const int64_t* off,
+                              const int32_t* mlo, const int32_t* len, double* dst) {
+  const int k = blockIdx.y;
+  const double2* x = w + int64_t(k) * nb;
+  const int32_t L = len[k];
+  const int64_t o = off[k];
+  const int64_t m0 = mlo[k];
+  for (int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; l < L;
+       l += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t m = (m0 + l) & (nb - 1);
+    dst[o + l] = x[m].x;
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int per = 256, unsigned cap = 8192) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  return unsigned(b > cap ? cap : b);
+}
+
+}  // namespace
+
+void band_limits(const rf_grid* g, int64_t* jlo, int64_t* jhi) {
+  const double df = g->fs / double(g->n);
+  *jlo = int64_t(std::ceil(g->f_low / df));
+  *jhi = int64_t(std::floor(g->f_high / df));
+}
+
+void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment) {
+  int64_t jlo, jhi;
+  band_limits(g, &jlo, &jhi);
+  const double df = g->fs / double(g->n);
+  double* part = static_cast<double*>(ctx->ws[WS_RED].ensure(sizeof(double) * kRedBlocks));
+  hipLaunchKernelGGL(k_moment_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, ctx->stream, psd,
+                     jlo, jhi, df, part);
+  RF_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kRedThreads), 0, ctx->stream, part, kRedBlocks,
+                     moment);
+  RF_HIP(hipGetLastError());
+}
+
+void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
+                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt) {
+  int64_t jlo, jhi;
+  band_limits(g, &jlo, &jhi);
+  const double df = g->fs / double(g->n);
+  dim3 grid(blocks_for(g->n, 256, 4096), unsigned(nt));
+  hipLaunchKernelGGL(k_mf_spectrum, grid, dim3(256), 0, ctx->stream, xf, psd, coef_dev, moment, Y,
+                     g->n, jlo, jhi, df);
+  RF_HIP(hipGetLastError());
+}
+
+void ratio_spectrum(rf_ctx* ctx, const rf_grid* g, int64_t nb, const Tf2Coef* ref_dev,
+                    const Tf2Coef* tgt_dev, const RatioParam* par_dev, double2* out, int nk) {
+  dim3 grid(blocks_for(nb, 256, 4096), unsigned(nk));
+  hipLaunchKernelGGL(k_ratio_spectrum, grid, dim3(256), 0, ctx->stream, ref_dev, tgt_dev, par_dev,
+                     out, nb, g->fs / double(nb), g->f_low, g->f_high, g->df_high);
+  RF_HIP(hipGetLastError());
+}
+
+void support_scan(rf_ctx* ctx, const double2* w, int64_t nb, int nk, double thr_tap, int32_t* lo,
+                  int32_t* hi, uint32_t* maxabs_bits) {
+  dim3 grid(blocks_for(nb, 256, 2048), unsigned(nk));
+  hipLaunchKernelGGL(k_support_scan, grid, dim3(256), 0, ctx->stream, w, nb, thr_tap, lo, hi,
+                     maxabs_bits);
+  RF_HIP(hipGetLastError());
+}
+
+void gather_taps(rf_ctx* ctx, const double2* w, int64_t nb, int nk, const int64_t* off_dev,
+                 const int32_t* mlo_dev, const int32_t* len_dev, double* dst) {
+  dim3 grid(blocks_for(nb, 256, 256), unsigned(nk));
+  hipLaunchKernelGGL(k_gather_taps, grid, dim3(256), 0, ctx->stream, w, nb, off_dev, mlo_dev,
+                     len_dev, dst);
+  RF_HIP(hipGetLastError());
+}
+
+void fill_u64(rf_ctx* ctx, uint64_t* p, uint64_t v, int64_t n) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256, 1024)), dim3(256), 0, ctx->stream, p, v, n);
+  RF_HIP(hipGetLastError());
+}
+void fill_u32(rf_ctx* ctx, uint32_t* p, uint32_t v, int64_t n) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256, 1024)), dim3(256), 0, ctx->stream, p, v, n);
+  RF_HIP(hipGetLastError());
+}
+
+}  // namespace rf

@@ -1,0 +1,252 @@
+"""ctypes binding of librf (the C ABI declared in include/rf.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+provides device memory and the stream; tensors are passed by data pointer.
+The library must have been built (paper_2511_12894_amd/build_lib.sh, or
+__graft_entry__.build()); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librf.so")
+
+RF_OK, RF_E_INVAL, RF_E_NOMEM, RF_E_HIP, RF_E_UNSUPPORTED, RF_E_OVERFLOW = range(6)
+RF_THR_PER_SECOND, RF_THR_PER_TAP = 0, 1
+RF_PREC_FP32, RF_PREC_SPLIT_FP16 = 0, 1
+PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
+
+EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "ratio_kernel_build",
+            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_free", "snr_reconstruct",
+            "snr_peaks")
+
+
+class RfGrid(ctypes.Structure):
+    _fields_ = [("fs", ctypes.c_double), ("n", ctypes.c_int64), ("f_low", ctypes.c_double),
+                ("f_high", ctypes.c_double), ("df_high", ctypes.c_double),
+                ("df_low_max", ctypes.c_double)]
+
+
+class RfTmpl(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_double), ("m2", ctypes.c_double)]
+
+
+class RfPeak(ctypes.Structure):
+    _fields_ = [("max_absz", ctypes.c_float), ("argmax", ctypes.c_int32)]
+
+
+class RfTrigger(ctypes.Structure):
+    _fields_ = [("tmpl", ctypes.c_int32), ("seg", ctypes.c_int32), ("idx", ctypes.c_int32),
+                ("absz", ctypes.c_float), ("argz", ctypes.c_float)]
+
+
+class RfPeakArgs(ctypes.Structure):
+    _fields_ = [("thr", ctypes.c_float), ("peaks", ctypes.c_void_p), ("trig", ctypes.c_void_p),
+                ("cap", ctypes.c_int64), ("ntrig", ctypes.POINTER(ctypes.c_int64))]
+
+
+class RfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librf status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librf.so (once).  Raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"librf.so not built at {path}; run paper_2511_12894_amd/build_lib.sh")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.rf_ctx_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.rf_ctx_destroy.argtypes = [vp]
+    lib.rf_last_error.argtypes = [vp]
+    lib.rf_last_error.restype = ctypes.c_char_p
+    lib.mf_ref_snr.argtypes = [vp, ctypes.POINTER(RfGrid), vp, vp, ctypes.POINTER(RfTmpl), i32, vp,
+                               ctypes.POINTER(dbl)]
+    lib.ratio_kernel_build.argtypes = [vp, ctypes.POINTER(RfGrid), vp, RfTmpl, ctypes.POINTER(RfTmpl),
+                                       i32, dbl, ctypes.c_int, i64, ctypes.POINTER(vp)]
+    lib.rf_kernels_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.rf_kernels_taps_fp64.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    lib.rf_kernels_free.argtypes = [vp]
+    lib.snr_reconstruct.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.snr_peaks.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
+    for name in EXPORTED:
+        if name != "rf_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def to_grid(g) -> RfGrid:
+    return RfGrid(float(g.fs), int(g.n), float(g.f_low), float(g.f_high), float(g.df_high),
+                  float(g.df_low_max))
+
+
+def _tmpl_array(ts):
+    arr = (RfTmpl * len(ts))()
+    for i, (m1, m2) in enumerate(ts):
+        arr[i] = RfTmpl(float(m1), float(m2))
+    return arr
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """rf_ctx on a device, enqueuing on a torch stream (default: current)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.lib = load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        st = self.lib.rf_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != RF_OK:
+            raise RfError(st, "rf_ctx_create failed")
+        self.h = h
+
+    def check(self, st):
+        if st != RF_OK:
+            raise RfError(st, self.lib.rf_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Kernels:
+    ctx: Context
+    h: ctypes.c_void_p
+    nk: int
+
+    def info(self):
+        nk = self.nk
+        m_lo = (ctypes.c_int64 * nk)()
+        ln = (ctypes.c_int32 * nk)()
+        nr = (ctypes.c_double * nk)()
+        dfl = (ctypes.c_double * nk)()
+        n = ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.rf_kernels_info(self.h, ctypes.byref(n), m_lo, ln, nr, dfl))
+        return dict(m_lo=list(m_lo), len=list(ln), norm_ratio=list(nr), df_low=list(dfl))
+
+    def taps(self, k: int):
+        import numpy as np
+        L = self.info()["len"][k]
+        out = (ctypes.c_double * max(L, 1))()
+        self.ctx.check(self.ctx.lib.rf_kernels_taps_fp64(self.h, k, out))
+        return np.frombuffer(out, dtype=np.float64, count=L).copy()
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.rf_kernels_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mf_ref_snr(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, templates, z=None,
+               want_sigma: bool = True):
+    """Complex SNR series of each template: z complex64 [nt, n] (device), sigma list."""
+    n = int(grid.n)
+    assert xf.dtype == torch.complex128 and xf.is_cuda and xf.numel() == n // 2 + 1 and xf.is_contiguous()
+    assert psd.dtype == torch.float64 and psd.is_cuda and psd.numel() == n // 2 + 1 and psd.is_contiguous()
+    nt = len(templates)
+    if z is None:
+        z = torch.empty((nt, n), dtype=torch.complex64, device=xf.device)
+    assert z.dtype == torch.complex64 and z.is_contiguous() and z.numel() >= nt * n
+    g = to_grid(grid)
+    sig = (ctypes.c_double * nt)() if want_sigma else None
+    ctx.check(ctx.lib.mf_ref_snr(ctx.h, ctypes.byref(g), _ptr(xf), _ptr(psd), _tmpl_array(templates),
+                                 nt, _ptr(z), sig))
+    return z, (list(sig) if want_sigma else None)
+
+
+def ratio_kernel_build(ctx: Context, grid, psd: torch.Tensor, ref, nbrs, thr: float = 1e-3,
+                       unit: int = RF_THR_PER_SECOND, n_build: int = 0) -> Kernels:
+    g = to_grid(grid)
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.ratio_kernel_build(ctx.h, ctypes.byref(g), _ptr(psd), RfTmpl(*map(float, ref)),
+                                         _tmpl_array(nbrs), len(nbrs), float(thr), int(unit),
+                                         int(n_build), ctypes.byref(h)))
+    return Kernels(ctx, h, len(nbrs))
+
+
+def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: str = "split16",
+                    z_out=None, store: bool = True, fused_thr: float | None = None,
+                    trig_cap: int = 4096):
+    """Reconstructed series [nk, n] (if store) and, with fused_thr, the fused
+    read-out (peaks tensor of RfPeak bytes, triggers, count)."""
+    n = z_ref.numel()
+    assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
+    if store and z_out is None:
+        z_out = torch.empty((kernels.nk, n), dtype=torch.complex64, device=z_ref.device)
+    fused = None
+    peaks = trig = None
+    cnt = ctypes.c_int64(0)
+    if fused_thr is not None:
+        peaks = torch.empty((kernels.nk, 2), dtype=torch.int32, device=z_ref.device)
+        trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
+        fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
+                           ctypes.pointer(cnt))
+    st = ctx.lib.snr_reconstruct(ctx.h, kernels.h, _ptr(z_ref), n, PREC[prec],
+                                 _ptr(z_out) if store else None,
+                                 ctypes.byref(fused) if fused is not None else None)
+    if st not in (RF_OK, RF_E_OVERFLOW):
+        ctx.check(st)
+    out = dict(z=z_out if store else None)
+    if fused is not None:
+        out.update(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+    return out
+
+
+def snr_peaks(ctx: Context, z: torch.Tensor, thr: float, trig_cap: int = 4096):
+    """Peaks and threshold crossings of series z [nt, n] (complex64, device)."""
+    assert z.dtype == torch.complex64 and z.is_cuda and z.is_contiguous() and z.dim() == 2
+    nt, n = z.shape
+    peaks = torch.empty((nt, 2), dtype=torch.int32, device=z.device)
+    trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z.device)
+    cnt = ctypes.c_int64(0)
+    st = ctx.lib.snr_peaks(ctx.h, _ptr(z), nt, n, ctypes.c_float(thr), _ptr(peaks), _ptr(trig),
+                           int(trig_cap), ctypes.byref(cnt))
+    if st not in (RF_OK, RF_E_OVERFLOW):
+        ctx.check(st)
+    return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+
+
+def decode_peaks(peaks: torch.Tensor):
+    """(max_absz float32 [nt], argmax int32 [nt]) from the RfPeak records."""
+    p = peaks.cpu().contiguous()
+    return p[:, 0].view(torch.float32).numpy().copy(), p[:, 1].numpy().copy()
+
+
+def decode_triggers(trig: torch.Tensor, count: int):
+    """List of (tmpl, seg, idx, absz, argz) for the first min(count, cap) records."""
+    t = trig.cpu().contiguous()[: min(count, trig.shape[0])]
+    ints = t[:, :3].numpy()
+    fl = t[:, 3:].view(torch.float32).numpy()
+    return [(int(a), int(b), int(c), float(d), float(e)) for (a, b, c), (d, e) in zip(ints, fl)]
