@@ -333,12 +333,12 @@ rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd
         T.ksteps = 0;
       } else {
         T.m0 = lo;
-        T.ksteps = (hi - lo + 15) / 16;
+        T.ksteps = ((hi - lo + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
       }
       T.b32_off = b32_total;
       T.b16_off = b16_total;
-      b32_total += T.ksteps * 2048;
-      b16_total += T.ksteps * 4096;
+      b32_total += T.ksteps * kB32PerStep;
+      b16_total += T.ksteps * kB16PerStep;
       K->max_ksteps = std::max(K->max_ksteps, T.ksteps);
       K->tiles.push_back(T);
     }

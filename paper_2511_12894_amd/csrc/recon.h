@@ -5,9 +5,12 @@
 
 namespace rf {
 
-constexpr int kTileKernels = 128;  // kernels per tile (4 blocks of 32)
-constexpr int kTimes = 128;        // output times per workgroup
-constexpr int kChunk = 512;        // taps per accumulation chunk
+constexpr int kTileKernels = 32;   // kernels per tile (one 32-wide MFMA block)
+constexpr int kTimes = 256;        // output times per workgroup (4 waves x 64)
+constexpr int kChunk = 512;        // taps per LDS window chunk / accumulation chunk
+constexpr int kStepAlign = 4;      // tiles span a multiple of 4 16-tap steps
+constexpr int kB32PerStep = 512;   // FP32 operand floats per 16-tap step of a tile
+constexpr int kB16PerStep = 1024;  // FP16 operand halves per 16-tap step (hi + lo)
 
 
 // Read-out target of a launch.  packed[seg * nk + k] holds the running peak

@@ -3,22 +3,31 @@
 //
 //   z_k[m] = c_k sum_{s} z_ref[(m + s) mod n] w_k[s],   c_k = N_ref / N_k,
 //
-// cast as a matrix product per tile of up to 128 kernels that share one
-// union support [m0, m0 + 16 ksteps): A[m][s] = z_ref[m + m0 + s] is a Hankel
-// matrix of the reference series (rows: output times, real and imaginary
-// parts as two operands), B[s][k] = w_k[s + m0] (zero outside kernel k's own
-// support).  A workgroup owns 128 output times x 128 kernels; its four
-// wavefronts each own 64 times x 64 kernels as 2 x 2 blocks of 32 x 32 MFMA
-// tiles.  The Hankel operand is read from a sliding window of z_ref staged in
-// LDS; B is pre-packed in fragment order so each MFMA operand is one
-// coalesced 256 B / 1 KiB load.  Accumulation runs in chunks of 512 taps: the
-// matrix-core accumulator restarts per chunk and is added into a second FP32
-// total, which bounds the rounding growth over long kernels.
+// cast as a matrix product per tile of up to 32 kernels that share one union
+// support [m0, m0 + 16 ksteps): A[m][s] = z_ref[m + m0 + s] is a Hankel matrix
+// of the reference series (rows: output times; real and imaginary parts are
+// two operands), B[s][k] = w_k[s + m0] (zero outside kernel k's own support).
+// Kernels are sorted by first tap before tiling, so a 32-kernel tile's union
+// support is close to each kernel's own, and one tile's B operand (about 2 MB)
+// stays resident in an XCD's L2 while consecutive workgroups -- spread over
+// all XCDs -- sweep the time axis of the same tile.
+//
+// A workgroup owns 256 output times x 32 kernels; each of its four wavefronts
+// owns 64 times as two 32 x 32 MFMA tiles (real and imaginary part each).  The
+// Hankel operand comes from a sliding window of z_ref staged in LDS (double
+// buffered, refilled from registers loaded during the previous chunk); B is
+// pre-packed in fragment order, so each operand is one coalesced load.
+// Software pipelining: a four-slot register ring keeps the loads of step s + 3
+// in flight while step s runs on the matrix cores.  Accumulation restarts per
+// chunk and is added into a second FP32 total, bounding the rounding growth
+// over long kernels.
 //
 // Two arithmetic forms: FP32 operands on the FP32 matrix cores
 // (v_mfma_f32_32x32x2_f32), and split FP16 (z = z_hi + z_lo, w = w_hi + w_lo
 // after power-of-two scaling; hi*hi + hi*lo + lo*hi with
-// v_mfma_f32_32x32x16_f16, FP32 accumulation).
+// v_mfma_f32_32x32x16_f16, FP32 accumulation).  In the split form the second
+// time block's Hankel fragment at step s is the first block's fragment at step
+// s + 2, so one LDS fragment load per plane and step serves both blocks.
 //
 // Optional fused read-out: instead of (or besides) storing the series, the
 // epilogue folds every output into the per-kernel peak (|z|^2 compared in FP32,
@@ -50,222 +59,366 @@ __device__ inline float abs2_rn(float re, float im) {
 }
 
 // Epilogue shared by both forms: scale, store and/or fold into the read-out.
-// tot[tb][nb][part] holds the wave's 2 x 2 blocks of (re, im).
+// tot[tb][ri] holds the wave's two time blocks, real and imaginary part.
 template <bool STORE, bool FUSED>
-__device__ inline void epilogue(floatx16 (&tot)[2][2][2], const TileDev& T, int64_t n, int64_t n0,
-                                int tw, int nw, int lane, const float* __restrict__ colscale,
+__device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t n, int64_t t_base,
+                                int lane, const float* __restrict__ colscale,
                                 const int32_t* __restrict__ slot_kernel, float extra_scale,
                                 float2* __restrict__ zout, const PeakOut& po) {
+  const int slot = lane & 31;
+  const bool live = slot < T.count;
+  const int k = live ? slot_kernel[T.first + slot] : 0;
+  const float cs = live ? colscale[T.first + slot] * extra_scale : 0.f;
+  Best best{-1.f, INT32_MAX};
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int slot = (2 * nw + nb) * 32 + (lane & 31);
-    const bool live = slot < T.count;
-    const int k = live ? slot_kernel[T.first + slot] : 0;
-    const float cs = live ? colscale[T.first + slot] * extra_scale : 0.f;
-    Best best{-1.f, INT32_MAX};
+  for (int tb = 0; tb < 2; ++tb) {
+    const int64_t base = t_base + 32 * tb;
 #pragma unroll
-    for (int tb = 0; tb < 2; ++tb) {
-      const int64_t base = n0 + 64 * tw + 32 * tb;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t m = base + acc_row(i, lane);
-        const float re = tot[tb][nb][0][i] * cs;
-        const float im = tot[tb][nb][1][i] * cs;
-        if (STORE && live) zout[int64_t(k) * n + m] = make_float2(re, im);
-        if (FUSED) {
-          const float a2 = abs2_rn(re, im);
-          best = better(best, Best{a2, int32_t(m)});
-          if (live && a2 > po.thr2) {
-            const unsigned long long slot_t = atomicAdd(po.count, 1ull);
-            if (int64_t(slot_t) < po.cap) {
-              rf_trigger tr;
-              tr.tmpl = k;
-              tr.seg = po.seg;
-              tr.idx = int32_t(m);
-              tr.absz = sqrtf(a2);
-              tr.argz = atan2f(im, re);
-              po.trig[slot_t] = tr;
-            }
+    for (int i = 0; i < 16; ++i) {
+      const int64_t m = base + acc_row(i, lane);
+      const float re = tot[tb][0][i] * cs;
+      const float im = tot[tb][1][i] * cs;
+      if (STORE && live) zout[int64_t(k) * n + m] = make_float2(re, im);
+      if (FUSED) {
+        const float a2 = abs2_rn(re, im);
+        best = better(best, Best{a2, int32_t(m)});
+        if (live && a2 > po.thr2) {
+          const unsigned long long slot_t = atomicAdd(po.count, 1ull);
+          if (int64_t(slot_t) < po.cap) {
+            rf_trigger tr;
+            tr.tmpl = k;
+            tr.seg = po.seg;
+            tr.idx = int32_t(m);
+            tr.absz = sqrtf(a2);
+            tr.argz = atan2f(im, re);
+            po.trig[slot_t] = tr;
           }
         }
       }
     }
-    if (FUSED) {
-      Best o{__shfl_xor(best.a2, 32), __shfl_xor(best.idx, 32)};
-      best = better(best, o);
-      if (live && lane < 32) {
-        const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
-                             uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
-        atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k),
-                  (unsigned long long)key);
-      }
+  }
+  if (FUSED) {
+    Best o{__shfl_xor(best.a2, 32), __shfl_xor(best.idx, 32)};
+    best = better(best, o);
+    if (live && lane < 32) {
+      const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
+                           uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
+      atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k),
+                (unsigned long long)key);
     }
   }
 }
 
+// Window of a chunk: samples z[(n0 + m0 + t0 + i) mod n], i < ch + kTimes + 32
+// (32 extra so that the prefetch of three steps ahead stays inside the buffer).
+constexpr int kWin = kChunk + kTimes + 32;
+constexpr int kStage = (kWin + 255) / 256;
+static_assert(kWin % 2 == 0, "window pairs");
+
+__device__ inline void zero(floatx16 (&a)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) a[x][y] = floatx16{};
+}
+__device__ inline void fold(floatx16 (&tot)[2][2], floatx16 (&acc)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      tot[x][y] += acc[x][y];
+      acc[x][y] = floatx16{};
+    }
+}
+
 template <bool STORE, bool FUSED>
-__global__ __launch_bounds__(256) void k_recon_f32(const float2* __restrict__ z, int64_t n,
-                                                   const TileDev* __restrict__ tiles,
-                                                   const float* __restrict__ b32,
-                                                   const float* __restrict__ colscale,
-                                                   const int32_t* __restrict__ slot_kernel,
-                                                   float2* __restrict__ zout, PeakOut po) {
-  __shared__ float zr[kChunk + kTimes];
-  __shared__ float zi[kChunk + kTimes];
+__global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__ z, int64_t n,
+                                                      const TileDev* __restrict__ tiles,
+                                                      const float* b32,
+                                                      const float* __restrict__ colscale,
+                                                      const int32_t* __restrict__ slot_kernel,
+                                                      float2* __restrict__ zout, PeakOut po) {
+  __shared__ float zr[2][kWin];
+  __shared__ float zi[2][kWin];
   const TileDev T = tiles[blockIdx.y];
   const int64_t n0 = int64_t(blockIdx.x) * kTimes;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tw = wave & 1, nw = wave >> 1;
   const int row = lane & 31, kh = lane >> 5;
-  floatx16 tot[2][2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) tot[a][b][c] = floatx16{};
+  floatx16 tot[2][2], acc[2][2];
+  zero(tot);
   const int64_t ntaps = T.ksteps * 16;
-  const float* __restrict__ B = b32 + T.b32_off;
+  const int nch = int((ntaps + kChunk - 1) / kChunk);
+  const int64_t last2 = T.ksteps * 8 - 1;           // last 2-tap step of the tile
+  const float* B = b32 + T.b32_off + lane;
   const int64_t mask = n - 1;
-  for (int64_t t0 = 0; t0 < ntaps; t0 += kChunk) {
-    const int ch = int(ntaps - t0 < kChunk ? ntaps - t0 : kChunk);
-    __syncthreads();
-    for (int i = threadIdx.x; i < ch + kTimes; i += 256) {
-      const float2 v = z[(n0 + T.m0 + t0 + i) & mask];
-      zr[i] = v.x;
-      zi[i] = v.y;
+  const int64_t gbase = n0 + T.m0;
+  float2 stage[kStage];
+  auto gather = [&](int64_t t0) {
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if (i < kWin) stage[r] = z[(gbase + t0 + i) & mask];
     }
-    __syncthreads();
-    floatx16 acc[2][2][2];
+  };
+  auto put = [&](int buf) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][b][c] = floatx16{};
-    const float* __restrict__ Bc = B + (t0 / 2) * 256;
-#pragma unroll 4
-    for (int s = 0; s < ch / 2; ++s) {
-      float bv[2];
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) bv[nb] = Bc[(s * 4 + 2 * nw + nb) * 64 + lane];
-#pragma unroll
-      for (int tb = 0; tb < 2; ++tb) {
-        const int idx = 64 * tw + 32 * tb + row + 2 * s + kh;
-        const float ar = zr[idx], ai = zi[idx];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          acc[tb][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bv[nb], acc[tb][nb][0], 0, 0, 0);
-          acc[tb][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bv[nb], acc[tb][nb][1], 0, 0, 0);
-        }
+    for (int r = 0; r < kStage; ++r) {
+      const int i = threadIdx.x + 256 * r;
+      if (i < kWin) {
+        zr[buf][i] = stage[r].x;
+        zi[buf][i] = stage[r].y;
       }
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) tot[a][b][c] += acc[a][b][c];
+  };
+  if (nch > 0) {
+    gather(0);
+    put(0);
   }
-  epilogue<STORE, FUSED>(tot, T, n, n0, tw, nw, lane, colscale, slot_kernel, 1.f, zout, po);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int64_t t0 = int64_t(c) * kChunk;
+    const int ch = int(ntaps - t0 < kChunk ? ntaps - t0 : kChunk);
+    const int buf = c & 1;
+    const bool more = c + 1 < nch;
+    if (more) gather(t0 + kChunk);
+    zero(acc);
+    const float* wr = &zr[buf][64 * wave + row + kh];
+    const float* wi = &zi[buf][64 * wave + row + kh];
+    const int64_t s0 = t0 / 2;
+    const int nst = ch / 2;                 // multiple of 32
+    float bq[4], aq[4][2][2];
+    auto load = [&](int st, float& bb, float (&aa)[2][2]) {
+      const int64_t g = s0 + st < last2 ? s0 + st : last2;
+      bb = B[g * 64];
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb) {
+        aa[tb][0] = wr[32 * tb + 2 * st];
+        aa[tb][1] = wi[32 * tb + 2 * st];
+      }
+    };
+    auto mma = [&](float bb, const float (&aa)[2][2]) {
+#pragma unroll
+      for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri)
+          acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x2f32(aa[tb][ri], bb, acc[tb][ri], 0, 0, 0);
+    };
+    load(0, bq[0], aq[0]);
+    load(1, bq[1], aq[1]);
+    load(2, bq[2], aq[2]);
+    for (int s = 0; s < nst; s += 4) {
+      load(s + 3, bq[3], aq[3]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bq[0], aq[0]);
+      load(s + 4, bq[0], aq[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bq[1], aq[1]);
+      load(s + 5, bq[1], aq[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bq[2], aq[2]);
+      load(s + 6, bq[2], aq[2]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bq[3], aq[3]);
+      // FP32 products enter the accumulator two at a time: fold it into the
+      // total every 128 taps to bound the rounding growth
+      if (((s + 4) & 63) == 0) fold(tot, acc);
+    }
+    fold(tot, acc);
+    if (more) put(buf ^ 1);
+    __syncthreads();
+  }
+  epilogue<STORE, FUSED>(tot, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, 1.f, zout, po);
 }
 
 // LDS window of the split reference series: 4 planes (re_hi, re_lo, im_hi,
-// im_lo) x 4 copies shifted by 0..3 samples, so that the 8 consecutive
-// samples an MFMA lane needs start on an 8-byte boundary in one of the copies.
-constexpr int kWin = kChunk + kTimes + 16;
+// im_lo), each holding 4 copies shifted by 0..3 samples, so that the 8
+// consecutive samples an MFMA lane needs start on an 8-byte boundary in one of
+// the copies.  The copies are interleaved in 8-byte groups, (copy sg, position
+// p) at half index (p & ~3) * 4 + sg * 4 + (p & 3): the 64 lanes of a fragment
+// load then touch consecutive 8-byte groups (no bank conflicts).
+__device__ inline int win_index(int sg, int p) { return (p & ~3) * 4 + sg * 4 + (p & 3); }
+
+// 8 consecutive samples of one copy: two 8-byte groups 16 halves apart.
+__device__ inline half8 lds_frag(const _Float16* p) {
+  const uint2* src = reinterpret_cast<const uint2*>(p);
+  const uint2 lo = src[0], hi = src[4];
+  const uint4 u = make_uint4(lo.x, lo.y, hi.x, hi.y);
+  half8 h;
+  __builtin_memcpy(&h, &u, 16);
+  return h;
+}
+
+// FP64 running total of the split form: tot[tb][ri][i] (128 registers).
+struct Tot64 {
+  double v[2][2][16];
+};
 
 template <bool STORE, bool FUSED>
-__global__ __launch_bounds__(256) void k_recon_f16(const __half* __restrict__ zs, int64_t n,
-                                                   const TileDev* __restrict__ tiles,
-                                                   const __half* __restrict__ b16,
-                                                   const float* __restrict__ colscale,
-                                                   const int32_t* __restrict__ slot_kernel,
-                                                   const float* __restrict__ zinv,
-                                                   float2* __restrict__ zout, PeakOut po) {
-  __shared__ __attribute__((aligned(16))) _Float16 win[4][4][kWin];
+__global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__ zs, int64_t n,
+                                                      const TileDev* __restrict__ tiles,
+                                                      const __half* b16,
+                                                      const float* __restrict__ colscale,
+                                                      const int32_t* __restrict__ slot_kernel,
+                                                      const float* __restrict__ zinv,
+                                                      float2* __restrict__ zout, PeakOut po) {
+  __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWin];
   const TileDev T = tiles[blockIdx.y];
   const int64_t n0 = int64_t(blockIdx.x) * kTimes;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tw = wave & 1, nw = wave >> 1;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
-  floatx16 tot[2][2][2];
+  // hi*hi products accumulate in `acc` and are folded into the FP64 total
+  // every 8 steps (so at most 8 FP32 roundings at the size of |z|); the two
+  // correction products, 2^-11 smaller, accumulate in `cor` per chunk
+  floatx16 acc[2][2], cor[2][2];
+  Tot64 tot;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) tot[a][b][c] = floatx16{};
+      for (int i = 0; i < 16; ++i) tot.v[x][y][i] = 0.0;
+  auto fold64 = [&](floatx16 (&a)[2][2]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) tot.v[x][y][i] += double(a[x][y][i]);
+        a[x][y] = floatx16{};
+      }
+  };
   const int64_t ntaps = T.ksteps * 16;
-  const half8* __restrict__ B = reinterpret_cast<const half8*>(b16 + T.b16_off);
+  const int nch = int((ntaps + kChunk - 1) / kChunk);
+  const int64_t last = T.ksteps - 1;
+  const half8* B = reinterpret_cast<const half8*>(b16 + T.b16_off) + lane;
   const _Float16* __restrict__ zp = reinterpret_cast<const _Float16*>(zs);
   const int64_t mask = n - 1;
-  for (int64_t t0 = 0; t0 < ntaps; t0 += kChunk) {
-    const int ch = int(ntaps - t0 < kChunk ? ntaps - t0 : kChunk);
-    __syncthreads();
-    for (int i = threadIdx.x; i < ch + kTimes; i += 256) {
-      const int64_t g = (n0 + T.m0 + t0 + i) & mask;
+  const int64_t gbase = n0 + T.m0;
+  // staging: each thread carries pairs of consecutive samples (i, i + 1),
+  // i = 2 tid + 512 r, packed two halves to a register
+  constexpr int kStage2 = (kWin + 511) / 512;
+  uint32_t stage[kStage2][4];
+  auto gather = [&](int64_t t0) {
 #pragma unroll
-      for (int pl = 0; pl < 4; ++pl) {
-        const _Float16 v = zp[int64_t(pl) * n + g];
+    for (int r = 0; r < kStage2; ++r) {
+      const int i = 2 * threadIdx.x + 512 * r;
+      if (i < kWin) {
+        const int64_t g0 = (gbase + t0 + i) & mask;
+        const int64_t g1 = (gbase + t0 + i + 1) & mask;
 #pragma unroll
-        for (int sg = 0; sg < 4; ++sg) {
-          const int p = i - sg;
-          if (p >= 0) win[pl][sg][p] = v;
+        for (int pl = 0; pl < 4; ++pl) {
+          const uint16_t lo = __builtin_bit_cast(uint16_t, zp[int64_t(pl) * n + g0]);
+          const uint16_t hi = __builtin_bit_cast(uint16_t, zp[int64_t(pl) * n + g1]);
+          stage[r][pl] = uint32_t(lo) | (uint32_t(hi) << 16);
         }
       }
     }
-    __syncthreads();
-    floatx16 acc[2][2][2];
+  };
+  auto put = [&](int buf) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][b][c] = floatx16{};
-    const half8* __restrict__ Bc = B + (t0 / 16) * 512;
-#pragma unroll 2
-    for (int s = 0; s < ch / 16; ++s) {
-      half8 bh[2], bl[2];
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const int blk = 2 * nw + nb;
-        bh[nb] = Bc[((s * 4 + blk) * 2 + 0) * 64 + lane];
-        bl[nb] = Bc[((s * 4 + blk) * 2 + 1) * 64 + lane];
-      }
-#pragma unroll
-      for (int tb = 0; tb < 2; ++tb) {
-        const int p = (row - sigma) + 64 * tw + 32 * tb + 8 * kh + 16 * s;
-        half8 a[4];
+    for (int r = 0; r < kStage2; ++r) {
+      const int i = 2 * threadIdx.x + 512 * r;
+      if (i < kWin) {
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) {
-          const uint2* src = reinterpret_cast<const uint2*>(&win[pl][sigma][p]);
-          uint2 lo = src[0], hi = src[1];
-          uint4 u = make_uint4(lo.x, lo.y, hi.x, hi.y);
-          __builtin_memcpy(&a[pl], &u, 16);
-        }
+          const _Float16 v0 = __builtin_bit_cast(_Float16, uint16_t(stage[r][pl] & 0xFFFFu));
+          const _Float16 v1 = __builtin_bit_cast(_Float16, uint16_t(stage[r][pl] >> 16));
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-#pragma unroll
-          for (int part = 0; part < 2; ++part) {
-            floatx16 c = acc[tb][nb][part];
-            c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[2 * part + 0], bh[nb], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[2 * part + 0], bl[nb], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[2 * part + 1], bh[nb], c, 0, 0, 0);
-            acc[tb][nb][part] = c;
+          for (int sg = 0; sg < 4; ++sg) {
+            if (i >= sg) win[buf][pl][win_index(sg, i - sg)] = v0;
+            if (i + 1 >= sg) win[buf][pl][win_index(sg, i + 1 - sg)] = v1;
           }
         }
       }
     }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) tot[a][b][c] += acc[a][b][c];
+  };
+  if (nch > 0) {
+    gather(0);
+    put(0);
   }
-  epilogue<STORE, FUSED>(tot, T, n, n0, tw, nw, lane, colscale, slot_kernel, *zinv, zout, po);
+  __syncthreads();
+  // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
+  // multiple of 4; in the interleaved layout 4 positions are 16 halves)
+  const int p0 = (row - sigma) + 64 * wave + 8 * kh;
+  for (int c = 0; c < nch; ++c) {
+    const int64_t t0 = int64_t(c) * kChunk;
+    const int ch = int(ntaps - t0 < kChunk ? ntaps - t0 : kChunk);
+    const int buf = c & 1;
+    const bool more = c + 1 < nch;
+    if (more) gather(t0 + kChunk);
+    zero(acc);
+    zero(cor);
+    const _Float16* wb[4];
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
+    const int64_t s0 = t0 / 16;
+    const int nst = ch / 16;                // multiple of 8
+    half8 f[4][4], bh[4], bl[4];            // [slot][plane], [slot]
+    auto loadF = [&](int j, half8 (&ff)[4]) {
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) ff[pl] = lds_frag(wb[pl] + 64 * j);
+    };
+    auto loadB = [&](int st, half8& h, half8& l) {
+      const int64_t g = s0 + st < last ? s0 + st : last;
+      h = B[g * 128];
+      l = B[g * 128 + 64];
+    };
+    // step s: time block 0 uses F(s), time block 1 uses F(s + 2); three split
+    // products, consecutive MFMAs feeding independent accumulators
+    auto mma = [&](const half8 (&f0)[4], const half8 (&f1)[4], const half8& h, const half8& l) {
+#pragma unroll
+      for (int part = 0; part < 3; ++part)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
+            const half8 bv = part == 1 ? l : h;
+            if (part == 0)
+              acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
+            else
+              cor[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, cor[tb][ri], 0, 0, 0);
+          }
+    };
+    // F runs three steps ahead (step s + 1 needs F(s + 3)), B two steps ahead
+    loadF(0, f[0]);
+    loadF(1, f[1]);
+    loadF(2, f[2]);
+    loadB(0, bh[0], bl[0]);
+    loadB(1, bh[1], bl[1]);
+    for (int s = 0; s < nst; s += 4) {
+      loadF(s + 3, f[3]);
+      loadB(s + 2, bh[2], bl[2]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(f[0], f[2], bh[0], bl[0]);
+      loadF(s + 4, f[0]);
+      loadB(s + 3, bh[3], bl[3]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(f[1], f[3], bh[1], bl[1]);
+      loadF(s + 5, f[1]);
+      loadB(s + 4, bh[0], bl[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(f[2], f[0], bh[2], bl[2]);
+      loadF(s + 6, f[2]);
+      loadB(s + 5, bh[1], bl[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(f[3], f[1], bh[3], bl[3]);
+      if ((s & 7) == 4) fold64(acc);
+    }
+    fold64(acc);
+    fold64(cor);
+    if (more) put(buf ^ 1);
+    __syncthreads();
+  }
+  floatx16 totf[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) totf[x][y][i] = float(tot.v[x][y][i]);
+  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, *zinv, zout, po);
 }
 
 // max(|re|, |im|) over the series, as float bits (non-negative floats order as integers)
@@ -307,35 +460,38 @@ __device__ inline double tap_of(const double* __restrict__ taps64, const int64_t
   return (l >= 0 && l < len[k]) ? taps64[off[k] + l] : 0.0;
 }
 
+// FP32 operand of a tile: per 2-tap step g, lane l holds w_{slot l%32}[m0 + 2 g + l/32].
 __global__ void k_pack_b32(const double* __restrict__ taps64, const int64_t* __restrict__ off,
                            const int64_t* __restrict__ mlo, const int32_t* __restrict__ len,
                            const TileDev* __restrict__ tiles, const int32_t* __restrict__ slot_kernel,
                            float* b32) {
   const TileDev T = tiles[blockIdx.y];
-  const int64_t total = T.ksteps * 8 * 4 * 64;
+  const int64_t total = T.ksteps * kB32PerStep;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t s = e / 256;
-    const int blk = int((e / 64) & 3), lane = int(e & 63);
-    const int slot = blk * 32 + (lane & 31);
+    const int64_t g = e / 64;
+    const int lane = int(e & 63);
+    const int slot = lane & 31;
     double v = 0.0;
-    if (slot < T.count) v = tap_of(taps64, off, mlo, len, slot_kernel[T.first + slot], T.m0 + 2 * s + (lane >> 5));
+    if (slot < T.count) v = tap_of(taps64, off, mlo, len, slot_kernel[T.first + slot], T.m0 + 2 * g + (lane >> 5));
     b32[T.b32_off + e] = float(v);
   }
 }
 
+// FP16 operand of a tile: per 16-tap step s, the hi fragment then the lo
+// fragment; lane l holds 8 halves w_{slot l%32}[m0 + 16 s + 8 (l/32) + 0..7]
+// (scaled by the kernel's power-of-two s_k).
 __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __restrict__ off,
                            const int64_t* __restrict__ mlo, const int32_t* __restrict__ len,
                            const double* __restrict__ kscale, const TileDev* __restrict__ tiles,
                            const int32_t* __restrict__ slot_kernel, __half* b16) {
   const TileDev T = tiles[blockIdx.y];
-  const int64_t total = T.ksteps * 4 * 2 * 64 * 8;
+  const int64_t total = T.ksteps * kB16PerStep;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t s = e / 4096;
-    const int blk = int((e / 1024) & 3), part = int((e / 512) & 1), lane = int((e / 8) & 63),
-              ee = int(e & 7);
-    const int slot = blk * 32 + (lane & 31);
+    const int64_t s = e / 1024;
+    const int part = int((e / 512) & 1), lane = int((e / 8) & 63), ee = int(e & 7);
+    const int slot = lane & 31;
     float out = 0.f;
     if (slot < T.count) {
       const int k = slot_kernel[T.first + slot];
@@ -372,11 +528,22 @@ __global__ __launch_bounds__(256) void k_peaks(const float2* __restrict__ z, int
     Best q{__shfl_xor(best.a2, o), __shfl_xor(best.idx, o)};
     best = better(best, q);
   }
-  if ((threadIdx.x & 63) == 0 && best.idx != INT32_MAX) {
-    const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
-                         uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
-    atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + blockIdx.y),
-              (unsigned long long)key);
+  __shared__ float sa[4];
+  __shared__ int32_t si[4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sa[wv] = best.a2;
+    si[wv] = best.idx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) best = better(best, Best{sa[i], si[i]});
+    if (best.idx != INT32_MAX) {
+      const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
+                           uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
+      atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + blockIdx.y),
+                (unsigned long long)key);
+    }
   }
 }
 
@@ -437,18 +604,23 @@ void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __
 void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const int64_t* mlo_dev,
                  const int32_t* len_dev, const double* kscale_dev, const TileDev* tiles_dev,
                  int ntiles, int64_t max_ksteps) {
-  dim3 g32(nblk(max_ksteps * 2048, 4096), unsigned(ntiles));
+  dim3 g32(nblk(max_ksteps * kB32PerStep, 4096), unsigned(ntiles));
   hipLaunchKernelGGL(k_pack_b32, g32, dim3(256), 0, ctx->stream, K->taps64, off_dev, mlo_dev,
                      len_dev, tiles_dev, K->slot_kernel, K->b32);
   RF_HIP(hipGetLastError());
-  dim3 g16(nblk(max_ksteps * 4096, 4096), unsigned(ntiles));
+  dim3 g16(nblk(max_ksteps * kB16PerStep, 4096), unsigned(ntiles));
   hipLaunchKernelGGL(k_pack_b16, g16, dim3(256), 0, ctx->stream, K->taps64, off_dev, mlo_dev,
                      len_dev, kscale_dev, tiles_dev, K->slot_kernel, K->b16);
   RF_HIP(hipGetLastError());
 }
 
 void peaks_launch(rf_ctx* ctx, const float2* z, int nt, int64_t n, const PeakOut& po) {
-  dim3 grid(nblk(n, 1024), unsigned(nt));
+  // about 4096 blocks in total, at least 16 and at most 1024 per series
+  int64_t per = 4096 / nt;
+  per = per < 16 ? 16 : (per > 1024 ? 1024 : per);
+  const int64_t cap = (n + 255) / 256;
+  if (per > cap) per = cap;
+  const dim3 grid{unsigned(per), unsigned(nt), 1u};
   hipLaunchKernelGGL(k_peaks, grid, dim3(256), 0, ctx->stream, z, n, po);
   RF_HIP(hipGetLastError());
 }

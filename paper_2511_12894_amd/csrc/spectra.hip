@@ -215,13 +215,27 @@ __global__ __launch_bounds__(256) void k_support_scan(const double2* __restrict_
       mhi = max(mhi, s);
     }
   }
-  // wave reduction, then one atomic per wave
+  // wave reduction, then block reduction, then one atomic per block
   for (int o = 32; o > 0; o >>= 1) {
     mlo = min(mlo, __shfl_xor(mlo, o));
     mhi = max(mhi, __shfl_xor(mhi, o));
     mx = fmaxf(mx, __shfl_xor(mx, o));
   }
+  __shared__ int32_t slo[4], shi[4];
+  __shared__ float smx[4];
+  const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    slo[wv] = mlo;
+    shi[wv] = mhi;
+    smx[wv] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      mlo = min(mlo, slo[i]);
+      mhi = max(mhi, shi[i]);
+      mx = fmaxf(mx, smx[i]);
+    }
     if (mlo != INT32_MAX) {
       atomicMin(&lo[blockIdx.y], mlo);
       atomicMax(&hi[blockIdx.y], mhi);
@@ -303,7 +317,7 @@ void ratio_spectrum(rf_ctx* ctx, const rf_grid* g, int64_t nb, const Tf2Coef* re
 
 void support_scan(rf_ctx* ctx, const double2* w, int64_t nb, int nk, double thr_tap, int32_t* lo,
                   int32_t* hi, uint32_t* maxabs_bits) {
-  dim3 grid(blocks_for(nb, 256, 2048), unsigned(nk));
+  dim3 grid(blocks_for(nb, 256, 256), unsigned(nk));
   hipLaunchKernelGGL(k_support_scan, grid, dim3(256), 0, ctx->stream, w, nb, thr_tap, lo, hi,
                      maxabs_bits);
   RF_HIP(hipGetLastError());
