@@ -56,6 +56,20 @@ def timed(fn, steps, warmup, stream):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
+def counter_traffic():
+    """Calibrated HBM bytes per launch of the split-FP16 kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since."""
+    import hashlib
+    try:
+        d = json.load(open(os.path.join(ROOT, "profiles", "k_recon_f16_counters.json")))
+        src = open(os.path.join(ROOT, d["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+        return None
+    return float(d["traffic_bytes_per_dispatch"])
+
+
 def executed_taps(info, per_tile=32, align=64):
     """Taps the matrix-core kernels execute: kernels sorted by first tap, 32
     per tile, each tile spanning its union support rounded up to 64 taps, for
@@ -205,7 +219,7 @@ def main():
         t_rec = res["step"]["recon_ms"] * 1e-3
         ach = alg_flops / t_rec / 1e12
         out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / PEAK_FP16_TFLOPS, "traffic": None,
+                           "frac": ach / PEAK_FP16_TFLOPS, "traffic": counter_traffic(),
                            "kernel": "k_recon_f16 (split-FP16 reconstruction)",
                            "mfma_products_frac": 3 * ach / PEAK_FP16_TFLOPS,
                            "executed_over_useful_taps": exec_taps / sum_l,
