@@ -105,6 +105,60 @@ def cpu_baseline(w, n_nbr_sample):
                        f"full 2^21-sample series, numpy FP64 on one host core ({dt:.2f} s)")
 
 
+def batched_leg(dev):
+    """Batched uneven workload (reduced): 4 segments of 32 s at 1024 Hz, 8
+    references with 8..96 lattice neighbours (log-uniform), one persistent
+    split-FP16 launch in a captured graph with autotuned chunks, against the
+    per-(segment, reference) call loop on the same data."""
+    wb = synth.workload_batched(n_seg=4, n_ref=8, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
+                                nbr_range=(8, 96))
+    g = wb["grid"]
+    stream = torch.cuda.Stream(dev)
+    ctx = rf.Context(0, stream)
+    psd = torch.from_numpy(wb["psd"]).to(dev)
+    xf = torch.from_numpy(np.stack(wb["segments"])).to(dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
+        batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=len(wb["segments"]))
+        chunks = batch.autotune(xf)
+        sum_l = sum(sum(k.info()["len"]) for k in ksets)
+        batch.run(xf, 6.0)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            out = batch.run(xf, 6.0)
+        t_batch = (time.perf_counter() - t0) / reps
+        z = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
+
+        def loop():
+            for s_ in range(len(wb["segments"])):
+                for r, K in enumerate(ksets):
+                    rf.mf_ref_snr(ctx, g, xf[s_].contiguous(), psd, [wb["refs"][r]], z=z, want_sigma=False)
+                    rf.snr_reconstruct(ctx, K, z[0], prec="split16", store=False, fused_thr=6.0)
+        loop()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        loop()
+        stream.synchronize()
+        t_loop = time.perf_counter() - t0
+    nseg = len(wb["segments"])
+    ktot = batch.ktotal
+    flops = 4.0 * g.n * sum_l * nseg
+    samples = (ktot + len(wb["refs"])) * g.n * nseg
+    res = dict(workload=wb["name"] + "-reduced", segments=nseg, references=len(wb["refs"]),
+               kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks,
+               batch_ms=t_batch * 1e3, loop_ms=t_loop * 1e3, speedup=t_loop / t_batch,
+               value=samples / t_batch, unit="template-samples/s",
+               frac_fp16_peak=flops / t_batch / 1e12 / PEAK_FP16_TFLOPS, ntrig=out["ntrig"])
+    batch.free()
+    for k in ksets:
+        k.free()
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +174,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "build"}
+    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "build", "batched"}
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -204,6 +258,8 @@ def main():
         e32 = (zout - zall[1:]).abs().max().item()
         res["err_vs_direct"] = dict(split16=e16, fp32=e32)
         del zall
+    if "batched" in legs:
+        res["batched"] = batched_leg(dev)
     torch.cuda.synchronize()
 
     out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -243,6 +299,8 @@ def main():
         extra["direct_fft_mf_ms"] = dms
         extra["direct_fft_mf_value"] = samples / (dms * 1e-3)
         extra["err_vs_direct_mf"] = res["err_vs_direct"]
+    if "batched" in res:
+        extra["batched"] = res["batched"]
     out["extra"] = extra
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -155,6 +155,46 @@ rf_status snr_reconstruct(rf_ctx* ctx, const rf_kernels* k, const void* z_ref, i
 rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr, rf_peak* peaks,
                     rf_trigger* trig, int64_t cap, int64_t* ntrig);
 
+/* ---- batched form (many references, uneven neighbour sets, several segments) ----
+ *
+ * A batch holds nref reference groups (each a template and its kernel set from
+ * ratio_kernel_build on the same grid) and nseg data segments.  One call of
+ * rf_batch_run computes, for every segment s and reference r, the reference
+ * series (as mf_ref_snr) and the reconstructed series of every kernel of group
+ * r (as snr_reconstruct with RF_PREC_SPLIT_FP16), reading them out only
+ * through the fused peak/threshold read-out -- the series are not stored.  The
+ * device work is one captured hipGraph (re-captured when a pointer, cap or thr
+ * changes) whose reconstruction is a single persistent launch over all
+ * (segment, tile, time block) work items, longest tiles first.  Kernel k of
+ * group r has global index kbase[r] + k.  The batch borrows psd and the kernel
+ * sets' contents are copied (the sets may be freed afterwards); it owns its
+ * device buffers (about 24 bytes per sample per (segment, reference)). */
+typedef struct rf_batch rf_batch;
+
+/* psd: device double [n/2+1], must outlive the batch; refs: host [nref];
+ * ksets: host [nref]; nseg * nref <= 65535.  Synchronises the stream. */
+rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, int32_t nref,
+                          const rf_tmpl* refs, rf_kernels* const* ksets, int32_t nseg,
+                          rf_batch** out);
+/* Host copies (any pointer may be NULL): total kernels, work items, kbase[nref],
+ * chosen chunk sizes (taps) for kernels of <= 1024, <= 8192 and longer taps. */
+rf_status rf_batch_info(const rf_batch* b, int32_t* ktotal, int64_t* nitems, int32_t* kbase,
+                        int32_t* chunk_per_bucket);
+/* Set the chunk sizes (each 256, 512 or 1024) without timing. */
+rf_status rf_batch_set_chunks(rf_batch* b, const int32_t* chunk_per_bucket);
+/* Time each chunk size on each kernel-length bucket's work items with the data
+ * xf_segs (device complex128 [nseg][n/2+1]) and keep the fastest; when
+ * cache_path is given, a line keyed by the batch's shape and the device name
+ * is read if present (no timing) or appended.  Synchronises. */
+rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const char* cache_path);
+/* xf_segs: device complex128 [nseg][n/2+1]; peaks: device rf_peak [nseg][ktotal];
+ * trig: device rf_trigger [cap] (tmpl = global kernel index, seg = segment);
+ * ntrig: host.  Needs a non-NULL stream in ctx (graph capture).  Synchronises;
+ * RF_E_OVERFLOW when the crossings exceed cap. */
+rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr, rf_peak* peaks,
+                       rf_trigger* trig, int64_t cap, int64_t* ntrig);
+rf_status rf_batch_free(rf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

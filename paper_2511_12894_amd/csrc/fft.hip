@@ -208,7 +208,7 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
 
 template <typename T>
 void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int batch) {
+                 int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in) {
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
@@ -216,8 +216,13 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   const int s = int(bits.size());
   V* wa = nullptr;
   V* wb = nullptr;
-  if (s > 1) wa = static_cast<V*>(ctx->ws[WS_FFT_A].ensure(sizeof(V) * size_t(n) * batch));
-  if (s > 2) wb = static_cast<V*>(ctx->ws[WS_FFT_B].ensure(sizeof(V) * size_t(n) * batch));
+  if (wsa_in) {
+    wa = wsa_in;
+    wb = wsb_in;
+  } else {
+    if (s > 1) wa = static_cast<V*>(ctx->ws[WS_FFT_A].ensure(sizeof(V) * size_t(n) * batch));
+    if (s > 2) wb = static_cast<V*>(ctx->ws[WS_FFT_B].ensure(sizeof(V) * size_t(n) * batch));
+  }
   const V* src = in;
   int64_t ns = 1;
   for (int i = 0; i < s; ++i) {
@@ -230,11 +235,12 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
 
 }  // namespace
 
-void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch) {
-  fft_inverse<float>(ctx, in, out, n, batch);
+void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch, float2* wsa,
+                     float2* wsb) {
+  fft_inverse<float>(ctx, in, out, n, batch, wsa, wsb);
 }
 void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch) {
-  fft_inverse<double>(ctx, in, out, n, batch);
+  fft_inverse<double>(ctx, in, out, n, batch, nullptr, nullptr);
 }
 
 }  // namespace rf

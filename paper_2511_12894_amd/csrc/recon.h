@@ -8,7 +8,8 @@ namespace rf {
 constexpr int kTileKernels = 32;   // kernels per tile (one 32-wide MFMA block)
 constexpr int kTimes = 256;        // output times per workgroup (4 waves x 64)
 constexpr int kChunk = 512;        // taps per LDS window chunk / accumulation chunk
-constexpr int kStepAlign = 4;      // tiles span a multiple of 4 16-tap steps
+constexpr int kChunkMax = 1024;    // largest chunk a split-FP16 work item may use
+constexpr int kStepAlign = 8;      // tiles span a multiple of 8 16-tap steps
 constexpr int kB32PerStep = 512;   // FP32 operand floats per 16-tap step of a tile
 constexpr int kB16PerStep = 1024;  // FP16 operand halves per 16-tap step (hi + lo)
 
@@ -25,11 +26,27 @@ struct PeakOut {
   int32_t nk;
 };
 
+// Batched form: a tile of some reference's kernel set (slot arrays global
+// over the batch) and one unit of work of the persistent launch.
+struct BatchTile {
+  TileDev t;
+  int32_t ref;
+  int32_t pad;
+};
+struct WorkItem {
+  int32_t seg, tile, tblock, chunk;
+};
+
 void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const TileDev* tiles,
                   int ntiles, const rf_kernels* K, const float* zinv, float2* zout, const PeakOut& po,
                   bool fused);
 void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __half* zs,
-                  float* inv_scale);
+                  float* inv_scale, int nseries = 1);
+int queue_blocks(int device);
+void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
+                  const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
+                  const __half* b16, const float* colscale, const int32_t* slot_kernel,
+                  const float* zinv_all, const PeakOut& po);
 void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const int64_t* mlo_dev,
                  const int32_t* len_dev, const double* kscale_dev, const TileDev* tiles_dev,
                  int ntiles, int64_t max_ksteps);

@@ -32,6 +32,8 @@
 // Optional fused read-out: instead of (or besides) storing the series, the
 // epilogue folds every output into the per-kernel peak (|z|^2 compared in FP32,
 // smallest index on ties) and appends threshold crossings.
+#include <algorithm>
+
 #include "recon.h"
 
 namespace rf {
@@ -112,6 +114,7 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
 // Window of a chunk: samples z[(n0 + m0 + t0 + i) mod n], i < ch + kTimes + 32
 // (32 extra so that the prefetch of three steps ahead stays inside the buffer).
 constexpr int kWin = kChunk + kTimes + 32;
+constexpr int kWinMax = kChunkMax + kTimes + 32;
 constexpr int kStage = (kWin + 255) / 256;
 static_assert(kWin % 2 == 0, "window pairs");
 
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     const float* wr = &zr[buf][64 * wave + row + kh];
     const float* wi = &zi[buf][64 * wave + row + kh];
     const int64_t s0 = t0 / 2;
-    const int nst = ch / 2;                 // multiple of 32
+    const int nst = ch / 2;                 // multiple of 64 (tiles span 128-tap multiples)
     float bq[4], aq[4][2][2];
     auto load = [&](int st, float& bb, float (&aa)[2][2]) {
       const int64_t g = s0 + st < last2 ? s0 + st : last2;
@@ -206,24 +209,25 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     load(0, bq[0], aq[0]);
     load(1, bq[1], aq[1]);
     load(2, bq[2], aq[2]);
-    for (int s = 0; s < nst; s += 4) {
-      load(s + 3, bq[3], aq[3]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(bq[0], aq[0]);
-      load(s + 4, bq[0], aq[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(bq[1], aq[1]);
-      load(s + 5, bq[1], aq[1]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(bq[2], aq[2]);
-      load(s + 6, bq[2], aq[2]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(bq[3], aq[3]);
-      // FP32 products enter the accumulator two at a time: fold it into the
-      // total every 128 taps to bound the rounding growth
-      if (((s + 4) & 63) == 0) fold(tot, acc);
+    // FP32 products enter the accumulator two at a time: it is folded into the
+    // total every 64 steps (128 taps) to bound the rounding growth
+    for (int s64 = 0; s64 < nst; s64 += 64) {
+      for (int s = s64; s < s64 + 64; s += 4) {
+        load(s + 3, bq[3], aq[3]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(bq[0], aq[0]);
+        load(s + 4, bq[0], aq[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(bq[1], aq[1]);
+        load(s + 5, bq[1], aq[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(bq[2], aq[2]);
+        load(s + 6, bq[2], aq[2]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(bq[3], aq[3]);
+      }
+      fold(tot, acc);
     }
-    fold(tot, acc);
     if (more) put(buf ^ 1);
     __syncthreads();
   }
@@ -253,17 +257,15 @@ struct Tot64 {
   double v[2][2][16];
 };
 
+// One work item of the split form: output times [n0, n0 + kTimes) of tile T,
+// window chunks of `chunk` taps (256, 512 or 1024; a multiple of 64).
 template <bool STORE, bool FUSED>
-__global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__ zs, int64_t n,
-                                                      const TileDev* __restrict__ tiles,
-                                                      const __half* b16,
-                                                      const float* __restrict__ colscale,
-                                                      const int32_t* __restrict__ slot_kernel,
-                                                      const float* __restrict__ zinv,
-                                                      float2* __restrict__ zout, PeakOut po) {
-  __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWin];
-  const TileDev T = tiles[blockIdx.y];
-  const int64_t n0 = int64_t(blockIdx.x) * kTimes;
+__device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
+                                      int64_t n, const TileDev& T, int64_t n0, int chunk,
+                                      const __half* b16, const float* __restrict__ colscale,
+                                      const int32_t* __restrict__ slot_kernel, float zinv,
+                                      float2* __restrict__ zout, const PeakOut& po) {
+  const int win_len = chunk + kTimes + 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
       }
   };
   const int64_t ntaps = T.ksteps * 16;
-  const int nch = int((ntaps + kChunk - 1) / kChunk);
+  const int nch = int((ntaps + chunk - 1) / chunk);
   const int64_t last = T.ksteps - 1;
   const half8* B = reinterpret_cast<const half8*>(b16 + T.b16_off) + lane;
   const _Float16* __restrict__ zp = reinterpret_cast<const _Float16*>(zs);
@@ -297,13 +299,13 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
   const int64_t gbase = n0 + T.m0;
   // staging: each thread carries pairs of consecutive samples (i, i + 1),
   // i = 2 tid + 512 r, packed two halves to a register
-  constexpr int kStage2 = (kWin + 511) / 512;
+  constexpr int kStage2 = (kWinMax + 511) / 512;
   uint32_t stage[kStage2][4];
   auto gather = [&](int64_t t0) {
 #pragma unroll
     for (int r = 0; r < kStage2; ++r) {
       const int i = 2 * threadIdx.x + 512 * r;
-      if (i < kWin) {
+      if (i < win_len) {
         const int64_t g0 = (gbase + t0 + i) & mask;
         const int64_t g1 = (gbase + t0 + i + 1) & mask;
 #pragma unroll
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
 #pragma unroll
     for (int r = 0; r < kStage2; ++r) {
       const int i = 2 * threadIdx.x + 512 * r;
-      if (i < kWin) {
+      if (i < win_len) {
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) {
           const _Float16 v0 = __builtin_bit_cast(_Float16, uint16_t(stage[r][pl] & 0xFFFFu));
@@ -342,18 +344,18 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
   // multiple of 4; in the interleaved layout 4 positions are 16 halves)
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
   for (int c = 0; c < nch; ++c) {
-    const int64_t t0 = int64_t(c) * kChunk;
-    const int ch = int(ntaps - t0 < kChunk ? ntaps - t0 : kChunk);
+    const int64_t t0 = int64_t(c) * chunk;
+    const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
     const int buf = c & 1;
     const bool more = c + 1 < nch;
-    if (more) gather(t0 + kChunk);
+    if (more) gather(t0 + chunk);
     zero(acc);
     zero(cor);
     const _Float16* wb[4];
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
     const int64_t s0 = t0 / 16;
-    const int nst = ch / 16;                // multiple of 8
+    const int nst = ch / 16;                // multiple of 8 (tiles span 128-tap multiples)
     half8 f[4][4], bh[4], bl[4];            // [slot][plane], [slot]
     auto loadF = [&](int j, half8 (&ff)[4]) {
 #pragma unroll
@@ -387,26 +389,30 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
     loadF(2, f[2]);
     loadB(0, bh[0], bl[0]);
     loadB(1, bh[1], bl[1]);
-    for (int s = 0; s < nst; s += 4) {
-      loadF(s + 3, f[3]);
-      loadB(s + 2, bh[2], bl[2]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(f[0], f[2], bh[0], bl[0]);
-      loadF(s + 4, f[0]);
-      loadB(s + 3, bh[3], bl[3]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(f[1], f[3], bh[1], bl[1]);
-      loadF(s + 5, f[1]);
-      loadB(s + 4, bh[0], bl[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(f[2], f[0], bh[2], bl[2]);
-      loadF(s + 6, f[2]);
-      loadB(s + 5, bh[1], bl[1]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(f[3], f[1], bh[3], bl[3]);
-      if ((s & 7) == 4) fold64(acc);
+    // one iteration = 8 steps; the hi*hi accumulator is folded at its end
+    for (int s = 0; s < nst; s += 8) {
+#pragma unroll
+      for (int h = 0; h < 8; h += 4) {
+        const int q = s + h;
+        loadF(q + 3, f[3]);
+        loadB(q + 2, bh[2], bl[2]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f[0], f[2], bh[0], bl[0]);
+        loadF(q + 4, f[0]);
+        loadB(q + 3, bh[3], bl[3]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f[1], f[3], bh[1], bl[1]);
+        loadF(q + 5, f[1]);
+        loadB(q + 4, bh[0], bl[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f[2], f[0], bh[2], bl[2]);
+        loadF(q + 6, f[2]);
+        loadB(q + 5, bh[1], bl[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(f[3], f[1], bh[3], bl[3]);
+      }
+      fold64(acc);
     }
-    fold64(acc);
     fold64(cor);
     if (more) put(buf ^ 1);
     __syncthreads();
@@ -418,12 +424,58 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 16; ++i) totf[x][y][i] = float(tot.v[x][y][i]);
-  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, *zinv, zout, po);
+  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, zinv, zout, po);
+}
+
+template <bool STORE, bool FUSED>
+__global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__ zs, int64_t n,
+                                                      const TileDev* __restrict__ tiles,
+                                                      const __half* b16,
+                                                      const float* __restrict__ colscale,
+                                                      const int32_t* __restrict__ slot_kernel,
+                                                      const float* __restrict__ zinv,
+                                                      float2* __restrict__ zout, PeakOut po, int chunk) {
+  __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWinMax];
+  recon_f16_item<STORE, FUSED>(win, zs, n, tiles[blockIdx.y], int64_t(blockIdx.x) * kTimes, chunk, b16,
+                               colscale, slot_kernel, *zinv, zout, po);
+}
+
+// Persistent form over a work list: every workgroup takes items
+// (segment, tile, time block, chunk) from a queue in the order given (longest
+// tiles first) until the list is exhausted; every wave reaches the exit.
+__global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __restrict__ zs_all, int64_t n,
+                                                            int32_t nref,
+                                                            const BatchTile* __restrict__ tiles,
+                                                            const WorkItem* __restrict__ items,
+                                                            int32_t nitems, uint32_t* counter,
+                                                            const __half* b16,
+                                                            const float* __restrict__ colscale,
+                                                            const int32_t* __restrict__ slot_kernel,
+                                                            const float* __restrict__ zinv_all,
+                                                            PeakOut po) {
+  __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWinMax];
+  __shared__ int32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = int32_t(atomicAdd(counter, 1u));
+    __syncthreads();
+    const int32_t it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const WorkItem w = items[it];
+    const BatchTile bt = tiles[w.tile];
+    const int64_t sr = int64_t(w.seg) * nref + bt.ref;
+    PeakOut p = po;
+    p.seg = w.seg;
+    recon_f16_item<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock) * kTimes, w.chunk,
+                                b16, colscale, slot_kernel, zinv_all[sr], nullptr, p);
+  }
 }
 
 // max(|re|, |im|) over the series, as float bits (non-negative floats order as integers)
 __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ z, int64_t n,
                                                 uint32_t* out) {
+  z += int64_t(blockIdx.y) * n;
+  out += blockIdx.y;
   float m = 0.f;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     const float2 v = z[i];
@@ -437,6 +489,10 @@ __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ z, in
 __global__ __launch_bounds__(256) void k_split(const float2* __restrict__ z, int64_t n,
                                                const uint32_t* __restrict__ maxbits, __half* zs,
                                                float* inv_scale) {
+  z += int64_t(blockIdx.y) * n;
+  maxbits += blockIdx.y;
+  zs += int64_t(blockIdx.y) * 4 * n;
+  inv_scale += blockIdx.y;
   const float mx = __uint_as_float(*maxbits);
   int ex = 0;
   frexpf(mx, &ex);
@@ -579,7 +635,7 @@ void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const 
   else                                                                                          \
     hipLaunchKernelGGL((k_recon_f16<S, F>), grid, dim3(256), 0, ctx->stream,                    \
                        static_cast<const __half*>(zsrc), n, tiles, K->b16, K->colscale16,       \
-                       K->slot_kernel, zinv, zout, po);
+                       K->slot_kernel, zinv, zout, po, int(kChunk));
   if (store && fused) {
     RF_RECON(true, true)
   } else if (store) {
@@ -592,12 +648,30 @@ void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const 
 }
 
 void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __half* zs,
-                  float* inv_scale) {
-  fill_u32(ctx, maxbits, 0u, 1);
-  hipLaunchKernelGGL(k_absmax, dim3(nblk(n, 2048)), dim3(256), 0, ctx->stream, z, n, maxbits);
+                  float* inv_scale, int nseries) {
+  fill_u32(ctx, maxbits, 0u, nseries);
+  const unsigned per = nblk(n, unsigned(std::max(64, 2048 / nseries)));
+  hipLaunchKernelGGL(k_absmax, dim3(per, unsigned(nseries)), dim3(256), 0, ctx->stream, z, n, maxbits);
   RF_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_split, dim3(nblk(n, 4096)), dim3(256), 0, ctx->stream, z, n, maxbits, zs,
-                     inv_scale);
+  hipLaunchKernelGGL(k_split, dim3(per, unsigned(nseries)), dim3(256), 0, ctx->stream, z, n, maxbits,
+                     zs, inv_scale);
+  RF_HIP(hipGetLastError());
+}
+
+int queue_blocks(int device) {
+  int per_cu = 0, ncu = 0;
+  RF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_recon_f16_queue, 256, 0));
+  RF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  return std::max(1, per_cu) * std::max(1, ncu);
+}
+
+void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
+                  const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
+                  const __half* b16, const float* colscale, const int32_t* slot_kernel,
+                  const float* zinv_all, const PeakOut& po) {
+  fill_u32(ctx, counter, 0u, 1);
+  hipLaunchKernelGGL(k_recon_f16_queue, dim3(unsigned(nblocks)), dim3(256), 0, ctx->stream, zs_all, n,
+                     nref, tiles, items, nitems, counter, b16, colscale, slot_kernel, zinv_all, po);
   RF_HIP(hipGetLastError());
 }
 

@@ -85,15 +85,19 @@ double tf2_t(const Tf2Coef& c, double f);      // t(f)  = Psi'(f) / (2 pi)
 // ------------------------------------------------------------------ launchers
 // Inverse (exp +) unnormalised complex DFT of `batch` contiguous series of n
 // points, in -> out (out may not alias in).  Uses ctx workspace slots A/B.
-void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch);
+// wsa/wsb: caller-owned scratch of n * batch elements each (both NULL: the
+// context's growable workspace, which a captured graph must not reference).
+void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch,
+                     float2* wsa = nullptr, float2* wsb = nullptr);
 void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch);
 
 // sum over the band of f^(-7/3) / S(f) -> *moment (device double), FP64, fixed order
 void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment);
 
 // Y[t][j] for the nt templates (FP64 arithmetic, complex64 store), using *moment
+// Y[seg][t][j] for nseg data segments (xf: [nseg][n/2+1]) and nt templates.
 void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
-                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt);
+                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt, int nseg = 1);
 
 // One-sided ratio spectra for nb-point kernels, nk targets (FP64), scaled by c_j / nb.
 struct RatioParam {

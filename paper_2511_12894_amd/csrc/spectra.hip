@@ -2,6 +2,7 @@
 // matched-filter weighting (section II.A), band moment for the template norms,
 // windowed ratio spectra (sections II.B-II.C), and the kernel support scan and
 // tap gather of the truncation (section II.D).
+#include <algorithm>
 #include <cmath>
 
 #include "rf_internal.h"
@@ -136,8 +137,10 @@ __global__ __launch_bounds__(256) void k_mf_spectrum(const double2* __restrict__
                                                      const Tf2Coef* __restrict__ coef,
                                                      const double* __restrict__ moment, float2* Y,
                                                      int64_t n, int64_t jlo, int64_t jhi, double df) {
+  // blockIdx.y: template, blockIdx.z: data segment (spectra of n/2+1 bins each)
   const Tf2Coef c = coef[blockIdx.y];
-  float2* y = Y + int64_t(blockIdx.y) * n;
+  float2* y = Y + (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * n;
+  xf += int64_t(blockIdx.z) * (n / 2 + 1);
   const double nh = c.amp * sqrt(4.0 * df * (*moment));
   const double g = 4.0 * df / nh * c.amp;
   for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
@@ -297,11 +300,12 @@ void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* momen
 }
 
 void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
-                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt) {
+                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt, int nseg) {
   int64_t jlo, jhi;
   band_limits(g, &jlo, &jhi);
   const double df = g->fs / double(g->n);
-  dim3 grid(blocks_for(g->n, 256, 4096), unsigned(nt));
+  dim3 grid(blocks_for(g->n, 256, unsigned(std::max(64, 4096 / (nt * nseg)))), unsigned(nt),
+            unsigned(nseg));
   hipLaunchKernelGGL(k_mf_spectrum, grid, dim3(256), 0, ctx->stream, xf, psd, coef_dev, moment, Y,
                      g->n, jlo, jhi, df);
   RF_HIP(hipGetLastError());

@@ -23,7 +23,8 @@ PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "ratio_kernel_build",
             "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_free", "snr_reconstruct",
-            "snr_peaks")
+            "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
+            "rf_batch_autotune", "rf_batch_run", "rf_batch_free")
 
 
 class RfGrid(ctypes.Structure):
@@ -82,6 +83,14 @@ def load(path: str = LIB_PATH):
     lib.rf_kernels_free.argtypes = [vp]
     lib.snr_reconstruct.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
     lib.snr_peaks.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
+    lib.rf_batch_create.argtypes = [vp, ctypes.POINTER(RfGrid), vp, i32, ctypes.POINTER(RfTmpl),
+                                    ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.rf_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)]
+    lib.rf_batch_set_chunks.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.rf_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p]
+    lib.rf_batch_run.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
+    lib.rf_batch_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "rf_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -250,3 +259,74 @@ def decode_triggers(trig: torch.Tensor, count: int):
     ints = t[:, :3].numpy()
     fl = t[:, 3:].view(torch.float32).numpy()
     return [(int(a), int(b), int(c), float(d), float(e)) for (a, b, c), (d, e) in zip(ints, fl)]
+
+
+class Batch:
+    """rf_batch: nseg segments x len(refs) reference groups with their kernel
+    sets, run as one captured graph with a persistent reconstruction launch.
+    The context must enqueue on a non-default stream."""
+
+    def __init__(self, ctx: Context, grid, psd: torch.Tensor, refs, ksets, nseg: int):
+        self.ctx = ctx
+        self.nseg = nseg
+        self.nref = len(refs)
+        self.n = int(grid.n)
+        self.psd = psd                       # borrowed by the library: keep alive
+        g = to_grid(grid)
+        handles = (ctypes.c_void_p * len(ksets))(*[k.h.value for k in ksets])
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rf_batch_create(ctx.h, ctypes.byref(g), _ptr(psd), len(refs), _tmpl_array(refs),
+                                          handles, int(nseg), ctypes.byref(h)))
+        self.h = h
+        self.ktotal = self.info()["ktotal"]
+
+    def info(self):
+        kt = ctypes.c_int32()
+        ni = ctypes.c_int64()
+        kb = (ctypes.c_int32 * self.nref)()
+        ch = (ctypes.c_int32 * 3)()
+        st = self.ctx.lib.rf_batch_info(self.h, ctypes.byref(kt), ctypes.byref(ni), kb, ch)
+        self.ctx.check(st)
+        return dict(ktotal=kt.value, nitems=ni.value, kbase=list(kb), chunks=list(ch))
+
+    def set_chunks(self, chunks):
+        arr = (ctypes.c_int32 * 3)(*chunks)
+        st = self.ctx.lib.rf_batch_set_chunks(self.h, arr)
+        if st != RF_OK:
+            raise RfError(st, "rf_batch_set_chunks failed")
+
+    def _inputs_ready(self, xf_segs):
+        assert xf_segs.dtype == torch.complex128 and xf_segs.is_cuda and xf_segs.is_contiguous()
+        assert xf_segs.shape == (self.nseg, self.n // 2 + 1)
+        self.ctx.stream.wait_stream(torch.cuda.current_stream(xf_segs.device))
+
+    def autotune(self, xf_segs: torch.Tensor, cache_path: str | None = None):
+        self._inputs_ready(xf_segs)
+        self.ctx.check(self.ctx.lib.rf_batch_autotune(self.ctx.h, self.h, _ptr(xf_segs),
+                                                      cache_path.encode() if cache_path else None))
+        return self.info()["chunks"]
+
+    def run(self, xf_segs: torch.Tensor, thr: float, trig_cap: int = 1 << 16, peaks=None, trig=None):
+        self._inputs_ready(xf_segs)
+        dev = xf_segs.device
+        if peaks is None:
+            peaks = torch.empty((self.nseg, self.ktotal, 2), dtype=torch.int32, device=dev)
+        if trig is None:
+            trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=dev)
+        cnt = ctypes.c_int64(0)
+        st = self.ctx.lib.rf_batch_run(self.ctx.h, self.h, _ptr(xf_segs), ctypes.c_float(thr), _ptr(peaks),
+                                       _ptr(trig), int(trig_cap), ctypes.byref(cnt))
+        if st not in (RF_OK, RF_E_OVERFLOW):
+            self.ctx.check(st)
+        return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rf_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
