@@ -343,3 +343,47 @@ def test_lattice_neighbours_are_distinct_and_physical():
     assert len(set(nb)) == 256
     for m1, m2 in nb:
         assert m1 >= m2 > 0
+
+
+# ------------------------------------------------------------------ MLP oracle
+
+def test_mlp_parameter_count():
+    from oracle import mlp
+    assert mlp.n_params() == 165760
+
+
+def test_mlp_gradient_matches_finite_differences():
+    """Central differences on a sample of parameters from every layer."""
+    from oracle import mlp
+    rng = np.random.default_rng(21)
+    theta = rng.standard_normal(mlp.n_params()) * 0.08
+    x = rng.standard_normal((7, 4))
+    t = rng.standard_normal((7, 128)) * 0.3
+    L, g = mlp.grad(theta, x, t)
+    assert L == pytest.approx(mlp.loss(theta, x, t), rel=1e-14)
+    offs = np.cumsum([0] + [i * o + o for i, o in mlp.LAYERS])
+    picks = np.concatenate([rng.integers(a, b, 12) for a, b in zip(offs[:-1], offs[1:])])
+    h = 1e-6
+    for p in picks:
+        e = np.zeros_like(theta)
+        e[p] = h
+        fd = (mlp.loss(theta + e, x, t) - mlp.loss(theta - e, x, t)) / (2 * h)
+        assert g[p] == pytest.approx(fd, rel=1e-5, abs=1e-11)
+
+
+def test_gelu_exact_form():
+    """gelu(u) = u Phi(u): Phi(0) = 1/2, Phi(1) = 0.8413447460685429, odd part identity."""
+    from oracle import mlp
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert mlp.gelu(np.array([1.0]))[0] == pytest.approx(0.8413447460685429, rel=1e-15)
+    u = np.linspace(-4, 4, 17)
+    np.testing.assert_allclose(mlp.gelu(u) - mlp.gelu(-u), u, atol=1e-14)
+
+
+def test_adam_first_step_moves_by_lr():
+    """With bias correction the first Adam step is lr * sign(g) (|g| >> eps)."""
+    from oracle import mlp
+    th = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    new, m, v = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    np.testing.assert_allclose(new, th - 0.01 * np.sign(g), rtol=1e-4)
