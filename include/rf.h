@@ -195,6 +195,70 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
                        rf_trigger* trig, int64_t cap, int64_t* ntrig);
 rf_status rf_batch_free(rf_batch* b);
 
+/* ---- learned kernels: an MLP predicting ratio kernels in an SVD basis ----
+ *
+ * The analytic ratio kernel of a pair, h[m] = (1/nb) sum_{j<=nb/2} c_j R~_j
+ * e^{2 pi i j m/nb} (c_0 = c_{nb/2} = 1, else 2; w = Re h is the exact kernel
+ * of ratio_kernel_build), is taken on the tap window (-window/2, window/2].
+ * A surrogate holds: the leading `rank` left singular vectors U of the
+ * training kernels (randomized range finder, Cholesky-QR applied twice), and an
+ * MLP 4 -> 256 -> 256 -> 256 -> 2 rank (exact GELU) from the standardised
+ * features (tau0_ref, tau3_ref, tau0_k - tau0_ref, tau3_k - tau3_ref) (Newtonian
+ * and 1.5PN chirp times at f_low) to the coefficients U^H h / scale (real parts,
+ * then imaginary parts).  The exact FP64 build provides the training data and
+ * the fallback.  Not part of the paper: an extension for storage and build
+ * time; its error is always judged against the exact kernels. */
+typedef struct rf_surrogate rf_surrogate;
+
+/* Training set: npair pairs (refs[p], nbrs[p]) (host), kernels built exactly
+ * on grid (grid.n = build length), window taps (power of two, <= n), rank = 64.
+ * omega: device double [npair][nomega] standard-normal draws for the range
+ * finder (rank <= nomega <= 256), supplied by the caller.  Synchronises. */
+rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* refs, const rf_tmpl* nbrs,
+                              int32_t npair, int32_t window, int32_t rank, const double* omega,
+                              int32_t nomega, rf_surrogate** out);
+/* Host copies (any may be NULL): window, rank, numerical rank of the training
+ * kernels, their singular values [numerical rank], coefficient scale, steps. */
+rf_status rf_surrogate_info(const rf_surrogate* s, int32_t* window, int32_t* rank, int32_t* numerical_rank,
+                            double* svals, double* out_scale, int64_t* steps_trained);
+/* Parameters: device float [165760], packed W1 [256][4], b1, W2 [256][256], b2,
+ * W3 [256][256], b3, W4 [128][256], b4.  set_params also resets Adam state. */
+rf_status rf_surrogate_set_params(rf_ctx* ctx, rf_surrogate* s, const float* theta);
+rf_status rf_surrogate_get_params(rf_ctx* ctx, const rf_surrogate* s, float* theta);
+/* Loss (mean squared error over rows x 128 outputs) and its gradient for inputs
+ * x (device float [rows][4], standardised) and targets t (device [rows][128]);
+ * grad_out: device float [165760].  Synchronises. */
+rf_status rf_surrogate_grad(rf_ctx* ctx, rf_surrogate* s, const float* x, const float* t, int32_t rows,
+                            float* loss_host, float* grad_out);
+/* Adam (0.9, 0.999, 1e-8; moments and bias correction continue across calls
+ * until set_params) with a cosine learning-rate decay from lr to 0 over this
+ * call's `steps` steps, one captured graph per step, batches of training rows
+ * order[step][0..batch) (device int32, supplied by the caller).  loss_host:
+ * host float [steps] or NULL.  Needs a non-NULL stream.  Synchronises. */
+rf_status rf_surrogate_train(rf_ctx* ctx, rf_surrogate* s, const int32_t* order, int32_t steps, int32_t batch,
+                             float lr, float* loss_host);
+/* Predicted coefficients U^H h of the pairs (ref, nbr[k]): device complex128 [nk][rank]. */
+rf_status rf_surrogate_predict(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                               void* coeffs);
+/* Exact coefficients U^H h of the pairs (ref, nbr[k]) (kernels built exactly on
+ * the training grid): device complex128 [nk][rank].  Synchronises. */
+rf_status rf_surrogate_project(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                               void* coeffs);
+/* Kernel set of the targets nbr[k] of ref from the surrogate: w = Re(U c) on
+ * the window, truncated as ratio_kernel_build truncates, with c the network's
+ * prediction, or coeffs (device complex128 [nk][rank]) when not NULL.  A kernel
+ * whose support reaches the window edge is replaced by the exact one.  With a check segment
+ * (check_grid sharing fs and band, check_xf device complex128 [n_c/2+1],
+ * check_psd device double [n_c/2+1]): each kernel's reconstructed series on it
+ * is compared with direct matched filtering; where max |dz| > tol the exact
+ * FP64 kernel replaces it.  fallback: host int32 [nk] (1 = exact), check_err:
+ * host float [nk] (0 without a check); either may be NULL.  Synchronises. */
+rf_status rf_surrogate_kernels(rf_ctx* ctx, rf_surrogate* s, const rf_grid* grid, const double* psd, rf_tmpl ref,
+                               const rf_tmpl* nbr, int32_t nk, const void* coeffs, double thr, rf_thr_unit unit,
+                               const rf_grid* check_grid, const void* check_xf, const double* check_psd,
+                               double tol, rf_kernels** out, int32_t* fallback, float* check_err);
+rf_status rf_surrogate_free(rf_surrogate* s);
+
 #ifdef __cplusplus
 }
 #endif

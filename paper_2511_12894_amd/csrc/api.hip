@@ -106,6 +106,85 @@ void free_kernels(rf_kernels* k) {
 }
 
 }  // namespace
+
+void free_kernel_set(rf_kernels* k) { free_kernels(k); }
+
+// Tiles, packed operands and device copies of a kernel set whose per-kernel
+// fields (m_lo, len, off, norm_ratio, kscale) and FP64 taps (host, concatenated
+// at off) are filled in.  Synchronises.
+void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& taps_host) {
+  const int32_t nk = K->nk;
+  K->total_taps = int64_t(taps_host.size());
+  K->taps64 = dev_alloc<double>(size_t(K->total_taps));
+  if (K->total_taps)
+    RF_HIP(hipMemcpy(K->taps64, taps_host.data(), sizeof(double) * taps_host.size(), hipMemcpyHostToDevice));
+
+  // tiles: kernels sorted by first tap, 32 per tile, union support per tile
+  std::vector<int32_t> order(nk);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return K->m_lo[a] < K->m_lo[b]; });
+  const int ntiles = (nk + kTileKernels - 1) / kTileKernels;
+  std::vector<int32_t> slot(size_t(ntiles) * kTileKernels, -1);
+  std::vector<float> cs32(slot.size(), 0.f), cs16(slot.size(), 0.f);
+  int64_t b32_total = 0, b16_total = 0;
+  K->tiles.clear();
+  K->max_ksteps = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    TileDev T{};
+    T.first = t * kTileKernels;
+    T.count = std::min(kTileKernels, nk - t * kTileKernels);
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int i = 0; i < T.count; ++i) {
+      const int k = order[T.first + i];
+      slot[T.first + i] = k;
+      cs32[T.first + i] = float(K->norm_ratio[k]);
+      cs16[T.first + i] = float(K->norm_ratio[k] / K->kscale[k]);
+      if (K->len[k] > 0) {
+        lo = std::min(lo, K->m_lo[k]);
+        hi = std::max(hi, K->m_lo[k] + K->len[k]);
+      }
+    }
+    if (lo == INT64_MAX) {
+      T.m0 = 0;
+      T.ksteps = 0;
+    } else {
+      T.m0 = lo;
+      T.ksteps = ((hi - lo + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
+    }
+    T.b32_off = b32_total;
+    T.b16_off = b16_total;
+    b32_total += T.ksteps * kB32PerStep;
+    b16_total += T.ksteps * kB16PerStep;
+    K->max_ksteps = std::max(K->max_ksteps, T.ksteps);
+    K->tiles.push_back(T);
+  }
+  K->tiles_dev = dev_alloc<TileDev>(K->tiles.size());
+  K->slot_kernel = dev_alloc<int32_t>(slot.size());
+  K->colscale32 = dev_alloc<float>(slot.size());
+  K->colscale16 = dev_alloc<float>(slot.size());
+  K->b32 = dev_alloc<float>(size_t(b32_total));
+  K->b16 = dev_alloc<__half>(size_t(b16_total));
+  RF_HIP(hipMemcpy(K->tiles_dev, K->tiles.data(), sizeof(TileDev) * K->tiles.size(), hipMemcpyHostToDevice));
+  RF_HIP(hipMemcpy(K->slot_kernel, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
+  RF_HIP(hipMemcpy(K->colscale32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
+  RF_HIP(hipMemcpy(K->colscale16, cs16.data(), sizeof(float) * cs16.size(), hipMemcpyHostToDevice));
+  if (K->max_ksteps > 0) {
+    int64_t* off_d = dev_alloc<int64_t>(size_t(nk) * 2);
+    int64_t* mlo_d = off_d + nk;
+    int32_t* len_d = dev_alloc<int32_t>(size_t(nk));
+    double* ks_d = dev_alloc<double>(size_t(nk));
+    RF_HIP(hipMemcpy(off_d, K->off.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(mlo_d, K->m_lo.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(len_d, K->len.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice));
+    RF_HIP(hipMemcpy(ks_d, K->kscale.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+    pack_launch(ctx, K, off_d, mlo_d, len_d, ks_d, K->tiles_dev, ntiles, K->max_ksteps);
+    sync(ctx);
+    (void)hipFree(off_d);
+    (void)hipFree(len_d);
+    (void)hipFree(ks_d);
+  }
+}
+
 }  // namespace rf
 
 using namespace rf;
@@ -298,75 +377,7 @@ rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd
       for (int i = 0; i < cnt; ++i) K->off[k0 + i] = base + offc[i];
       taps_host.insert(taps_host.end(), chunk_taps.begin(), chunk_taps.begin() + tot);
     }
-    K->total_taps = int64_t(taps_host.size());
-    K->taps64 = dev_alloc<double>(size_t(K->total_taps));
-    if (K->total_taps)
-      RF_HIP(hipMemcpy(K->taps64, taps_host.data(), sizeof(double) * taps_host.size(), hipMemcpyHostToDevice));
-
-    // tiles: kernels sorted by first tap, 128 per tile, union support per tile
-    std::vector<int32_t> order(nk);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return K->m_lo[a] < K->m_lo[b]; });
-    const int ntiles = (nk + kTileKernels - 1) / kTileKernels;
-    std::vector<int32_t> slot(size_t(ntiles) * kTileKernels, -1);
-    std::vector<float> cs32(slot.size(), 0.f), cs16(slot.size(), 0.f);
-    int64_t b32_total = 0, b16_total = 0;
-    K->tiles.clear();
-    K->max_ksteps = 0;
-    for (int t = 0; t < ntiles; ++t) {
-      TileDev T{};
-      T.first = t * kTileKernels;
-      T.count = std::min(kTileKernels, nk - t * kTileKernels);
-      int64_t lo = INT64_MAX, hi = INT64_MIN;
-      for (int i = 0; i < T.count; ++i) {
-        const int k = order[T.first + i];
-        slot[T.first + i] = k;
-        cs32[T.first + i] = float(K->norm_ratio[k]);
-        cs16[T.first + i] = float(K->norm_ratio[k] / K->kscale[k]);
-        if (K->len[k] > 0) {
-          lo = std::min(lo, K->m_lo[k]);
-          hi = std::max(hi, K->m_lo[k] + K->len[k]);
-        }
-      }
-      if (lo == INT64_MAX) {
-        T.m0 = 0;
-        T.ksteps = 0;
-      } else {
-        T.m0 = lo;
-        T.ksteps = ((hi - lo + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
-      }
-      T.b32_off = b32_total;
-      T.b16_off = b16_total;
-      b32_total += T.ksteps * kB32PerStep;
-      b16_total += T.ksteps * kB16PerStep;
-      K->max_ksteps = std::max(K->max_ksteps, T.ksteps);
-      K->tiles.push_back(T);
-    }
-    K->tiles_dev = dev_alloc<TileDev>(K->tiles.size());
-    K->slot_kernel = dev_alloc<int32_t>(slot.size());
-    K->colscale32 = dev_alloc<float>(slot.size());
-    K->colscale16 = dev_alloc<float>(slot.size());
-    K->b32 = dev_alloc<float>(size_t(b32_total));
-    K->b16 = dev_alloc<__half>(size_t(b16_total));
-    RF_HIP(hipMemcpy(K->tiles_dev, K->tiles.data(), sizeof(TileDev) * K->tiles.size(), hipMemcpyHostToDevice));
-    RF_HIP(hipMemcpy(K->slot_kernel, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
-    RF_HIP(hipMemcpy(K->colscale32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
-    RF_HIP(hipMemcpy(K->colscale16, cs16.data(), sizeof(float) * cs16.size(), hipMemcpyHostToDevice));
-    if (K->max_ksteps > 0) {
-      int64_t* off_d = dev_alloc<int64_t>(size_t(nk) * 2);
-      int64_t* mlo_d = off_d + nk;
-      int32_t* len_d = dev_alloc<int32_t>(size_t(nk));
-      double* ks_d = dev_alloc<double>(size_t(nk));
-      RF_HIP(hipMemcpy(off_d, K->off.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
-      RF_HIP(hipMemcpy(mlo_d, K->m_lo.data(), sizeof(int64_t) * nk, hipMemcpyHostToDevice));
-      RF_HIP(hipMemcpy(len_d, K->len.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice));
-      RF_HIP(hipMemcpy(ks_d, K->kscale.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
-      pack_launch(ctx, K, off_d, mlo_d, len_d, ks_d, K->tiles_dev, ntiles, K->max_ksteps);
-      sync(ctx);
-      (void)hipFree(off_d);
-      (void)hipFree(len_d);
-      (void)hipFree(ks_d);
-    }
+    finalize_kernel_set(ctx, K, taps_host);
     *out = K;
   });
   if (st != RF_OK && K) {

@@ -120,6 +120,12 @@ void fill_u64(rf_ctx* ctx, uint64_t* p, uint64_t v, int64_t n);
 void fill_u32(rf_ctx* ctx, uint32_t* p, uint32_t v, int64_t n);
 
 }  // namespace rf
+struct rf_kernels;
+namespace rf {
+void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& taps_host);
+void free_kernel_set(rf_kernels* k);
+
+}  // namespace rf
 
 // ------------------------------------------------------------------ kernel set
 namespace rf {
@@ -146,7 +152,7 @@ struct rf_kernels {
   std::vector<double> kscale;        // power-of-two FP16 scale s_k
   double* taps64 = nullptr;          // device, concatenated FP64 taps
   int64_t total_taps = 0;
-  // reconstruction tiles (kernels sorted by support, 128 per tile)
+  // reconstruction tiles (kernels sorted by first tap, 32 per tile)
   std::vector<rf::TileDev> tiles;
   int64_t max_ksteps = 0;
   rf::TileDev* tiles_dev = nullptr;

@@ -24,7 +24,11 @@ PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "ratio_kernel_build",
             "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_free", "snr_reconstruct",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
-            "rf_batch_autotune", "rf_batch_run", "rf_batch_free")
+            "rf_batch_autotune", "rf_batch_run", "rf_batch_free", "rf_surrogate_create",
+            "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
+            "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
+            "rf_surrogate_kernels",
+            "rf_surrogate_free")
 
 
 class RfGrid(ctypes.Structure):
@@ -91,6 +95,20 @@ def load(path: str = LIB_PATH):
     lib.rf_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p]
     lib.rf_batch_run.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
     lib.rf_batch_free.argtypes = [vp]
+    lib.rf_surrogate_create.argtypes = [vp, ctypes.POINTER(RfGrid), ctypes.POINTER(RfTmpl), ctypes.POINTER(RfTmpl),
+                                        i32, i32, i32, vp, i32, ctypes.POINTER(vp)]
+    lib.rf_surrogate_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.rf_surrogate_set_params.argtypes = [vp, vp, vp]
+    lib.rf_surrogate_get_params.argtypes = [vp, vp, vp]
+    lib.rf_surrogate_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
+    lib.rf_surrogate_train.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
+    lib.rf_surrogate_predict.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, vp]
+    lib.rf_surrogate_project.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, vp]
+    lib.rf_surrogate_kernels.argtypes = [vp, vp, ctypes.POINTER(RfGrid), vp, RfTmpl, ctypes.POINTER(RfTmpl), i32,
+                                         vp, dbl, ctypes.c_int, ctypes.POINTER(RfGrid), vp, vp, dbl,
+                                         ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+    lib.rf_surrogate_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "rf_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -323,6 +341,105 @@ class Batch:
     def free(self):
         if getattr(self, "h", None):
             self.ctx.lib.rf_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+N_MLP_PARAMS = 165760
+
+
+class Surrogate:
+    """rf_surrogate: SVD basis of exact analytic kernels + MLP (trained on the
+    GPU by the library's own kernels).  The context must use a non-default
+    stream for training (graph capture)."""
+
+    def __init__(self, ctx: Context, grid, refs, nbrs, window: int, omega: torch.Tensor, rank: int = 64):
+        self.ctx = ctx
+        self.grid = grid
+        assert omega.dtype == torch.float64 and omega.is_cuda and omega.is_contiguous()
+        assert omega.shape[0] == len(refs) == len(nbrs)
+        g = to_grid(grid)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        ctx.check(ctx.lib.rf_surrogate_create(ctx.h, ctypes.byref(g), _tmpl_array(refs), _tmpl_array(nbrs),
+                                              len(refs), int(window), int(rank), _ptr(omega), int(omega.shape[1]),
+                                              ctypes.byref(h)))
+        self.h = h
+        self.rank = rank
+
+    def info(self):
+        w, r, kr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        sc, st = ctypes.c_double(), ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.rf_surrogate_info(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(kr),
+                                                      None, ctypes.byref(sc), ctypes.byref(st)))
+        sv = (ctypes.c_double * max(kr.value, 1))()
+        self.ctx.check(self.ctx.lib.rf_surrogate_info(self.h, None, None, None, sv, None, None))
+        return dict(window=w.value, rank=r.value, numerical_rank=kr.value, svals=list(sv)[:kr.value],
+                    out_scale=sc.value, steps=st.value)
+
+    def set_params(self, theta: torch.Tensor):
+        assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == N_MLP_PARAMS
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_set_params(self.ctx.h, self.h, _ptr(theta)))
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(N_MLP_PARAMS, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_get_params(self.ctx.h, self.h, _ptr(out)))
+        return out
+
+    def grad(self, x: torch.Tensor, t: torch.Tensor):
+        rows = x.shape[0]
+        g = torch.empty(N_MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_grad(self.ctx.h, self.h, _ptr(x), _ptr(t), rows,
+                                                      ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train(self, order: torch.Tensor, lr: float):
+        steps, batch = order.shape
+        hist = (ctypes.c_float * steps)()
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_train(self.ctx.h, self.h, _ptr(order), steps, batch, float(lr), hist))
+        return list(hist)
+
+    def predict(self, ref, nbrs):
+        c = torch.empty((len(nbrs), self.rank), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        self.ctx.check(self.ctx.lib.rf_surrogate_predict(self.ctx.h, self.h, RfTmpl(*map(float, ref)),
+                                                         _tmpl_array(nbrs), len(nbrs), _ptr(c)))
+        return c
+
+    def project(self, ref, nbrs):
+        c = torch.empty((len(nbrs), self.rank), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        self.ctx.check(self.ctx.lib.rf_surrogate_project(self.ctx.h, self.h, RfTmpl(*map(float, ref)),
+                                                         _tmpl_array(nbrs), len(nbrs), _ptr(c)))
+        return c
+
+    def kernels(self, grid, psd, ref, nbrs, coeffs=None, thr=1e-3, unit=RF_THR_PER_SECOND, check=None, tol=2e-4):
+        """Kernel set from the surrogate (network coefficients unless `coeffs`);
+        check = (grid, xf, psd) of a check segment."""
+        nk = len(nbrs)
+        g = to_grid(grid)
+        fb = (ctypes.c_int32 * nk)()
+        err = (ctypes.c_float * nk)()
+        h = ctypes.c_void_p()
+        cg = to_grid(check[0]) if check else None
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_kernels(
+            self.ctx.h, self.h, ctypes.byref(g), _ptr(psd), RfTmpl(*map(float, ref)), _tmpl_array(nbrs), nk,
+            _ptr(coeffs) if coeffs is not None else None, float(thr), int(unit), ctypes.byref(cg) if check else None, _ptr(check[1]) if check else None,
+            _ptr(check[2]) if check else None, float(tol), ctypes.byref(h), fb, err))
+        return Kernels(self.ctx, h, nk), list(fb), list(err)
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rf_surrogate_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -307,3 +307,41 @@ def workload_batched(n_seg: int = 8, n_ref: int = 64, duration: float = 256.0,
         injections.append((s, m1, m2, 10.0, t0, phi))
     return dict(name=f"batched-{n_seg}seg-{duration:g}s-{n_ref}ref", grid=grid, psd=psd,
                 segments=segs, refs=refs, groups=groups, injections=injections)
+
+
+# ------------------------------------------------------- learned-kernel inputs
+
+def surrogate_pairs(f0: float, count: int, seed: int, m_range=(1.0, 3.0), steps: int = 10):
+    """Training pairs: references with m1, m2 ~ U[m_range] (m1 >= m2) and a
+    neighbour at a random offset of at most `steps` lattice steps in each
+    chirp-time direction (the lattice of neighbour_lattice)."""
+    rng = np.random.default_rng(seed)
+    refs, nbrs = [], []
+    while len(refs) < count:
+        a, b = rng.uniform(*m_range, size=2)
+        ref = (float(max(a, b)), float(min(a, b)))
+        t0r, t3r = chirp_times(*ref, f0)
+        i, j = rng.integers(-steps, steps + 1, size=2)
+        ms = masses_from_chirp_times(t0r + i * 5.0 / 3.0 * _DMC_REL * t0r, t3r + j * 3.0 / 5.0 * _DETA_REL * t3r, f0)
+        if ms is None:
+            continue
+        refs.append(ref)
+        nbrs.append(ms)
+    return refs, nbrs
+
+
+def surrogate_random_inputs(seed: int, npair: int, nomega: int, steps: int, batch: int):
+    """Random numbers the surrogate's construction and training draw: standard
+    normal range-finder draws [npair][nomega], initial parameters (weights
+    N(0, 2/fan_in), zero biases, packed W1 b1 W2 b2 W3 b3 W4 b4) and the batch
+    order (shuffled epochs) [steps][batch]."""
+    rng = np.random.default_rng(seed)
+    omega = rng.standard_normal((npair, nomega))
+    parts = []
+    for fi, fo in ((4, 256), (256, 256), (256, 256), (256, 128)):
+        parts.append((rng.standard_normal((fo, fi)) * np.sqrt(2.0 / fi)).ravel())
+        parts.append(np.zeros(fo))
+    theta = np.concatenate(parts).astype(np.float32)
+    need = steps * batch
+    order = np.concatenate([rng.permutation(npair) for _ in range(need // npair + 1)])[:need]
+    return omega, theta, order.reshape(steps, batch).astype(np.int32)

@@ -1,0 +1,239 @@
+"""Learned ratio kernels on the GPU: the MLP's gradients against the FP64 oracle,
+the SVD basis against exact kernels, training, and the check-segment fallback
+to the exact FP64 build."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mf as omf
+from oracle import mlp as omlp
+from oracle import ratio as orat
+from paper_2511_12894_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NPAIR = 2048
+WINDOW = 8192
+NOMEGA = 128
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_12894_amd import rf as rfmod
+    rfmod.load()
+    return rfmod
+
+
+@pytest.fixture(scope="module")
+def st(rf):
+    """Surrogate trained on pairs at 1024 Hz, f_low = 30 Hz (kernels built at
+    n = 2^15), a held-out reference with 24 lattice neighbours, and a 32 s
+    check segment with an injection."""
+    stream = torch.cuda.Stream()
+    ctx = rf.Context(0, stream)
+    gb = synth.make_grid(1024.0, 1 << 15, 30.0)
+    refs, nbrs = synth.surrogate_pairs(gb.f_low, NPAIR, seed=6001)
+    omega, theta, _ = synth.surrogate_random_inputs(6002, NPAIR, NOMEGA, 1, 256)
+    gs = synth.make_grid(1024.0, 1 << 15, 30.0)
+    psd = synth.make_psd(gs)
+    ref = (1.5, 1.3)
+    nb = synth.neighbour_lattice(*ref, gs.f_low, 24)
+    xf = synth.noise(gs, psd, seed=6003)
+    xf = synth.inject(gs, psd, xf, *nb[5], 14.0, 12.0, 0.7)
+    _say("learned: creating surrogate")
+    with torch.cuda.stream(stream):
+        S = rf.Surrogate(ctx, gb, refs, nbrs, WINDOW, torch.from_numpy(omega).cuda(), rank=64)
+        out = dict(ctx=ctx, stream=stream, S=S, gb=gb, gs=gs, psd=psd, psd_d=torch.from_numpy(psd).cuda(),
+                   xf=xf, xf_d=torch.from_numpy(xf).cuda(), ref=ref, nb=nb, theta0=theta)
+        yield out
+    torch.cuda.synchronize()
+    S.free()
+    ctx.close()
+
+
+@pytest.mark.parametrize("rows", [37, 300])
+def test_gradient_matches_oracle(rf, st, rows):
+    """GPU forward/backward (FP32) against the FP64 oracle at the same point."""
+    S = st["S"]
+    rng = np.random.default_rng(100 + rows)
+    x = rng.standard_normal((rows, 4)).astype(np.float32)
+    t = (0.3 * rng.standard_normal((rows, 128))).astype(np.float32)
+    th = st["theta0"]
+    with torch.cuda.stream(st["stream"]):
+        S.set_params(torch.from_numpy(th).cuda())
+        loss, g = S.grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    l_ref, g_ref = omlp.grad(th.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    assert abs(loss - l_ref) <= 1e-5 * l_ref
+    scale = np.abs(g_ref).max()
+    err = np.abs(g - g_ref).max() / scale
+    _say(f"rows {rows}: loss {loss:.6f} vs {l_ref:.6f}, max |dg| / max |g| = {err:.2e}")
+    assert err <= 1e-5
+    # per layer, relative to that layer's own gradient scale
+    k = 0
+    for fi, fo in omlp.LAYERS:
+        for size in (fi * fo, fo):
+            seg = slice(k, k + size)
+            assert np.abs(g[seg] - g_ref[seg]).max() <= 1e-4 * np.abs(g_ref[seg]).max() + 1e-12
+            k += size
+
+
+def test_basis_spectrum(rf, st):
+    inf = st["S"].info()
+    sv = np.array(inf["svals"])
+    assert inf["window"] == WINDOW and inf["rank"] == 64
+    assert 8 <= inf["numerical_rank"] <= NOMEGA
+    assert np.all(np.diff(sv) <= 1e-12 * sv[0])           # descending
+    assert sv[min(63, len(sv) - 1)] <= 1e-5 * sv[0]          # rank 64 captures the bank
+
+
+def test_projected_kernels_reproduce_exact(rf, st):
+    """w = Re(U U^H h) of held-out pairs against the exact FP64 build and the oracle."""
+    S, ctx = st["S"], st["ctx"]
+    with torch.cuda.stream(st["stream"]):
+        c = S.project(st["ref"], st["nb"])
+        KP, fb, _ = S.kernels(st["gs"], st["psd_d"], st["ref"], st["nb"], coeffs=c)
+        KE = rf.ratio_kernel_build(ctx, st["gs"], st["psd_d"], st["ref"], st["nb"])
+    assert sum(fb) == 0
+    ip, ie = KP.info(), KE.info()
+    worst = 0.0
+    for k in range(len(st["nb"])):
+        a, b = KE.taps(k), KP.taps(k)
+        lo = min(ie["m_lo"][k], ip["m_lo"][k])
+        hi = max(ie["m_lo"][k] + len(a), ip["m_lo"][k] + len(b))
+        A = np.zeros(hi - lo)
+        B = np.zeros(hi - lo)
+        A[ie["m_lo"][k] - lo:ie["m_lo"][k] - lo + len(a)] = a
+        B[ip["m_lo"][k] - lo:ip["m_lo"][k] - lo + len(b)] = b
+        worst = max(worst, np.abs(A - B).max() / np.abs(A).max())
+        assert abs(ip["m_lo"][k] - ie["m_lo"][k]) <= 2 and abs(len(a) - len(b)) <= 4
+        np.testing.assert_allclose(ip["norm_ratio"][k], ie["norm_ratio"][k], rtol=1e-14)
+    _say(f"projected vs exact taps: max |dw| / max |w| = {worst:.2e}")
+    assert worst <= 1e-6
+    # the oracle's kernel of one neighbour
+    kb = orat.build_kernel(st["gs"], st["ref"], st["nb"][7])
+    b = KP.taps(7)
+    m0 = ip["m_lo"][7]
+    full = kb["full"]
+    ref_taps = full[np.arange(m0, m0 + len(b)) % len(full)]
+    assert np.abs(b - ref_taps).max() <= 1e-6 * np.abs(full).max()
+    KP.free()
+    KE.free()
+
+
+def _train(rf, st, steps, lr, seed=6100):
+    _, _, order = synth.surrogate_random_inputs(seed, NPAIR, NOMEGA, steps, 256)
+    with torch.cuda.stream(st["stream"]):
+        st["S"].set_params(torch.from_numpy(st["theta0"]).cuda())
+        hist = st["S"].train(torch.from_numpy(order).cuda(), lr)
+    return np.array(hist)
+
+
+def test_training_is_deterministic_and_learns(rf, st):
+    S = st["S"]
+    with torch.cuda.stream(st["stream"]):
+        S.set_params(torch.from_numpy(st["theta0"]).cuda())
+        c_exact = S.project(st["ref"], st["nb"])
+        c_untrained = S.predict(st["ref"], st["nb"])
+    h1 = _train(rf, st, 1500, 3e-3)
+    p1 = S.get_params().cpu().numpy()
+    assert S.info()["steps"] == 1500
+    h2 = _train(rf, st, 1500, 3e-3)             # replay of the captured graph
+    p2 = S.get_params().cpu().numpy()
+    np.testing.assert_array_equal(h1, h2)
+    np.testing.assert_array_equal(p1, p2)
+    _say(f"loss {h1[0]:.3e} -> {h1[-100:].mean():.3e}")
+    assert h1[-100:].mean() < h1[0] / 100
+    with torch.cuda.stream(st["stream"]):
+        c_trained = S.predict(st["ref"], st["nb"])
+    e0 = torch.linalg.norm(c_untrained - c_exact).item()
+    e1 = torch.linalg.norm(c_trained - c_exact).item()
+    _say(f"coefficient error untrained {e0:.3e} trained {e1:.3e}")
+    assert e1 < e0 / 10
+
+
+def test_network_kernels_with_check_fallback(rf, st):
+    """Every kernel either passes the check segment at 2e-4 or is the exact one;
+    the final set reconstructs the segment within 2e-4 of direct matched filtering."""
+    S, ctx = st["S"], st["ctx"]
+    _train(rf, st, 1500, 3e-3)
+    gs = st["gs"]
+    chk = (gs, st["xf_d"], st["psd_d"])
+    with torch.cuda.stream(st["stream"]):
+        K, fb, err = S.kernels(gs, st["psd_d"], st["ref"], st["nb"], check=chk, tol=2e-4)
+        zr, _ = rf.mf_ref_snr(ctx, gs, st["xf_d"], st["psd_d"], [st["ref"]])
+        out = rf.snr_reconstruct(ctx, K, zr[0].contiguous(), prec="split16")
+        zd, _ = rf.mf_ref_snr(ctx, gs, st["xf_d"], st["psd_d"], st["nb"])
+    torch.cuda.synchronize()
+    _say(f"fallback {sum(fb)}/{len(fb)}, check errors median {np.median(err):.2e} max {np.max(err):.2e}")
+    for k in range(len(fb)):
+        assert fb[k] == 1 or err[k] <= 2e-4
+    dz = (out["z"] - zd).abs().amax(dim=1).cpu().numpy()
+    assert dz.max() <= 2e-4
+    K.free()
+
+
+def test_forced_fallback_equals_exact_build(rf, st):
+    """tol = 0: every kernel is replaced; the set is the exact build, bit for bit."""
+    S, ctx = st["S"], st["ctx"]
+    gs = st["gs"]
+    with torch.cuda.stream(st["stream"]):
+        K, fb, _ = S.kernels(gs, st["psd_d"], st["ref"], st["nb"], check=(gs, st["xf_d"], st["psd_d"]), tol=0.0)
+        KE = rf.ratio_kernel_build(ctx, gs, st["psd_d"], st["ref"], st["nb"])
+        zr, _ = rf.mf_ref_snr(ctx, gs, st["xf_d"], st["psd_d"], [st["ref"]])
+        a = rf.snr_reconstruct(ctx, K, zr[0].contiguous(), prec="split16")["z"]
+        b = rf.snr_reconstruct(ctx, KE, zr[0].contiguous(), prec="split16")["z"]
+    torch.cuda.synchronize()
+    assert all(fb)
+    assert K.info() == KE.info()
+    for k in (0, 11, 23):
+        np.testing.assert_array_equal(K.taps(k), KE.taps(k))
+    assert torch.equal(a, b)
+    K.free()
+    KE.free()
+
+
+def test_coefficient_storage_gain(rf, st):
+    """The SVD-coefficient form keeps the exact-kernel accuracy (no fallback at
+    2e-4 on the check segment) with 64 complex coefficients per kernel instead
+    of its taps."""
+    S, ctx = st["S"], st["ctx"]
+    gs = st["gs"]
+    with torch.cuda.stream(st["stream"]):
+        c = S.project(st["ref"], st["nb"])
+        K, fb, err = S.kernels(gs, st["psd_d"], st["ref"], st["nb"], coeffs=c,
+                               check=(gs, st["xf_d"], st["psd_d"]), tol=2e-4)
+    assert sum(fb) == 0 and max(err) <= 2e-4
+    taps = sum(K.info()["len"])
+    coef_bytes = 64 * 16 * len(st["nb"])
+    _say(f"taps {taps} ({4 * taps} B as FP32) vs coefficients {coef_bytes} B: {4 * taps / coef_bytes:.1f}x")
+    assert 4 * taps >= 8 * coef_bytes
+    K.free()
+
+
+def test_surrogate_argument_errors(rf, st):
+    S, ctx = st["S"], st["ctx"]
+    g_other = synth.make_grid(1024.0, 1 << 15, 25.0)
+    psd = torch.from_numpy(synth.make_psd(g_other)).cuda()
+    with torch.cuda.stream(st["stream"]):
+        with pytest.raises(rf.RfError) as e:
+            S.kernels(g_other, psd, st["ref"], st["nb"])
+        assert e.value.code == rf.RF_E_INVAL
+        small = synth.make_grid(1024.0, 4096, 30.0)
+        with pytest.raises(rf.RfError) as e:
+            S.kernels(small, torch.from_numpy(synth.make_psd(small)).cuda(), st["ref"], st["nb"])
+        assert e.value.code == rf.RF_E_INVAL
+        om = torch.zeros((4, NOMEGA), dtype=torch.float64, device="cuda")
+        with pytest.raises(rf.RfError) as e:
+            rf.Surrogate(ctx, st["gb"], [(1.4, 1.3)] * 4, [(1.41, 1.3)] * 4, WINDOW, om)
+        assert e.value.code == rf.RF_E_INVAL
