@@ -159,6 +159,108 @@ def batched_leg(dev):
     return res
 
 
+def learned_leg(dev, w, psd, xf, K_exact, build_s, steps):
+    stream = torch.cuda.Stream(dev)          # training replays a captured graph: not the null stream
+    ctx = rf.Context(0, stream)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        res = _learned(dev, ctx, stream, w, psd, xf, K_exact, build_s, steps)
+    torch.cuda.synchronize()
+    ctx.close()
+    return res
+
+
+def _learned(dev, ctx, stream, w, psd, xf, K_exact, build_s, steps):
+    """Learned kernels (C4 shape): a surrogate trained on 20 000 exact kernels of
+    random pairs (1-3 Msun, neighbours within 10 lattice steps) built at 4096 Hz,
+    f_low = 20 Hz, n = 2^17, on a 32768-tap window; then the realistic
+    workload's 256 kernels from the network and from projected SVD
+    coefficients, each checked on a 64 s noise segment (fallback to the exact
+    FP64 kernel above 2e-4), with SNR error against direct matched filtering,
+    storage, build time and the reconstruction rate with the final set."""
+    g = w["grid"]
+    nbrs = w["nbrs"]
+    n = g.n
+    gb = synth.make_grid(g.fs, 1 << 17, g.f_low)
+    npair, nomega, window, batch, lr, tsteps = 20000, 128, 32768, 256, 3e-3, 10000
+    refs, pn = synth.surrogate_pairs(gb.f_low, npair, seed=4001)
+    omega, theta, order = synth.surrogate_random_inputs(4002, npair, nomega, tsteps, batch)
+    om = torch.from_numpy(omega).to(dev)
+    od = torch.from_numpy(order).to(dev)
+    th = torch.from_numpy(theta).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = rf.Surrogate(ctx, gb, refs, pn, window, om, rank=64)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    S.set_params(th)
+    t0 = time.perf_counter()
+    hist = S.train(od, lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    inf = S.info()
+    gc = synth.make_grid(g.fs, 1 << 18, g.f_low)
+    psdc = synth.make_psd(gc)
+    chk = (gc, torch.from_numpy(synth.noise(gc, psdc, seed=4100)).to(dev), torch.from_numpy(psdc).to(dev))
+    zref = torch.empty((1, n), dtype=torch.complex64, device=dev)
+    rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
+    zd, _ = rf.mf_ref_snr(ctx, g, xf, psd, nbrs, want_sigma=False)
+    zo = torch.empty((len(nbrs), n), dtype=torch.complex64, device=dev)
+
+    def err_vs_direct(K):
+        rf.snr_reconstruct(ctx, K, zref[0], prec="split16", z_out=zo)
+        return (zo - zd).abs().amax(dim=1).cpu().numpy()
+
+    res = dict(training_pairs=npair, window_taps=window, basis_rank=64, numerical_rank=inf["numerical_rank"],
+               create_s=t_create, train_steps=tsteps, train_batch=batch, train_lr=lr, train_s=t_train,
+               train_ms_per_step=t_train / tsteps * 1e3, loss_first=float(hist[0]),
+               loss_last100=float(np.mean(hist[-100:])))
+    # network coefficients
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    KN, fb, cerr = S.kernels(g, psd, w["ref"], nbrs, check=chk, tol=2e-4)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    cp = S.project(w["ref"], nbrs)
+    cn = S.predict(w["ref"], nbrs)
+    crel = (torch.linalg.norm(cn - cp, dim=1) / torch.linalg.norm(cp, dim=1)).cpu().numpy()
+    e_net = err_vs_direct(KN)
+    # projected SVD coefficients
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cp = S.project(w["ref"], nbrs)
+    KP, fbp, cerrp = S.kernels(g, psd, w["ref"], nbrs, coeffs=cp, check=chk, tol=2e-4)
+    torch.cuda.synchronize()
+    t_proj = time.perf_counter() - t0
+    e_proj = err_vs_direct(KP)
+    # reconstruction rate with the network's final set (ref MF + split-FP16 + fused peaks)
+    def step():
+        rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
+        rf.snr_reconstruct(ctx, KN, zref[0], prec="split16", z_out=zo, fused_thr=6.0, trig_cap=1 << 16)
+
+    wall, _ = timed(step, max(2, steps // 2), 1, stream)
+    ms = wall / max(2, steps // 2)
+    sum_exact = int(sum(K_exact.info()["len"]))
+    res.update(
+        network=dict(build_with_check_s=t_net, fallback=int(sum(fb)), fallback_frac=sum(fb) / len(nbrs),
+                     check_err_median=float(np.median(cerr)), check_err_max=float(np.max(cerr)),
+                     coef_rel_err_median=float(np.median(crel)), coef_rel_err_max=float(np.max(crel)),
+                     snr_err_vs_direct_final=float(e_net.max())),
+        svd_coefficients=dict(build_with_check_s=t_proj, fallback=int(sum(fbp)),
+                              check_err_max=float(np.max(cerrp)), snr_err_vs_direct=float(e_proj.max())),
+        exact=dict(build_s=build_s, snr_err_vs_direct=float(err_vs_direct(K_exact).max())),
+        storage_bytes=dict(exact_taps_fp32=4 * sum_exact, exact_taps_fp64=8 * sum_exact,
+                           svd_coefficients=16 * 64 * len(nbrs), basis_fp64=16 * 64 * window,
+                           network_params=4 * rf.N_MLP_PARAMS,
+                           bank_exact_fp32_est=4 * npair * sum_exact // len(nbrs)),
+        learned_split16_step_ms=ms, learned_split16_value=(1 + len(nbrs)) * n / (ms * 1e-3))
+    KN.free()
+    KP.free()
+    S.free()
+    del zd, zo
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,7 +268,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nbrs", type=int, default=24)
-    ap.add_argument("--only", default="", help="comma list of legs to run (profiling): step,fp32,direct,build")
+    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,batched,learned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -174,7 +276,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "build", "batched"}
+    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "batched", "learned"}
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -259,7 +361,11 @@ def main():
         res["err_vs_direct"] = dict(split16=e16, fp32=e32)
         del zall
     if "batched" in legs:
+        log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
+    if "learned" in legs:
+        log("bench: learned kernels (training, inference, check and fallback)")
+        res["learned"] = learned_leg(dev, w, psd, xf, K, build_s, args.steps)
     torch.cuda.synchronize()
 
     out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -301,6 +407,8 @@ def main():
         extra["err_vs_direct_mf"] = res["err_vs_direct"]
     if "batched" in res:
         extra["batched"] = res["batched"]
+    if "learned" in res:
+        extra["learned"] = res["learned"]
     out["extra"] = extra
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
