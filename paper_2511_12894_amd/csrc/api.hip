@@ -148,8 +148,8 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
       T.m0 = 0;
       T.ksteps = 0;
     } else {
-      T.m0 = lo;
-      T.ksteps = ((hi - lo + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
+      T.m0 = lo & ~int64_t(3);            // a multiple of 4: the window refill moves 4-sample blocks
+      T.ksteps = ((hi - T.m0 + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
     }
     T.b32_off = b32_total;
     T.b16_off = b16_total;

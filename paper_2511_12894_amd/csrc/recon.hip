@@ -34,6 +34,8 @@
 // smallest index on ties) and appends threshold crossings.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "recon.h"
 
 namespace rf {
@@ -114,7 +116,7 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
 // Window of a chunk: samples z[(n0 + m0 + t0 + i) mod n], i < ch + kTimes + 32
 // (32 extra so that the prefetch of three steps ahead stays inside the buffer).
 constexpr int kWin = kChunk + kTimes + 32;
-constexpr int kWinMax = kChunkMax + kTimes + 32;
+constexpr int kWinMax = kChunkMax + kTimes + 64;   // F fragments are read up to 5 steps past a chunk
 constexpr int kStage = (kWin + 255) / 256;
 static_assert(kWin % 2 == 0, "window pairs");
 
@@ -269,10 +271,10 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
-  // hi*hi products accumulate in `acc` and are folded into the FP64 total
-  // every 8 steps (so at most 8 FP32 roundings at the size of |z|); the two
-  // correction products, 2^-11 smaller, accumulate in `cor` per chunk
-  floatx16 acc[2][2], cor[2][2];
+  // The three split products of 16 steps (256 taps) accumulate in one FP32 set
+  // that is then folded into the FP64 total; only the rounding of partial sums
+  // over 256 taps reaches the total.
+  floatx16 acc[2][2];
   Tot64 tot;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -280,6 +282,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 16; ++i) tot.v[x][y][i] = 0.0;
+  zero(acc);
   auto fold64 = [&](floatx16 (&a)[2][2]) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -294,80 +297,87 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int nch = int((ntaps + chunk - 1) / chunk);
   const int64_t last = T.ksteps - 1;
   const half8* B = reinterpret_cast<const half8*>(b16 + T.b16_off) + lane;
-  const _Float16* __restrict__ zp = reinterpret_cast<const _Float16*>(zs);
+  const uint2* __restrict__ zq = reinterpret_cast<const uint2*>(zs);   // 4 halves per element
   const int64_t mask = n - 1;
-  const int64_t gbase = n0 + T.m0;
-  // staging: each thread carries pairs of consecutive samples (i, i + 1),
-  // i = 2 tid + 512 r, packed two halves to a register
-  constexpr int kStage2 = (kWinMax + 511) / 512;
-  uint32_t stage[kStage2][4];
-  auto gather = [&](int64_t t0) {
+  const int64_t gbase = n0 + T.m0;        // a multiple of 4 (tiles start on 4-tap boundaries)
+  // Window refill in 4-position blocks: block k of every copy sg holds samples
+  // 4k + sg .. 4k + sg + 3, 16 contiguous halves (32 bytes) in the interleaved
+  // layout, so block k needs samples 4k .. 4k + 6, two aligned 4-sample loads
+  // per plane.  Thread t handles block t, staged in registers while the
+  // previous chunk computes, and block t + 256 (chunks above 736 taps only)
+  // loaded at refill time.
+  const int nblk = win_len / 4;
+  uint2 stage[4][2];
+  auto load_blk = [&](int64_t t0, int k, uint2 (&v)[4][2]) {
+    const int64_t g = ((gbase + t0 + 4 * k) & mask) >> 2;
+    const int64_t g2 = ((gbase + t0 + 4 * k + 4) & mask) >> 2;
 #pragma unroll
-    for (int r = 0; r < kStage2; ++r) {
-      const int i = 2 * threadIdx.x + 512 * r;
-      if (i < win_len) {
-        const int64_t g0 = (gbase + t0 + i) & mask;
-        const int64_t g1 = (gbase + t0 + i + 1) & mask;
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          const uint16_t lo = __builtin_bit_cast(uint16_t, zp[int64_t(pl) * n + g0]);
-          const uint16_t hi = __builtin_bit_cast(uint16_t, zp[int64_t(pl) * n + g1]);
-          stage[r][pl] = uint32_t(lo) | (uint32_t(hi) << 16);
-        }
-      }
+    for (int pl = 0; pl < 4; ++pl) {
+      v[pl][0] = zq[int64_t(pl) * (n >> 2) + g];
+      v[pl][1] = zq[int64_t(pl) * (n >> 2) + g2];
     }
   };
-  auto put = [&](int buf) {
+  auto store_blk = [&](int buf, int k, const uint2 (&v)[4][2]) {
 #pragma unroll
-    for (int r = 0; r < kStage2; ++r) {
-      const int i = 2 * threadIdx.x + 512 * r;
-      if (i < win_len) {
-#pragma unroll
-        for (int pl = 0; pl < 4; ++pl) {
-          const _Float16 v0 = __builtin_bit_cast(_Float16, uint16_t(stage[r][pl] & 0xFFFFu));
-          const _Float16 v1 = __builtin_bit_cast(_Float16, uint16_t(stage[r][pl] >> 16));
-#pragma unroll
-          for (int sg = 0; sg < 4; ++sg) {
-            if (i >= sg) win[buf][pl][win_index(sg, i - sg)] = v0;
-            if (i + 1 >= sg) win[buf][pl][win_index(sg, i + 1 - sg)] = v1;
-          }
-        }
-      }
+    for (int pl = 0; pl < 4; ++pl) {
+      // halves 0..7 of the block's samples as four 32-bit words
+      const uint32_t w0 = v[pl][0].x, w1 = v[pl][0].y, w2 = v[pl][1].x, w3 = v[pl][1].y;
+      const uint32_t o0 = __builtin_amdgcn_alignbit(w1, w0, 16);   // halves 1, 2
+      const uint32_t o1 = __builtin_amdgcn_alignbit(w2, w1, 16);   // halves 3, 4
+      const uint32_t o2 = __builtin_amdgcn_alignbit(w3, w2, 16);   // halves 5, 6
+      // copy 0: halves 0-3, copy 1: 1-4, copy 2: 2-5, copy 3: 3-6
+      uint4* dst = reinterpret_cast<uint4*>(&win[buf][pl][16 * k]);
+      dst[0] = make_uint4(w0, w1, o0, o1);
+      dst[1] = make_uint4(w1, w2, o1, o2);
+    }
+  };
+  auto gather = [&](int64_t t0) {
+    if (int(threadIdx.x) < nblk) load_blk(t0, threadIdx.x, stage);
+  };
+  auto put = [&](int64_t t0, int buf) {
+    if (int(threadIdx.x) < nblk) store_blk(buf, threadIdx.x, stage);
+    const int k = threadIdx.x + 256;
+    if (k < nblk) {
+      uint2 v[4][2];
+      load_blk(t0, k, v);
+      store_blk(buf, k, v);
     }
   };
   if (nch > 0) {
     gather(0);
-    put(0);
+    put(0, 0);
   }
   __syncthreads();
   // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
   // multiple of 4; in the interleaved layout 4 positions are 16 halves)
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
+  // B ring (slot = step % 8, six steps ahead); it runs on across chunks
+  half8 bh[8], bl[8];
+  auto loadB = [&](int64_t st, half8& h, half8& l) {
+    const int64_t g = st < last ? st : last;
+    h = B[g * 128];
+    l = B[g * 128 + 64];
+  };
+#pragma unroll
+  for (int j = 0; j < 6; ++j) loadB(j, bh[j], bl[j]);
   for (int c = 0; c < nch; ++c) {
     const int64_t t0 = int64_t(c) * chunk;
     const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
     const int buf = c & 1;
     const bool more = c + 1 < nch;
     if (more) gather(t0 + chunk);
-    zero(acc);
-    zero(cor);
     const _Float16* wb[4];
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
     const int64_t s0 = t0 / 16;
     const int nst = ch / 16;                // multiple of 8 (tiles span 128-tap multiples)
-    half8 f[4][4], bh[4], bl[4];            // [slot][plane], [slot]
+    half8 f[8][4];                          // F ring [slot][plane], slot = step % 8
     auto loadF = [&](int j, half8 (&ff)[4]) {
 #pragma unroll
       for (int pl = 0; pl < 4; ++pl) ff[pl] = lds_frag(wb[pl] + 64 * j);
     };
-    auto loadB = [&](int st, half8& h, half8& l) {
-      const int64_t g = s0 + st < last ? s0 + st : last;
-      h = B[g * 128];
-      l = B[g * 128 + 64];
-    };
-    // step s: time block 0 uses F(s), time block 1 uses F(s + 2); three split
-    // products, consecutive MFMAs feeding independent accumulators
+    // step s: time block 0 uses F(s), time block 1 uses F(s + 2); the three
+    // split products, consecutive MFMAs feeding independent accumulators
     auto mma = [&](const half8 (&f0)[4], const half8 (&f1)[4], const half8& h, const half8& l) {
 #pragma unroll
       for (int part = 0; part < 3; ++part)
@@ -377,44 +387,33 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
           for (int ri = 0; ri < 2; ++ri) {
             const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
             const half8 bv = part == 1 ? l : h;
-            if (part == 0)
-              acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
-            else
-              cor[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, cor[tb][ri], 0, 0, 0);
+            acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
           }
     };
-    // F runs three steps ahead (step s + 1 needs F(s + 3)), B two steps ahead
-    loadF(0, f[0]);
-    loadF(1, f[1]);
-    loadF(2, f[2]);
-    loadB(0, bh[0], bl[0]);
-    loadB(1, bh[1], bl[1]);
-    // one iteration = 8 steps; the hi*hi accumulator is folded at its end
-    for (int s = 0; s < nst; s += 8) {
 #pragma unroll
-      for (int h = 0; h < 8; h += 4) {
-        const int q = s + h;
-        loadF(q + 3, f[3]);
-        loadB(q + 2, bh[2], bl[2]);
+    for (int j = 0; j < 5; ++j) loadF(j, f[j]);
+    // F runs five steps ahead, B six (slots step % 8)
+    auto steps = [&](int q, auto count) {
+#pragma unroll
+      for (int h = 0; h < decltype(count)::value; ++h) {
+        loadF(q + h + 5, f[(h + 5) & 7]);
+        loadB(s0 + q + h + 6, bh[(h + 6) & 7], bl[(h + 6) & 7]);
         __builtin_amdgcn_sched_barrier(0);
-        mma(f[0], f[2], bh[0], bl[0]);
-        loadF(q + 4, f[0]);
-        loadB(q + 3, bh[3], bl[3]);
+        mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
         __builtin_amdgcn_sched_barrier(0);
-        mma(f[1], f[3], bh[1], bl[1]);
-        loadF(q + 5, f[1]);
-        loadB(q + 4, bh[0], bl[0]);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(f[2], f[0], bh[2], bl[2]);
-        loadF(q + 6, f[2]);
-        loadB(q + 5, bh[1], bl[1]);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(f[3], f[1], bh[3], bl[3]);
       }
+    };
+    // the accumulator is folded every 16 steps (and after a trailing 8)
+    int q = 0;
+    for (; q + 16 <= nst; q += 16) {
+      steps(q, std::integral_constant<int, 16>{});
       fold64(acc);
     }
-    fold64(cor);
-    if (more) put(buf ^ 1);
+    if (q < nst) {
+      steps(q, std::integral_constant<int, 8>{});
+      fold64(acc);
+    }
+    if (more) put(t0 + chunk, buf ^ 1);
     __syncthreads();
   }
   floatx16 totf[2][2];
