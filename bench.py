@@ -159,6 +159,51 @@ def batched_leg(dev):
     return res
 
 
+def factored_leg(dev, ctx, w, psd, xf, K, steps, tol=2e-6):
+    """Factored reconstruction of the same 256 series through the kernel set's
+    leading basis (J FFT correlations + matrix-core mixing), fused read-out,
+    series stored; timed like the step, with its error against direct MF."""
+    g = w["grid"]
+    n = g.n
+    nbrs = w["nbrs"]
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = rf.Factored(ctx, K, g, tol=tol, jmax=128)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = F.info()
+    zref = torch.empty((1, n), dtype=torch.complex64, device=dev)
+    zout = torch.empty((len(nbrs), n), dtype=torch.complex64, device=dev)
+    rec = []
+
+    def step():
+        rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = F.reconstruct(zref[0], z_out=zout, fused_thr=6.0, trig_cap=1 << 16)
+        b.record(stream)
+        rec.append((a, b))
+        return out
+
+    wall, _ = timed(step, steps, 2, stream)
+    rms = float(np.mean([a.elapsed_time(b) for a, b in rec[-steps:]]))
+    last = step()
+    zd, _ = rf.mf_ref_snr(ctx, g, xf, psd, nbrs, want_sigma=False)
+    err = (zout - zd).abs().max().item()
+    del zd
+    ms = wall / steps
+    J = info["J"]
+    res = dict(J=J, tol=tol, max_resid=float(max(info["resid"])), union_taps=info["len"], build_s=t_build,
+               step_ms=ms, recon_ms=rms, value=(1 + len(nbrs)) * n / (ms * 1e-3), unit="template-samples/s",
+               err_vs_direct_mf=err, ntrig=last["ntrig"],
+               mix_flops=4.0 * J * len(nbrs) * n, fft_transforms=J + 1,
+               storage_bytes=dict(basis_spectra_fp32=8 * J * (n // 2), coefficients=4 * J * len(nbrs)))
+    F.free()
+    return res
+
+
 def learned_leg(dev, w, psd, xf, K_exact, build_s, steps):
     stream = torch.cuda.Stream(dev)          # training replays a captured graph: not the null stream
     ctx = rf.Context(0, stream)
@@ -268,7 +313,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nbrs", type=int, default=24)
-    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,batched,learned")
+    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,factored,batched,learned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -276,7 +321,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "batched", "learned"}
+    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "batched", "learned"}
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -360,6 +405,9 @@ def main():
         e32 = (zout - zall[1:]).abs().max().item()
         res["err_vs_direct"] = dict(split16=e16, fp32=e32)
         del zall
+    if "factored" in legs:
+        log("bench: factored reconstruction through the kernel-set basis")
+        res["factored"] = factored_leg(dev, ctx, w, psd, xf, K, args.steps)
     if "batched" in legs:
         log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
@@ -405,6 +453,8 @@ def main():
         extra["direct_fft_mf_ms"] = dms
         extra["direct_fft_mf_value"] = samples / (dms * 1e-3)
         extra["err_vs_direct_mf"] = res["err_vs_direct"]
+    if "factored" in res:
+        extra["factored"] = res["factored"]
     if "batched" in res:
         extra["batched"] = res["batched"]
     if "learned" in res:

@@ -259,6 +259,38 @@ rf_status rf_surrogate_kernels(rf_ctx* ctx, rf_surrogate* s, const rf_grid* grid
                                double tol, rf_kernels** out, int32_t* fallback, float* check_err);
 rf_status rf_surrogate_free(rf_surrogate* s);
 
+/* ---- factored reconstruction through a basis of a kernel set ----
+ *
+ * Every kernel of a set is replaced by its projection on the set's leading
+ * J-dimensional subspace: with W the kernels on their union support and
+ * W W^T = V diag(lambda) V^T, w~_k = sum_{j<J} V[k][j] b_j, b_j = sum_k V[k][j] w_k
+ * (the best rank-J approximation).  The correlation of sec. II.B (eq.
+ * `convolution`) then splits into J basis correlations y_j = z_ref (*) b_j, done
+ * with one forward and J inverse FFTs of length n, and a mixing product
+ * z~_k = (N_ref / N_k) sum_j V[k][j] y_j on the matrix cores.  Not in the paper.
+ */
+typedef struct rf_factored rf_factored;
+
+/* Basis of the kernel set K for series of grid->n samples (a multiple of 256)
+ * and grid's band.  J is the smallest basis size whose largest per-kernel
+ * relative residual ||w_k - w~_k|| / ||w_k|| is at most tol, capped at jmax
+ * (1..128) and at the number of kernels (1..256); tol <= 0 takes the cap.
+ * Synchronises. */
+rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* grid, double tol, int32_t jmax,
+                            rf_factored** out);
+/* Host copies (any may be NULL): basis size J, union support (first tap m0,
+ * length), Gram eigenvalues lambda [nk] (descending), per-kernel relative
+ * residuals [nk]. */
+rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_t* len, double* lambda,
+                           double* resid);
+/* As snr_reconstruct with the projected kernels: z_ref device complex64 [n]
+ * (n as built), band-limited to the build grid's band (a matched-filter series
+ * is); z_out device complex64 [nk][n] or NULL; fused read-out as in
+ * snr_reconstruct.  Synchronises when fused. */
+rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, void* z_out,
+                                   const rf_peak_args* fused);
+rf_status rf_factored_free(rf_factored* F);
+
 #ifdef __cplusplus
 }
 #endif

@@ -175,3 +175,29 @@ def build_kernel(grid, ref, tgt, threshold=1e-3, per_second=True, n_r=None):
     w = ratio_taps(grid.fs, n_r, grid.f_low, grid.f_high, dfl, grid.df_high, ref, tgt)
     m_lo, taps = truncate(w, grid.fs, threshold, per_second)
     return dict(m_lo=m_lo, taps=taps, df_low=dfl, full=w)
+
+
+def project_kernel_set(kernels, rank: int):
+    """Best rank-`rank` approximation of a set of truncated kernels.
+
+    Not in the paper: the factored form of the reconstruction replaces every
+    kernel of a set by its projection on the set's leading singular subspace
+    (Eckart-Young: the rank-J matrix nearest the set in the Frobenius norm),
+    then correlates as in section II.B eq. `convolution` with those kernels.
+    kernels: list of (m_lo, taps).  The kernels are laid out on their union
+    support [M0, M0 + L); the projection is taken from numpy's SVD of that
+    K x L matrix.  Returns (M0, projected [K][L], relative residuals
+    ||w_k - w~_k|| / ||w_k||).
+    """
+    live = [(m, t) for m, t in kernels if len(t)]
+    m0 = min(m for m, _ in live)
+    m1 = max(m + len(t) for m, t in live)
+    W = np.zeros((len(kernels), m1 - m0))
+    for k, (m, t) in enumerate(kernels):
+        W[k, m - m0:m - m0 + len(t)] = t
+    U, s, Vt = np.linalg.svd(W, full_matrices=False)
+    J = min(rank, len(s))
+    Wt = (U[:, :J] * s[:J]) @ Vt[:J]
+    nrm = np.linalg.norm(W, axis=1)
+    resid = np.linalg.norm(W - Wt, axis=1) / np.where(nrm > 0, nrm, 1.0)
+    return m0, Wt, resid

@@ -14,6 +14,28 @@ constexpr int kB32PerStep = 512;   // FP32 operand floats per 16-tap step of a t
 constexpr int kB16PerStep = 1024;  // FP16 operand halves per 16-tap step (hi + lo)
 
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Output element (row, col) held by lane `lane` in accumulator register i of a
+// 32 x 32 MFMA tile: col = lane % 32, row = 8 (i / 4) + 4 (lane / 32) + i % 4.
+__device__ inline int acc_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+// Running peak of a series: larger |z|^2 wins, equal values the smaller index.
+struct Best {
+  float a2;
+  int32_t idx;
+};
+__device__ inline Best better(Best a, Best b) {
+  if (b.a2 > a.a2 || (b.a2 == a.a2 && b.idx < a.idx)) return b;
+  return a;
+}
+
+// |z|^2 with both products and the sum rounded separately (no fused multiply-add),
+// the rounding every read-out and every check of it uses
+__device__ inline float abs2_rn(float re, float im) {
+  return __fadd_rn(__fmul_rn(re, re), __fmul_rn(im, im));
+}
+
 // Read-out target of a launch.  packed[seg * nk + k] holds the running peak
 // key (|z|^2 float bits << 32 | ~index); triggers append at *count.
 struct PeakOut {

@@ -41,26 +41,7 @@
 namespace rf {
 namespace {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-
-// Output element (row, col) held by lane `lane` in accumulator register i of a
-// 32 x 32 MFMA tile: col = lane % 32, row = 8 (i / 4) + 4 (lane / 32) + i % 4.
-__device__ inline int acc_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
-
-struct Best {
-  float a2;
-  int32_t idx;
-};
-__device__ inline Best better(Best a, Best b) {
-  // larger |z|^2 wins; equal values: smaller index
-  if (b.a2 > a.a2 || (b.a2 == a.a2 && b.idx < a.idx)) return b;
-  return a;
-}
-
-__device__ inline float abs2_rn(float re, float im) {
-  return __fadd_rn(__fmul_rn(re, re), __fmul_rn(im, im));
-}
 
 // Epilogue shared by both forms: scale, store and/or fold into the read-out.
 // tot[tb][ri] holds the wave's two time blocks, real and imaginary part.

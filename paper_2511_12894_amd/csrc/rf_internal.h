@@ -93,6 +93,8 @@ void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, in
 
 // sum over the band of f^(-7/3) / S(f) -> *moment (device double), FP64, fixed order
 void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment);
+// band bins j with f_low <= j fs / n <= f_high: [jlo, jhi]
+void band_limits(const rf_grid* g, int64_t* jlo, int64_t* jhi);
 
 // Y[t][j] for the nt templates (FP64 arithmetic, complex64 store), using *moment
 // Y[seg][t][j] for nseg data segments (xf: [nseg][n/2+1]) and nt templates.

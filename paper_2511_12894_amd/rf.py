@@ -27,7 +27,8 @@ EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "r
             "rf_batch_autotune", "rf_batch_run", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
             "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
-            "rf_surrogate_kernels",
+            "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
+            "rf_factored_free",
             "rf_surrogate_free")
 
 
@@ -109,6 +110,11 @@ def load(path: str = LIB_PATH):
                                          vp, dbl, ctypes.c_int, ctypes.POINTER(RfGrid), vp, vp, dbl,
                                          ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     lib.rf_surrogate_free.argtypes = [vp]
+    lib.rf_factored_build.argtypes = [vp, vp, ctypes.POINTER(RfGrid), dbl, i32, ctypes.POINTER(vp)]
+    lib.rf_factored_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.snr_reconstruct_factored.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.rf_factored_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "rf_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -440,6 +446,64 @@ class Surrogate:
     def free(self):
         if getattr(self, "h", None):
             self.ctx.lib.rf_surrogate_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Factored:
+    """rf_factored: a kernel set's leading basis for series of grid.n samples."""
+
+    def __init__(self, ctx: Context, kernels: Kernels, grid, tol: float = 2e-6, jmax: int = 128):
+        self.ctx = ctx
+        self.nk = kernels.nk
+        g = to_grid(grid)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        ctx.check(ctx.lib.rf_factored_build(ctx.h, kernels.h, ctypes.byref(g), float(tol), int(jmax),
+                                            ctypes.byref(h)))
+        self.h = h
+
+    def info(self):
+        j = ctypes.c_int32()
+        m0, ln = ctypes.c_int64(), ctypes.c_int64()
+        lam = (ctypes.c_double * self.nk)()
+        res = (ctypes.c_double * self.nk)()
+        self.ctx.check(self.ctx.lib.rf_factored_info(self.h, ctypes.byref(j), ctypes.byref(m0), ctypes.byref(ln),
+                                                     lam, res))
+        return dict(J=j.value, m0=m0.value, len=ln.value, lam=list(lam), resid=list(res))
+
+    def reconstruct(self, z_ref: torch.Tensor, z_out=None, store: bool = True, fused_thr: float | None = None,
+                    trig_cap: int = 4096):
+        n = z_ref.numel()
+        assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
+        if store and z_out is None:
+            z_out = torch.empty((self.nk, n), dtype=torch.complex64, device=z_ref.device)
+        fused = None
+        peaks = trig = None
+        cnt = ctypes.c_int64(0)
+        if fused_thr is not None:
+            peaks = torch.empty((self.nk, 2), dtype=torch.int32, device=z_ref.device)
+            trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
+            fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
+                               ctypes.pointer(cnt))
+        st = self.ctx.lib.snr_reconstruct_factored(self.ctx.h, self.h, _ptr(z_ref), n,
+                                                   _ptr(z_out) if store else None,
+                                                   ctypes.byref(fused) if fused is not None else None)
+        if st not in (RF_OK, RF_E_OVERFLOW):
+            self.ctx.check(st)
+        out = dict(z=z_out if store else None)
+        if fused is not None:
+            out.update(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+        return out
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rf_factored_free(self.h)
             self.h = None
 
     def __del__(self):

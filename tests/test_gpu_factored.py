@@ -1,0 +1,199 @@
+"""Factored reconstruction (kernel-set basis, FFT correlations, matrix-core
+mixing) against the FP64 oracle with the same projected kernels, against
+direct matched filtering, and its fused read-out against the stored series."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mf as omf
+from oracle import peaks as opk
+from oracle import ratio as orat
+from paper_2511_12894_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_12894_amd import rf as rfmod
+    rfmod.load()
+    return rfmod
+
+
+@pytest.fixture(scope="module")
+def ctx(rf):
+    c = rf.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _oracle_setup(w, nbrs):
+    g = w["grid"]
+    zr, nr = omf.grid_snr_series(g, w["xf"], w["psd"], *w["ref"])
+    ks = [orat.build_kernel(g, w["ref"], nb) for nb in nbrs]
+    norms = [omf.norm(g.fs, g.n, g.f_low, g.f_high, w["psd"], omf.template_spectrum(g.fs, g.n, *nb)) for nb in nbrs]
+    return zr, nr, ks, norms
+
+
+def _gpu_inputs(rf, ctx, w, nbrs):
+    g = w["grid"]
+    xf = torch.from_numpy(w["xf"]).cuda()
+    psd = torch.from_numpy(w["psd"]).cuda()
+    K = rf.ratio_kernel_build(ctx, g, psd, w["ref"], nbrs)
+    z, _ = rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]])
+    return xf, psd, K, z[0].contiguous()
+
+
+@pytest.fixture(scope="module")
+def small(rf, ctx):
+    w = synth.workload_small()
+    _say("factored small: oracle")
+    zr, nr, ks, norms = _oracle_setup(w, w["nbrs"])
+    xf, psd, K, z = _gpu_inputs(rf, ctx, w, w["nbrs"])
+    yield dict(w=w, zr=zr, nr=nr, ks=ks, norms=norms, xf=xf, psd=psd, K=K, z=z)
+    K.free()
+
+
+def test_full_rank_equals_the_exact_kernels(rf, ctx, small):
+    """J = K: the projection is the identity, so the factored form must match the
+    oracle's reconstruction with the exact truncated kernels."""
+    w = small["w"]
+    F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=16)
+    assert F.info()["J"] == 16
+    z = F.reconstruct(small["z"])["z"].cpu().numpy()
+    err = 0.0
+    for k, kb in enumerate(small["ks"]):
+        zo = orat.reconstruct(small["zr"], kb["m_lo"], kb["taps"], small["nr"] / small["norms"][k])
+        err = max(err, np.abs(z[k] - zo).max())
+    _say(f"factored J=16 vs oracle exact kernels: max|dz| = {err:.3e}")
+    assert err <= 1e-5
+    F.free()
+
+
+@pytest.mark.parametrize("J", [3, 8])
+def test_rank_j_matches_the_oracle_projection(rf, ctx, small, J):
+    w = small["w"]
+    F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=J)
+    info = F.info()
+    m0, Wt, res = orat.project_kernel_set([(k["m_lo"], k["taps"]) for k in small["ks"]], J)
+    assert info["J"] == J and info["m0"] == m0 and info["len"] == Wt.shape[1]
+    np.testing.assert_allclose(info["resid"], res, rtol=1e-6, atol=1e-12)
+    z = F.reconstruct(small["z"])["z"].cpu().numpy()
+    err = 0.0
+    for k in range(len(small["ks"])):
+        zo = orat.reconstruct(small["zr"], m0, Wt[k], small["nr"] / small["norms"][k])
+        err = max(err, np.abs(z[k] - zo).max())
+    _say(f"factored J={J} vs oracle projection: max|dz| = {err:.3e}")
+    assert err <= 1e-5
+    F.free()
+
+
+def test_tolerance_picks_the_smallest_basis(rf, ctx, small):
+    w = small["w"]
+    ks = [(k["m_lo"], k["taps"]) for k in small["ks"]]
+    tol = 1e-3
+    F = rf.Factored(ctx, small["K"], w["grid"], tol=tol, jmax=16)
+    J = F.info()["J"]
+    assert orat.project_kernel_set(ks, J)[2].max() <= tol * (1 + 1e-6)
+    if J > 1:
+        assert orat.project_kernel_set(ks, J - 1)[2].max() > tol * (1 - 1e-6)
+    F.free()
+
+
+@pytest.fixture(scope="module")
+def real64(rf, ctx):
+    """Realistic structure at 64 s: 4096 Hz, f_low 20 Hz, ref 1.6+1.2, 64 lattice
+    neighbours (kernels of ~12k taps), four injections."""
+    w = synth.workload_realistic(n_nbr=64, duration=64.0)
+    _say("factored realistic-64s: oracle kernels")
+    zr, nr, ks, norms = _oracle_setup(w, w["nbrs"])
+    xf, psd, K, z = _gpu_inputs(rf, ctx, w, w["nbrs"])
+    yield dict(w=w, zr=zr, nr=nr, ks=ks, norms=norms, xf=xf, psd=psd, K=K, z=z)
+    K.free()
+
+
+def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64):
+    w = real64["w"]
+    g = w["grid"]
+    F = rf.Factored(ctx, real64["K"], g, tol=2e-6, jmax=128)
+    info = F.info()
+    J = info["J"]
+    _say(f"realistic-64s: J = {J}, max residual {max(info['resid']):.2e}")
+    assert max(info["resid"]) <= 2e-6
+    out = F.reconstruct(real64["z"], fused_thr=6.0, trig_cap=1 << 14)
+    z = out["z"]
+    # sampled outputs against the oracle with its own projection of the same kernels
+    m0, Wt, _ = orat.project_kernel_set([(k["m_lo"], k["taps"]) for k in real64["ks"]], J)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.integers(0, g.n, 200)] +
+                                   [int(t0 * g.fs) + np.arange(-40, 40) for *_, t0, _p in w["injections"]]))
+    zh = z.cpu().numpy()
+    err = 0.0
+    for k in range(0, len(real64["ks"]), 7):
+        zo = orat.reconstruct_samples(real64["zr"], m0, Wt[k], real64["nr"] / real64["norms"][k], idx)
+        err = max(err, np.abs(zh[k, idx] - zo).max())
+    _say(f"realistic-64s factored vs oracle projection (sampled): {err:.3e}")
+    assert err <= 1e-5
+    # every sample against direct matched filtering on the GPU
+    zd, _ = rf.mf_ref_snr(ctx, g, real64["xf"], real64["psd"], w["nbrs"])
+    ed = (z - zd).abs().max().item()
+    _say(f"realistic-64s factored vs direct MF: {ed:.3e}")
+    assert ed <= 2e-4
+    # fused read-out = read-out of the stored series
+    ref = rf.snr_peaks(ctx, z, 6.0, trig_cap=1 << 14)
+    torch.cuda.synchronize()
+    assert torch.equal(out["peaks"], ref["peaks"])
+    got = set(rf.decode_triggers(out["trig"], out["ntrig"]))
+    exp = set(rf.decode_triggers(ref["trig"], ref["ntrig"]))
+    assert got == exp and out["ntrig"] > 0
+    # peaks of the oracle series at the strongest injection's template
+    k = [i for i, nb in enumerate(w["nbrs"]) if tuple(nb) == tuple(w["injections"][3][:2])][0]
+    zo = orat.reconstruct(real64["zr"], m0, Wt[k], real64["nr"] / real64["norms"][k])
+    pv, pi = opk.peak(zo)
+    v, i = rf.decode_peaks(out["peaks"])
+    assert abs(v[k] - pv) <= 1e-5
+    F.free()
+
+
+def test_ragged_kernel_count_and_fused_only(rf, ctx):
+    """24 kernels (a partial 32-kernel tile), read-out without storing."""
+    w = synth.workload_small()
+    g = w["grid"]
+    nbrs = synth.neighbour_lattice(*w["ref"], g.f_low, 24)
+    xf, psd, K, z = _gpu_inputs(rf, ctx, w, nbrs)
+    F = rf.Factored(ctx, K, g, tol=1e-4, jmax=24)
+    full = F.reconstruct(z)["z"]
+    fused = F.reconstruct(z, store=False, fused_thr=5.0)
+    ref = rf.snr_peaks(ctx, full, 5.0)
+    torch.cuda.synchronize()
+    assert torch.equal(fused["peaks"], ref["peaks"])
+    assert set(rf.decode_triggers(fused["trig"], fused["ntrig"])) == set(rf.decode_triggers(ref["trig"], ref["ntrig"]))
+    F.free()
+    K.free()
+
+
+def test_argument_errors(rf, ctx, small):
+    w = small["w"]
+    with pytest.raises(rf.RfError) as e:
+        rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=0)
+    assert e.value.code == rf.RF_E_INVAL
+    with pytest.raises(rf.RfError) as e:
+        rf.Factored(ctx, small["K"], w["grid"], tol=float("nan"), jmax=8)
+    assert e.value.code == rf.RF_E_INVAL
+    F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=8)
+    short = torch.zeros(w["grid"].n // 2, dtype=torch.complex64, device="cuda")
+    with pytest.raises(rf.RfError) as e:
+        F.reconstruct(short)
+    assert e.value.code == rf.RF_E_INVAL
+    F.free()

@@ -387,3 +387,62 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([0.3, -4.0, 1e-3])
     new, m, v = mlp.adam_step(th, g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(new, th - 0.01 * np.sign(g), rtol=1e-4)
+
+
+# ---- projection of a kernel set (factored form, not in the paper) ----
+
+def _random_set(rng, k, lo=-30, hi=30, nmin=5, nmax=40):
+    out = []
+    for _ in range(k):
+        m = int(rng.integers(lo, hi))
+        out.append((m, rng.standard_normal(int(rng.integers(nmin, nmax)))))
+    return out
+
+
+def test_projection_full_rank_is_identity():
+    rng = np.random.default_rng(71)
+    ks = _random_set(rng, 6)
+    m0, Wt, res = ratio.project_kernel_set(ks, 6)
+    for k, (m, t) in enumerate(ks):
+        row = np.zeros(Wt.shape[1])
+        row[m - m0:m - m0 + len(t)] = t
+        assert np.abs(Wt[k] - row).max() <= 1e-12 * np.abs(t).max()
+    assert res.max() <= 1e-12
+
+
+def test_projection_exact_on_a_rank_two_set():
+    rng = np.random.default_rng(72)
+    a, b = rng.standard_normal(40), rng.standard_normal(40)
+    ks = [(-7, c1 * a + c2 * b) for c1, c2 in rng.standard_normal((9, 2))]
+    _, _, r2 = ratio.project_kernel_set(ks, 2)
+    _, _, r1 = ratio.project_kernel_set(ks, 1)
+    assert r2.max() <= 1e-12
+    assert r1.max() > 1e-3
+
+
+def test_projection_is_the_nearest_rank_j_set():
+    """Eckart-Young: no other rank-3 set is closer; the squared error equals the
+    sum of the Gram matrix's trailing eigenvalues (from eigvalsh, not the SVD)."""
+    rng = np.random.default_rng(73)
+    ks = [(0, rng.standard_normal(30)) for _ in range(8)]
+    W = np.array([t for _, t in ks])
+    _, Wt, _ = ratio.project_kernel_set(ks, 3)
+    err = np.linalg.norm(W - Wt)
+    lam = np.sort(np.linalg.eigvalsh(W @ W.T))[::-1]
+    assert abs(err ** 2 - lam[3:].sum()) <= 1e-10 * lam.sum()
+    assert np.linalg.matrix_rank(Wt, tol=1e-10 * np.abs(Wt).max()) == 3
+    for trial in range(5):
+        B = rng.standard_normal((3, 30)) if trial else W[:3]        # rows spanning a 3-d space
+        Qb, _ = np.linalg.qr(B.T)
+        assert err <= np.linalg.norm(W - W @ Qb @ Qb.T) + 1e-12
+
+
+def test_projection_residual_decreases_with_rank():
+    w = synth.workload_small()
+    ks = [ratio.build_kernel(w["grid"], w["ref"], nb) for nb in w["nbrs"]]
+    prev = np.inf
+    for J in (2, 4, 8, 12, 16):
+        _, _, res = ratio.project_kernel_set([(k["m_lo"], k["taps"]) for k in ks], J)
+        assert res.max() <= prev + 1e-15
+        prev = res.max()
+    assert prev <= 1e-12
