@@ -179,12 +179,13 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
   constexpr int kMixTimes = 32 * kMixWaves;
   constexpr int KP = 32 * kMixTiles;
   extern __shared__ __attribute__((aligned(16))) float smem[];
-  float* Cs = smem;                                          // [JP][32][kMixTiles]
+  constexpr int NG = kMixTiles / kMixGroup;                  // sweeps per time block
+  float* Cs = smem;                                          // [JP][NG][32 lanes][kMixGroup]
   Best* best = reinterpret_cast<Best*>(Cs + JP * KP);        // [kMixWaves][KP]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int e = threadIdx.x; e < JP * KP; e += 64 * kMixWaves) {
-    const int j = e / KP, k = e % KP;
-    Cs[(j * 32 + (k & 31)) * kMixTiles + (k >> 5)] = Cg[e];
+    const int j = e / KP, k = e % KP, tile = k >> 5;
+    Cs[((j * NG + tile / kMixGroup) * 32 + (k & 31)) * kMixGroup + tile % kMixGroup] = Cg[e];
   }
   if (FUSED)
     for (int e = threadIdx.x; e < kMixWaves * KP; e += 64 * kMixWaves) best[e] = Best{-1.f, INT32_MAX};
@@ -204,9 +205,10 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
       im[s] = v.y;
     }
   };
-  // B operands of group g's tiles for basis pair s: C[2s + kr][(G g + t) 32 + lane % 32]
+  // B operands of sweep g's tiles for basis pair s: C[2s + kr][(G g + t) 32 + lane % 32],
+  // consecutive lanes reading consecutive words
   typedef float floatG __attribute__((ext_vector_type(kMixGroup)));
-  const floatG* cb = reinterpret_cast<const floatG*>(Cs + (kr * 32 + (lane & 31)) * kMixTiles);
+  const floatG* cb = reinterpret_cast<const floatG*>(Cs) + kr * NG * 32 + (lane & 31);
   if (int64_t(blockIdx.x) < nblk) loadA(blockIdx.x, are, aim);
   for (int64_t tbk = blockIdx.x; tbk < nblk; tbk += gridDim.x) {
     const int64_t t0 = tbk * kMixTimes + 32 * wave;
@@ -219,10 +221,10 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
         cre[t] = floatx16{};
         cim[t] = floatx16{};
       }
-      floatG bcur = cb[g], bnext = bcur;
+      floatG bcur = cb[g * 32], bnext = bcur;
 #pragma unroll
       for (int s = 0; s < JP / 2; ++s) {
-        if (s + 1 < JP / 2) bnext = cb[(s + 1) * (2 * 32 * kMixTiles / kMixGroup) + g];
+        if (s + 1 < JP / 2) bnext = cb[((s + 1) * 2 * NG + g) * 32];
 #pragma unroll
         for (int t = 0; t < kMixGroup; ++t) {
           cre[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[s], bcur[t], cre[t], 0, 0, 0);
@@ -236,11 +238,17 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
         const bool live = k < nk;
         Best bt{-1.f, INT32_MAX};
         uint32_t cross = 0;
+        if (STORE && live) {
+          // rows i, i + 1 (i even) are consecutive times: one 16-byte store
+          float4* zrow = reinterpret_cast<float4*>(zout + int64_t(k) * n + t0);
+#pragma unroll
+          for (int i = 0; i < 16; i += 2)
+            zrow[acc_row(i, lane) >> 1] = make_float4(cre[t][i], cim[t][i], cre[t][i + 1], cim[t][i + 1]);
+        }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int64_t m = t0 + acc_row(i, lane);
           const float re = cre[t][i], im = cim[t][i];
-          if (STORE && live) zout[int64_t(k) * n + m] = make_float2(re, im);
           if (FUSED) {
             const float a2 = abs2_rn(re, im);
             bt = better(bt, Best{a2, int32_t(m)});
