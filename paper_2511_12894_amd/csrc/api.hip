@@ -162,8 +162,10 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
   K->slot_kernel = dev_alloc<int32_t>(slot.size());
   K->colscale32 = dev_alloc<float>(slot.size());
   K->colscale16 = dev_alloc<float>(slot.size());
-  K->b32 = dev_alloc<float>(size_t(b32_total));
-  K->b16 = dev_alloc<__half>(size_t(b16_total));
+  K->b32 = dev_alloc<float>(size_t(b32_total + int64_t(kOperandPadSteps) * kB32PerStep));
+  K->b16 = dev_alloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep));
+  fill_u32(ctx, reinterpret_cast<uint32_t*>(K->b32 + b32_total), 0u, int64_t(kOperandPadSteps) * kB32PerStep);
+  fill_u32(ctx, reinterpret_cast<uint32_t*>(K->b16 + b16_total), 0u, int64_t(kOperandPadSteps) * kB16PerStep / 2);
   RF_HIP(hipMemcpy(K->tiles_dev, K->tiles.data(), sizeof(TileDev) * K->tiles.size(), hipMemcpyHostToDevice));
   RF_HIP(hipMemcpy(K->slot_kernel, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
   RF_HIP(hipMemcpy(K->colscale32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));

@@ -177,7 +177,8 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
       slot_total += int64_t(K->tiles.size()) * kTileKernels;
     }
     // global slot arrays and tiles: group r's kernels get global indices kbase[r] + k
-    b->b16 = balloc<__half>(size_t(b16_total));
+    b->b16 = balloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep));
+    fill_u32(ctx, reinterpret_cast<uint32_t*>(b->b16 + b16_total), 0u, int64_t(kOperandPadSteps) * kB16PerStep / 2);
     b->colscale = balloc<float>(size_t(slot_total));
     b->slot_kernel = balloc<int32_t>(size_t(slot_total));
     int64_t b16_off = 0, slot_off = 0;

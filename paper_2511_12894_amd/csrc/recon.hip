@@ -252,10 +252,11 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
-  // The three split products of 16 steps (256 taps) accumulate in one FP32 set
-  // that is then folded into the FP64 total; only the rounding of partial sums
-  // over 256 taps reaches the total.
-  floatx16 acc[2][2];
+  // hi*hi products accumulate in `acc`, folded into the FP64 total every 32
+  // steps (at most 32 FP32 roundings at the size of |z| per fold); the two
+  // correction products, 2^-11 smaller, accumulate in `cor` over the whole
+  // item, folded once at its end.
+  floatx16 acc[2][2], cor[2][2];
   Tot64 tot;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -264,6 +265,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
 #pragma unroll
       for (int i = 0; i < 16; ++i) tot.v[x][y][i] = 0.0;
   zero(acc);
+  zero(cor);
   auto fold64 = [&](floatx16 (&a)[2][2]) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -276,7 +278,6 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   };
   const int64_t ntaps = T.ksteps * 16;
   const int nch = int((ntaps + chunk - 1) / chunk);
-  const int64_t last = T.ksteps - 1;
   const half8* B = reinterpret_cast<const half8*>(b16 + T.b16_off) + lane;
   const uint2* __restrict__ zq = reinterpret_cast<const uint2*>(zs);   // 4 halves per element
   const int64_t mask = n - 1;
@@ -334,10 +335,9 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
   // B ring (slot = step % 8, six steps ahead); it runs on across chunks
   half8 bh[8], bl[8];
-  auto loadB = [&](int64_t st, half8& h, half8& l) {
-    const int64_t g = st < last ? st : last;
-    h = B[g * 128];
-    l = B[g * 128 + 64];
+  auto loadB = [&](int64_t st, half8& h, half8& l) {   // st <= ksteps + 5: inside the padding
+    h = B[st * 128];
+    l = B[st * 128 + 64];
   };
 #pragma unroll
   for (int j = 0; j < 6; ++j) loadB(j, bh[j], bl[j]);
@@ -368,7 +368,10 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
           for (int ri = 0; ri < 2; ++ri) {
             const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
             const half8 bv = part == 1 ? l : h;
-            acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
+            if (part == 0)
+              acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
+            else
+              cor[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, cor[tb][ri], 0, 0, 0);
           }
     };
 #pragma unroll
@@ -384,19 +387,20 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
         __builtin_amdgcn_sched_barrier(0);
       }
     };
-    // the accumulator is folded every 16 steps (and after a trailing 8)
+    // acc is folded every 32 steps and at the chunk's end
     int q = 0;
-    for (; q + 16 <= nst; q += 16) {
-      steps(q, std::integral_constant<int, 16>{});
+    for (; q + 32 <= nst; q += 32) {
+      steps(q, std::integral_constant<int, 32>{});
       fold64(acc);
     }
     if (q < nst) {
-      steps(q, std::integral_constant<int, 8>{});
+      for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
       fold64(acc);
     }
     if (more) put(t0 + chunk, buf ^ 1);
     __syncthreads();
   }
+  fold64(cor);
   floatx16 totf[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
