@@ -309,6 +309,24 @@ def workload_batched(n_seg: int = 8, n_ref: int = 64, duration: float = 256.0,
                 segments=segs, refs=refs, groups=groups, injections=injections)
 
 
+def workload_stress(n_nbr: int = 1024, refs=((1.0, 1.0), (1.167, 1.167), (1.333, 1.333), (1.5, 1.5)),
+                    duration: float = 2048.0, fs: float = 4096.0, f_low: float = 10.0, seed: int = 1005):
+    """Next-generation-detector shape: 2048 s at 4096 Hz (n = 2^23), f_low = 10 Hz,
+    equal-mass references with `n_nbr` lattice neighbours each, one injection at
+    SNR 15 at t0 = 1000 s on a seeded neighbour of the first reference."""
+    n = int(round(duration * fs))
+    grid = make_grid(fs, n, f_low)
+    psd = make_psd(grid)
+    rng = np.random.default_rng(seed)
+    groups = [neighbour_lattice(m1, m2, f_low, n_nbr) for m1, m2 in refs]
+    xf = noise(grid, psd, seed=seed)
+    m1, m2 = groups[0][int(rng.integers(n_nbr))]
+    phi = float(rng.uniform(0.0, 2.0 * math.pi))
+    xf = inject(grid, psd, xf, m1, m2, 15.0, 1000.0, phi)
+    return dict(name=f"stress-{duration:g}s-{fs:g}Hz-{len(refs)}ref-{n_nbr}nbr", grid=grid, psd=psd, xf=xf,
+                refs=[tuple(r) for r in refs], groups=groups, injections=[(m1, m2, 15.0, 1000.0, phi)])
+
+
 # ------------------------------------------------------- learned-kernel inputs
 
 def surrogate_pairs(f0: float, count: int, seed: int, m_range=(1.0, 3.0), steps: int = 10):
