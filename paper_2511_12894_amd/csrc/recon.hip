@@ -117,6 +117,37 @@ __device__ inline void fold(floatx16 (&tot)[2][2], floatx16 (&acc)[2][2]) {
     }
 }
 
+// FP64 running total of a wave's outputs: tot[tb][ri][i] (128 registers).
+struct Tot64 {
+  double v[2][2][16];
+};
+__device__ inline void zero64(Tot64& t) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t.v[x][y][i] = 0.0;
+}
+__device__ inline void fold64(Tot64& t, floatx16 (&a)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t.v[x][y][i] += double(a[x][y][i]);
+      a[x][y] = floatx16{};
+    }
+}
+__device__ inline void to_f32(const Tot64& t, floatx16 (&o)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) o[x][y][i] = float(t.v[x][y][i]);
+}
+
 template <bool STORE, bool FUSED>
 __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__ z, int64_t n,
                                                       const TileDev* __restrict__ tiles,
@@ -130,8 +161,9 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
   const int64_t n0 = int64_t(blockIdx.x) * kTimes;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
-  floatx16 tot[2][2], acc[2][2];
-  zero(tot);
+  floatx16 acc[2][2];
+  Tot64 tot;
+  zero64(tot);
   const int64_t ntaps = T.ksteps * 16;
   const int nch = int((ntaps + kChunk - 1) / kChunk);
   const int64_t last2 = T.ksteps * 8 - 1;           // last 2-tap step of the tile
@@ -193,7 +225,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     load(1, bq[1], aq[1]);
     load(2, bq[2], aq[2]);
     // FP32 products enter the accumulator two at a time: it is folded into the
-    // total every 64 steps (128 taps) to bound the rounding growth
+    // FP64 total every 64 steps (128 taps), so only FP32 roundings of partial
+    // sums over 128 taps reach the result, whatever the kernel length
     for (int s64 = 0; s64 < nst; s64 += 64) {
       for (int s = s64; s < s64 + 64; s += 4) {
         load(s + 3, bq[3], aq[3]);
@@ -209,12 +242,14 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
         __builtin_amdgcn_sched_barrier(0);
         mma(bq[3], aq[3]);
       }
-      fold(tot, acc);
+      fold64(tot, acc);
     }
     if (more) put(buf ^ 1);
     __syncthreads();
   }
-  epilogue<STORE, FUSED>(tot, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, 1.f, zout, po);
+  floatx16 totf[2][2];
+  to_f32(tot, totf);
+  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, 1.f, zout, po);
 }
 
 // LDS window of the split reference series: 4 planes (re_hi, re_lo, im_hi,
@@ -235,10 +270,6 @@ __device__ inline half8 lds_frag(const _Float16* p) {
   return h;
 }
 
-// FP64 running total of the split form: tot[tb][ri][i] (128 registers).
-struct Tot64 {
-  double v[2][2][16];
-};
 
 // One work item of the split form: output times [n0, n0 + kTimes) of tile T,
 // window chunks of `chunk` taps (256, 512 or 1024; a multiple of 64).
