@@ -159,10 +159,11 @@ def batched_leg(dev):
     return res
 
 
-def factored_leg(dev, ctx, w, psd, xf, K, steps, tol=2e-6):
+def factored_leg(dev, ctx, w, psd, xf, K, steps, tol=2e-6, precs=("split16", "fp32")):
     """Factored reconstruction of the same 256 series through the kernel set's
     leading basis (J FFT correlations + matrix-core mixing), fused read-out,
-    series stored; timed like the step, with its error against direct MF."""
+    series stored; timed like the step for each mixing precision, with its
+    error against direct MF."""
     g = w["grid"]
     n = g.n
     nbrs = w["nbrs"]
@@ -173,33 +174,35 @@ def factored_leg(dev, ctx, w, psd, xf, K, steps, tol=2e-6):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     info = F.info()
+    J = info["J"]
     zref = torch.empty((1, n), dtype=torch.complex64, device=dev)
     zout = torch.empty((len(nbrs), n), dtype=torch.complex64, device=dev)
-    rec = []
-
-    def step():
-        rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        out = F.reconstruct(zref[0], z_out=zout, fused_thr=6.0, trig_cap=1 << 16)
-        b.record(stream)
-        rec.append((a, b))
-        return out
-
-    wall, _ = timed(step, steps, 2, stream)
-    rms = float(np.mean([a.elapsed_time(b) for a, b in rec[-steps:]]))
-    last = step()
     zd, _ = rf.mf_ref_snr(ctx, g, xf, psd, nbrs, want_sigma=False)
-    err = (zout - zd).abs().max().item()
-    del zd
-    ms = wall / steps
-    J = info["J"]
     res = dict(J=J, tol=tol, max_resid=float(max(info["resid"])), union_taps=info["len"], build_s=t_build,
-               step_ms=ms, recon_ms=rms, value=(1 + len(nbrs)) * n / (ms * 1e-3), unit="template-samples/s",
-               err_vs_direct_mf=err, ntrig=last["ntrig"],
                mix_flops=4.0 * J * len(nbrs) * n, fft_transforms=J + 1,
                storage_bytes=dict(basis_spectra_fp32=8 * J * (n // 2), coefficients=4 * J * len(nbrs)))
+    for prec in precs:
+        rec = []
+
+        def step():
+            rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = F.reconstruct(zref[0], z_out=zout, fused_thr=6.0, trig_cap=1 << 16, prec=prec)
+            b.record(stream)
+            rec.append((a, b))
+            return out
+
+        log(f"bench: factored {prec}")
+        wall, _ = timed(step, steps, 2, stream)
+        rms = float(np.mean([a.elapsed_time(b) for a, b in rec[-steps:]]))
+        last = step()
+        err = (zout - zd).abs().max().item()
+        ms = wall / steps
+        res[prec] = dict(step_ms=ms, recon_ms=rms, value=(1 + len(nbrs)) * n / (ms * 1e-3),
+                         unit="template-samples/s", err_vs_direct_mf=err, ntrig=last["ntrig"])
+    del zd
     F.free()
     return res
 

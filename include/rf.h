@@ -285,10 +285,13 @@ rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_
                            double* resid);
 /* As snr_reconstruct with the projected kernels: z_ref device complex64 [n]
  * (n as built), band-limited to the build grid's band (a matched-filter series
- * is); z_out device complex64 [nk][n] or NULL; fused read-out as in
+ * is); prec selects the mixing product: RF_PREC_FP32 (FP32 matrix cores) or
+ * RF_PREC_SPLIT_FP16 (hi/lo FP16 parts of both operands after power-of-two
+ * scales, three products, FP32 accumulation); the basis transforms are FP32
+ * either way.  z_out device complex64 [nk][n] or NULL; fused read-out as in
  * snr_reconstruct.  Synchronises when fused. */
-rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, void* z_out,
-                                   const rf_peak_args* fused);
+rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec,
+                                   void* z_out, const rf_peak_args* fused);
 rf_status rf_factored_free(rf_factored* F);
 
 #ifdef __cplusplus

@@ -162,7 +162,7 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     b->n = grid->n;
     b->psd = psd;
     std::vector<Tf2Coef> coef(nref);
-    int64_t tile_total = 0, b16_total = 0, slot_total = 0;
+    int64_t b16_total = 0, slot_total = 0;
     for (int r = 0; r < nref; ++r) {
       RF_CHECK(refs[r].m1 > 0 && refs[r].m2 > 0, "rf_batch_create: template masses must be positive");
       coef[r] = tf2_coef(refs[r]);
@@ -173,7 +173,6 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
         RF_CHECK(T.ksteps * 16 <= b->n, "rf_batch_create: kernel support longer than the segment");
         b16_total += T.ksteps * kB16PerStep;
       }
-      tile_total += int64_t(K->tiles.size());
       slot_total += int64_t(K->tiles.size()) * kTileKernels;
     }
     // global slot arrays and tiles: group r's kernels get global indices kbase[r] + k

@@ -37,6 +37,12 @@ struct rf_factored {
   float2* Qin = nullptr;     // [n]
   float2* S = nullptr;       // [J][n]: basis spectra (zero off the band)
   float2* Y = nullptr;       // [JP][n]: basis correlations y_j (rows from J on zero)
+  // split-FP16 mixing: the coefficients as hi/lo FP16 B operand fragments
+  // [JP/16][8 tiles][2 planes][64 lanes][8 basis indices] after the scale cscale
+  _Float16* Cp = nullptr;
+  uint32_t* zmax = nullptr;  // max(|re|, |im|) of the series being reconstructed (float bits)
+  float l1max = 0.f;         // largest L1 norm of a basis vector
+  float cscale = 1.f;        // power-of-two scale of the packed coefficients
   std::vector<double> lambda, resid;
 };
 
@@ -126,13 +132,6 @@ __global__ void k_band_gather(const double2* __restrict__ in, int64_t n, int64_t
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nb; i += int64_t(gridDim.x) * 256) {
     const double2 v = in[int64_t(j) * n + b0 + i];
     out[int64_t(j) * nb + i] = make_float2(float(v.x), float(v.y));
-  }
-}
-
-__global__ void k_conj(const float2* __restrict__ z, int64_t n, float2* __restrict__ out) {
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    const float2 v = z[i];
-    out[i] = make_float2(v.x, -v.y);
   }
 }
 
@@ -319,6 +318,242 @@ __global__ void k_trig_finish(rf_trigger* __restrict__ trig, const unsigned long
   }
 }
 
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+// Power-of-two scale that puts the FP16 parts of the basis correlations in
+// range: |y_j[m]| <= max|z_ref| ||b_j||_1 (Hoelder), max|z_ref| <= sqrt(2)
+// max(|re|, |im|); the bound times the scale stays below 2^14 (four times
+// under the FP16 limit, room for the transforms' rounding).  Values far below
+// the bound keep their relative precision: FP16 is floating point, and the
+// subnormal floor sits about 2^-38 below the bound.
+__device__ inline float y_scale(const uint32_t* zmax, float l1max) {
+  const float bound = 1.41421357f * __uint_as_float(*zmax) * l1max;
+  if (!(bound > 0.f) || !(bound < 3.0e38f)) return 1.f;
+  int e = 0;
+  frexpf(bound, &e);                 // bound in [2^(e-1), 2^e)
+  return ldexpf(1.f, 14 - e);
+}
+
+// conj(z) as the forward-transform input, and max(|re|, |im|) of z (one
+// atomic per workgroup into zmax, which starts at zero)
+__global__ __launch_bounds__(256) void k_conj_max(const float2* __restrict__ z, int64_t n,
+                                                  float2* __restrict__ out, uint32_t* zmax) {
+  __shared__ float wmax[4];
+  float m = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 v = z[i];
+    out[i] = make_float2(v.x, -v.y);
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(zmax, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
+}
+
+// L1 norm of each basis vector (row of Bm [J][L]), one workgroup per row
+__global__ __launch_bounds__(256) void k_row_l1(const double* __restrict__ Bm, int64_t L, double* __restrict__ out) {
+  __shared__ double part[256];
+  const double* row = Bm + int64_t(blockIdx.x) * L;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < L; i += 256) s += fabs(row[i]);
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+// Split-FP16 mixing on v_mfma_f32_32x32x16_f16, transposed against the FP32
+// mixing: rows = 32 kernels, columns = 32 output times, K = 16 basis indices,
+// so that a lane holds one time of 16 kernels and every store of a row of
+// accumulators writes two whole 256-byte runs of series.  y ~ y_hi + y_lo (split
+// in registers from the FP32 correlations after the scale s_y) and
+// C ~ C_hi + C_lo (packed at build time, scale s_c); three products per term
+// (hi hi, hi lo, lo hi) with FP32 accumulation, output times 1 / (s_y s_c)
+// (exact: powers of two).  8 waves (2 per SIMD; 4 waves, one per SIMD, from
+// 128 basis vectors on), the packed coefficients in LDS as
+// [ks][tile][plane][lane] 16-byte fragments; each wave holds its 32 times'
+// fragments for all basis indices and sweeps the kernel tiles two at a time.
+// Read-out: the running peak key of every (kernel, time lane) pair is an LDS
+// atomic max (two time lanes per slot from 112 basis vectors on, for room),
+// reduced to one global atomic per kernel and workgroup at the end; crossings
+// as in the FP32 mixing.
+// two waves per SIMD while the fragments fit in 256 registers, else one
+template <int JP>
+constexpr int mix16_waves() { return JP <= 112 ? 8 : 4; }
+template <int JP>
+constexpr int mix16_slots() { return JP <= 96 ? 32 : 16; }
+
+template <int JP, bool STORE, bool FUSED>
+__global__ __launch_bounds__(64 * mix16_waves<JP>(), 1) void k_mix16(const float2* __restrict__ Y, int64_t n,
+                                                                     const half8* __restrict__ Cp, int nk,
+                                                                     const uint32_t* __restrict__ zmax,
+                                                                     float l1max, float cscale,
+                                                                     float2* __restrict__ zout, PeakOut po) {
+  constexpr int KS = JP / 16;
+  constexpr int W = mix16_waves<JP>();
+  constexpr int G = 2;
+  constexpr int S = mix16_slots<JP>();
+  constexpr int KP = 32 * kMixTiles;
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  half8* Cs = reinterpret_cast<half8*>(smem);                                                      // [KS][8][2][64]
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(Cs + KS * kMixTiles * 2 * 64);  // [KP][S]
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ntiles = (nk + 31) >> 5;
+  // store offset of this lane from a tile's row of kernel 32 tile + acc_row(i, 0) at time t0
+  // (below 2^29 bytes for n up to 2^24)
+  const uint32_t loff = uint32_t(4 * (lane >> 5)) * uint32_t(n) + uint32_t(lane & 31);
+  for (int e = threadIdx.x; e < KS * kMixTiles * 2 * 64; e += 64 * W) Cs[e] = Cp[e];
+  if (FUSED)
+    for (int e = threadIdx.x; e < KP * S; e += 64 * W) keys[e] = 0ull;
+  __syncthreads();
+  const float sy = y_scale(zmax, l1max);
+  const float inv = 1.f / (sy * cscale);
+  const int64_t nblk = n / (32 * W);
+  const int slot = (lane & 31) / (32 / S);
+  // B operand: lane holds y_{16 ks + 8 (lane / 32) + q}[t0 + lane % 32], q < 8
+  const float2* Ylane = Y + int64_t(8 * (lane >> 5)) * n + 32 * wave + (lane & 31);
+  for (int64_t tbk = blockIdx.x; tbk < nblk; tbk += gridDim.x) {
+    const int64_t t0 = tbk * (32 * W) + 32 * wave;
+    const int64_t m = t0 + (lane & 31);         // this lane's output time
+    half8 y[4][KS];                             // re hi, re lo, im hi, im lo
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      float2 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = Ylane[tbk * (32 * W) + int64_t(16 * ks + q) * n];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float re = v[q].x * sy, im = v[q].y * sy;
+        const _Float16 rh = _Float16(re), ih = _Float16(im);
+        y[0][ks][q] = rh;
+        y[1][ks][q] = _Float16(re - float(rh));
+        y[2][ks][q] = ih;
+        y[3][ks][q] = _Float16(im - float(ih));
+      }
+    }
+    for (int g = 0; G * g < ntiles; ++g) {
+      floatx16 cre[G], cim[G];
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        cre[t] = floatx16{};
+        cim[t] = floatx16{};
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          const half8 ch = Cs[((ks * kMixTiles + G * g + t) * 2 + 0) * 64 + lane];
+          const half8 cl = Cs[((ks * kMixTiles + G * g + t) * 2 + 1) * 64 + lane];
+          cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch, y[0][ks], cre[t], 0, 0, 0);
+          cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch, y[2][ks], cim[t], 0, 0, 0);
+          cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cl, y[0][ks], cre[t], 0, 0, 0);
+          cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cl, y[2][ks], cim[t], 0, 0, 0);
+          cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch, y[1][ks], cre[t], 0, 0, 0);
+          cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch, y[3][ks], cim[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        // register i holds kernel kb + acc_row(i, 0) (kb carries the 4 (lane / 32) part)
+        const int kb = (G * g + t) * 32 + 4 * (lane >> 5);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          cre[t][i] *= inv;
+          cim[t][i] *= inv;
+        }
+        if (STORE) {
+          float2* zt = zout + int64_t((G * g + t) * 32) * n + t0;      // wave-uniform
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (kb + acc_row(i, 0) < nk) (zt + int64_t(acc_row(i, 0)) * n)[loff] = make_float2(cre[t][i], cim[t][i]);
+        }
+        if (FUSED) {
+          uint32_t cross = 0;
+          const uint32_t ikey = 0xFFFFFFFFu - uint32_t(m);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int k = kb + acc_row(i, 0);
+            if (k < nk) {
+              const float a2 = abs2_rn(cre[t][i], cim[t][i]);
+              atomicMax(&keys[k * S + slot], (unsigned long long)((uint64_t(__float_as_uint(a2)) << 32) | ikey));
+              if (a2 > po.thr2) cross |= 1u << i;
+            }
+          }
+          if (cross) {
+#pragma unroll 1
+            for (int i = 0; i < 16; ++i)
+              if ((cross >> i) & 1u) {
+                const unsigned long long sl = atomicAdd(po.count, 1ull);
+                if (int64_t(sl) < po.cap) {
+                  rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
+                  tr.tmpl = kb + acc_row(i, 0);
+                  tr.seg = po.seg;
+                  tr.idx = int32_t(m);
+                  tr.absz = cre[t][i];
+                  tr.argz = cim[t][i];
+                  po.trig[sl] = tr;
+                }
+              }
+          }
+        }
+      }
+    }
+  }
+  if (FUSED) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < nk; k += 64 * W) {
+      unsigned long long b = 0ull;
+      for (int s2 = 0; s2 < S; ++s2) b = max(b, keys[k * S + s2]);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
+    }
+  }
+}
+
+template <int JP>
+void mix16_launch_jp(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& po, bool fused) {
+  constexpr int KS = JP / 16;
+  constexpr int W = mix16_waves<JP>();
+  const size_t lds = sizeof(half8) * size_t(KS) * kMixTiles * 2 * 64 +
+                     (fused ? sizeof(unsigned long long) * 32 * kMixTiles * mix16_slots<JP>() : 0);
+  int dev = 0, cus = 0;
+  RF_HIP(hipGetDevice(&dev));
+  RF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t nblk = F->n / (32 * W);
+  const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(nblk, cus)));
+  const half8* Cp = reinterpret_cast<const half8*>(F->Cp);
+#define RF_MIX16(S, FU)                                                                                  \
+  do {                                                                                                   \
+    auto kfn = k_mix16<JP, S, FU>;                                                                       \
+    RF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),                                       \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));                   \
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(64 * W), lds, ctx->stream, F->Y, F->n, Cp, F->nk, F->zmax,  \
+                       F->l1max, F->cscale, zout, po);                                                   \
+  } while (0)
+  if (zout && fused) RF_MIX16(true, true);
+  else if (zout) RF_MIX16(true, false);
+  else RF_MIX16(false, true);
+#undef RF_MIX16
+  RF_HIP(hipGetLastError());
+}
+
+void mix16_launch(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& po, bool fused) {
+  switch (F->JP) {
+    case 16: mix16_launch_jp<16>(ctx, F, zout, po, fused); break;
+    case 32: mix16_launch_jp<32>(ctx, F, zout, po, fused); break;
+    case 48: mix16_launch_jp<48>(ctx, F, zout, po, fused); break;
+    case 64: mix16_launch_jp<64>(ctx, F, zout, po, fused); break;
+    case 80: mix16_launch_jp<80>(ctx, F, zout, po, fused); break;
+    case 96: mix16_launch_jp<96>(ctx, F, zout, po, fused); break;
+    case 112: mix16_launch_jp<112>(ctx, F, zout, po, fused); break;
+    case 128: mix16_launch_jp<128>(ctx, F, zout, po, fused); break;
+    default: throw Error{RF_E_INVAL, "factored: basis size out of range"};
+  }
+}
+
 template <int JP>
 void mix_launch_jp(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& po, bool fused) {
   constexpr int KP = 32 * kMixTiles;
@@ -361,7 +596,8 @@ void mix_launch(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& 
 
 void free_factored(rf_factored* F) {
   if (!F) return;
-  for (void* p : {(void*)F->Ub, (void*)F->C, (void*)F->Q, (void*)F->Qin, (void*)F->S, (void*)F->Y})
+  for (void* p : {(void*)F->Ub, (void*)F->C, (void*)F->Q, (void*)F->Qin, (void*)F->S, (void*)F->Y, (void*)F->Cp,
+                  (void*)F->zmax})
     if (p) (void)hipFree(p);
   delete F;
 }
@@ -512,13 +748,55 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
       }
       RF_HIP(hipStreamSynchronize(ctx->stream));
     }
+    // largest L1 norm of a basis vector (bounds the correlations for the FP16 split)
+    {
+      double* l1 = falloc<double>(size_t(J));
+      hipLaunchKernelGGL(k_row_l1, dim3(unsigned(J)), dim3(256), 0, ctx->stream, Bm, L, l1);
+      RF_HIP(hipGetLastError());
+      std::vector<double> l1h(J);
+      fcopy(ctx, l1h.data(), l1, sizeof(double) * J, hipMemcpyDeviceToHost);
+      (void)hipFree(l1);
+      F->l1max = float(*std::max_element(l1h.begin(), l1h.end()) * (1.0 + 1e-6));
+    }
     (void)hipFree(Bm);
     // mixing coefficients with the norm ratios folded in
     std::vector<float> ch(size_t(F->JP) * F->KP, 0.f);
+    std::vector<double> cd(size_t(F->JP) * F->KP, 0.0);
+    double cmax = 0.0;
     for (int j = 0; j < J; ++j)
-      for (int k = 0; k < nk; ++k) ch[size_t(j) * F->KP + k] = float(V[size_t(k) * nk + j] * K->norm_ratio[k]);
+      for (int k = 0; k < nk; ++k) {
+        const double c = V[size_t(k) * nk + j] * K->norm_ratio[k];
+        cd[size_t(j) * F->KP + k] = c;
+        ch[size_t(j) * F->KP + k] = float(c);
+        cmax = std::max(cmax, std::fabs(c));
+      }
     F->C = falloc<float>(ch.size());
     fcopy(ctx, F->C, ch.data(), sizeof(float) * ch.size(), hipMemcpyHostToDevice);
+    // the same, split into FP16 hi + lo after a power-of-two scale (largest
+    // scaled value in [2^13, 2^14)), in the B operand layout of the 32x32x16
+    // product: lane l of k-step ks, tile t holds C[16 ks + 8 (l / 32) + q][32 t + l % 32]
+    {
+      int e = 0;
+      std::frexp(cmax > 0 ? cmax : 1.0, &e);
+      const double cs = std::ldexp(1.0, 14 - e);
+      F->cscale = float(cs);
+      const int KS = F->JP / 16;
+      std::vector<_Float16> cp(size_t(KS) * kMixTiles * 2 * 64 * 8);
+      for (int ks = 0; ks < KS; ++ks)
+        for (int t = 0; t < kMixTiles; ++t)
+          for (int l = 0; l < 64; ++l)
+            for (int q = 0; q < 8; ++q) {
+              const double c = cd[size_t(16 * ks + 8 * (l / 32) + q) * F->KP + 32 * t + l % 32] * cs;
+              const _Float16 hi = _Float16(float(c));
+              const _Float16 lo = _Float16(float(c - double(float(hi))));
+              const size_t base = ((size_t(ks) * kMixTiles + t) * 2) * 64 * 8 + size_t(l) * 8 + q;
+              cp[base] = hi;
+              cp[base + 64 * 8] = lo;
+            }
+      F->Cp = falloc<_Float16>(cp.size());
+      fcopy(ctx, F->Cp, cp.data(), sizeof(_Float16) * cp.size(), hipMemcpyHostToDevice);
+    }
+    F->zmax = falloc<uint32_t>(1);
     // run buffers; the band products never touch the off-band bins, zeroed once
     F->Q = falloc<float2>(size_t(n));
     F->Qin = falloc<float2>(size_t(n));
@@ -547,11 +825,12 @@ rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_
   return RF_OK;
 }
 
-rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, void* z_out,
-                                   const rf_peak_args* fused) {
+rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec,
+                                   void* z_out, const rf_peak_args* fused) {
   if (!ctx) return RF_E_INVAL;
   return fguard(ctx, [&] {
     RF_CHECK(F && z_ref, "snr_reconstruct_factored: null pointer");
+    RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct_factored: unknown precision");
     RF_CHECK(n == F->n, "snr_reconstruct_factored: series length differs from the build");
     RF_CHECK(z_out || fused, "snr_reconstruct_factored: need z_out or fused read-out");
     if (fused) {
@@ -572,15 +851,19 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
       po.seg = 0;
       po.nk = F->nk;
     }
-    hipLaunchKernelGGL(k_conj, dim3(nblocks(n)), dim3(256), 0, ctx->stream, static_cast<const float2*>(z_ref), n,
-                       F->Qin);
+    fill_u32(ctx, F->zmax, 0u, 1);
+    hipLaunchKernelGGL(k_conj_max, dim3(nblocks(n)), dim3(256), 0, ctx->stream, static_cast<const float2*>(z_ref),
+                       n, F->Qin, F->zmax);
     RF_HIP(hipGetLastError());
     fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
     hipLaunchKernelGGL(k_band_products, dim3(nblocks(F->nb)), dim3(256), 0, ctx->stream, F->Q, F->Ub, n, F->b0,
                        F->nb, F->J, float(1.0 / double(n)), F->S);
     RF_HIP(hipGetLastError());
     fft_inverse_f32(ctx, F->S, F->Y, n, F->J);
-    mix_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
+    if (prec == RF_PREC_SPLIT_FP16)
+      mix16_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
+    else
+      mix_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
     if (fused && fused->cap > 0) {
       hipLaunchKernelGGL(k_trig_finish, dim3(nblocks(fused->cap, 1024)), dim3(256), 0, ctx->stream, fused->trig,
                          po.count, fused->cap);

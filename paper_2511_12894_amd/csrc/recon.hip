@@ -107,15 +107,6 @@ __device__ inline void zero(floatx16 (&a)[2][2]) {
 #pragma unroll
     for (int y = 0; y < 2; ++y) a[x][y] = floatx16{};
 }
-__device__ inline void fold(floatx16 (&tot)[2][2], floatx16 (&acc)[2][2]) {
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      tot[x][y] += acc[x][y];
-      acc[x][y] = floatx16{};
-    }
-}
 
 // FP64 running total of a wave's outputs: tot[tb][ri][i] (128 registers).
 struct Tot64 {

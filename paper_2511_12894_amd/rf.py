@@ -113,7 +113,7 @@ def load(path: str = LIB_PATH):
     lib.rf_factored_build.argtypes = [vp, vp, ctypes.POINTER(RfGrid), dbl, i32, ctypes.POINTER(vp)]
     lib.rf_factored_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
-    lib.snr_reconstruct_factored.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.snr_reconstruct_factored.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(RfPeakArgs)]
     lib.rf_factored_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "rf_last_error":
@@ -478,7 +478,7 @@ class Factored:
         return dict(J=j.value, m0=m0.value, len=ln.value, lam=list(lam), resid=list(res))
 
     def reconstruct(self, z_ref: torch.Tensor, z_out=None, store: bool = True, fused_thr: float | None = None,
-                    trig_cap: int = 4096):
+                    trig_cap: int = 4096, prec: str = "split16"):
         n = z_ref.numel()
         assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
         if store and z_out is None:
@@ -491,7 +491,7 @@ class Factored:
             trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
             fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
                                ctypes.pointer(cnt))
-        st = self.ctx.lib.snr_reconstruct_factored(self.ctx.h, self.h, _ptr(z_ref), n,
+        st = self.ctx.lib.snr_reconstruct_factored(self.ctx.h, self.h, _ptr(z_ref), n, PREC[prec],
                                                    _ptr(z_out) if store else None,
                                                    ctypes.byref(fused) if fused is not None else None)
         if st not in (RF_OK, RF_E_OVERFLOW):

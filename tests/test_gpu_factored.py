@@ -65,36 +65,41 @@ def small(rf, ctx):
     K.free()
 
 
-def test_full_rank_equals_the_exact_kernels(rf, ctx, small):
+PRECS = ["split16", "fp32"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_full_rank_equals_the_exact_kernels(rf, ctx, small, prec):
     """J = K: the projection is the identity, so the factored form must match the
     oracle's reconstruction with the exact truncated kernels."""
     w = small["w"]
     F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=16)
     assert F.info()["J"] == 16
-    z = F.reconstruct(small["z"])["z"].cpu().numpy()
+    z = F.reconstruct(small["z"], prec=prec)["z"].cpu().numpy()
     err = 0.0
     for k, kb in enumerate(small["ks"]):
         zo = orat.reconstruct(small["zr"], kb["m_lo"], kb["taps"], small["nr"] / small["norms"][k])
         err = max(err, np.abs(z[k] - zo).max())
-    _say(f"factored J=16 vs oracle exact kernels: max|dz| = {err:.3e}")
+    _say(f"factored {prec} J=16 vs oracle exact kernels: max|dz| = {err:.3e}")
     assert err <= 1e-5
     F.free()
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("J", [3, 8])
-def test_rank_j_matches_the_oracle_projection(rf, ctx, small, J):
+def test_rank_j_matches_the_oracle_projection(rf, ctx, small, J, prec):
     w = small["w"]
     F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=J)
     info = F.info()
     m0, Wt, res = orat.project_kernel_set([(k["m_lo"], k["taps"]) for k in small["ks"]], J)
     assert info["J"] == J and info["m0"] == m0 and info["len"] == Wt.shape[1]
     np.testing.assert_allclose(info["resid"], res, rtol=1e-6, atol=1e-12)
-    z = F.reconstruct(small["z"])["z"].cpu().numpy()
+    z = F.reconstruct(small["z"], prec=prec)["z"].cpu().numpy()
     err = 0.0
     for k in range(len(small["ks"])):
         zo = orat.reconstruct(small["zr"], m0, Wt[k], small["nr"] / small["norms"][k])
         err = max(err, np.abs(z[k] - zo).max())
-    _say(f"factored J={J} vs oracle projection: max|dz| = {err:.3e}")
+    _say(f"factored {prec} J={J} vs oracle projection: max|dz| = {err:.3e}")
     assert err <= 1e-5
     F.free()
 
@@ -123,7 +128,8 @@ def real64(rf, ctx):
     K.free()
 
 
-def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64):
+@pytest.mark.parametrize("prec", PRECS)
+def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64, prec):
     w = real64["w"]
     g = w["grid"]
     F = rf.Factored(ctx, real64["K"], g, tol=2e-6, jmax=128)
@@ -131,7 +137,7 @@ def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64):
     J = info["J"]
     _say(f"realistic-64s: J = {J}, max residual {max(info['resid']):.2e}")
     assert max(info["resid"]) <= 2e-6
-    out = F.reconstruct(real64["z"], fused_thr=6.0, trig_cap=1 << 14)
+    out = F.reconstruct(real64["z"], fused_thr=6.0, trig_cap=1 << 14, prec=prec)
     z = out["z"]
     # sampled outputs against the oracle with its own projection of the same kernels
     m0, Wt, _ = orat.project_kernel_set([(k["m_lo"], k["taps"]) for k in real64["ks"]], J)
@@ -143,12 +149,12 @@ def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64):
     for k in range(0, len(real64["ks"]), 7):
         zo = orat.reconstruct_samples(real64["zr"], m0, Wt[k], real64["nr"] / real64["norms"][k], idx)
         err = max(err, np.abs(zh[k, idx] - zo).max())
-    _say(f"realistic-64s factored vs oracle projection (sampled): {err:.3e}")
+    _say(f"realistic-64s factored {prec} vs oracle projection (sampled): {err:.3e}")
     assert err <= 1e-5
     # every sample against direct matched filtering on the GPU
     zd, _ = rf.mf_ref_snr(ctx, g, real64["xf"], real64["psd"], w["nbrs"])
     ed = (z - zd).abs().max().item()
-    _say(f"realistic-64s factored vs direct MF: {ed:.3e}")
+    _say(f"realistic-64s factored {prec} vs direct MF: {ed:.3e}")
     assert ed <= 2e-4
     # fused read-out = read-out of the stored series
     ref = rf.snr_peaks(ctx, z, 6.0, trig_cap=1 << 14)
@@ -166,21 +172,38 @@ def test_realistic_against_oracle_and_direct_mf(rf, ctx, real64):
     F.free()
 
 
-def test_ragged_kernel_count_and_fused_only(rf, ctx):
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_kernel_count_and_fused_only(rf, ctx, prec):
     """24 kernels (a partial 32-kernel tile), read-out without storing."""
     w = synth.workload_small()
     g = w["grid"]
     nbrs = synth.neighbour_lattice(*w["ref"], g.f_low, 24)
     xf, psd, K, z = _gpu_inputs(rf, ctx, w, nbrs)
     F = rf.Factored(ctx, K, g, tol=1e-4, jmax=24)
-    full = F.reconstruct(z)["z"]
-    fused = F.reconstruct(z, store=False, fused_thr=5.0)
+    full = F.reconstruct(z, prec=prec)["z"]
+    fused = F.reconstruct(z, store=False, fused_thr=5.0, prec=prec)
     ref = rf.snr_peaks(ctx, full, 5.0)
     torch.cuda.synchronize()
     assert torch.equal(fused["peaks"], ref["peaks"])
     assert set(rf.decode_triggers(fused["trig"], fused["ntrig"])) == set(rf.decode_triggers(ref["trig"], ref["ntrig"]))
     F.free()
     K.free()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_power_of_two_scaling_is_exact(rf, ctx, small, prec):
+    """Scaling z_ref by 2^e scales every output by exactly 2^e (the FP16 split
+    takes its scale from the series' maximum, so its parts do not change), and
+    a zero series reconstructs to zeros."""
+    w = small["w"]
+    F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=8)
+    z1 = F.reconstruct(small["z"], prec=prec)["z"].clone()
+    for e in (-20, 7):
+        ze = F.reconstruct(small["z"] * (2.0 ** e), prec=prec)["z"]
+        assert torch.equal(ze, z1 * (2.0 ** e)), e
+    z0 = F.reconstruct(torch.zeros_like(small["z"]), prec=prec)["z"]
+    assert torch.count_nonzero(z0).item() == 0
+    F.free()
 
 
 def test_argument_errors(rf, ctx, small):
@@ -196,4 +219,7 @@ def test_argument_errors(rf, ctx, small):
     with pytest.raises(rf.RfError) as e:
         F.reconstruct(short)
     assert e.value.code == rf.RF_E_INVAL
+    st = ctx.lib.snr_reconstruct_factored(ctx.h, F.h, small["z"].data_ptr(), w["grid"].n, 7,
+                                          small["z"].data_ptr(), None)
+    assert st == rf.RF_E_INVAL
     F.free()

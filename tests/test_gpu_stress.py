@@ -89,11 +89,13 @@ def test_reconstruction(rf, st, prec):
     del z, out
 
 
-def test_factored(rf, st):
+@pytest.mark.parametrize("prec", ["split16", "fp32"])
+def test_factored(rf, st, prec):
     F = rf.Factored(st["ctx"], st["K"], st["g"], tol=2e-6, jmax=48)
     J = F.info()["J"]
-    z = F.reconstruct(st["z"])["z"]
+    z = F.reconstruct(st["z"], prec=prec)["z"]
     ed = (z - st["zd"]).abs().max().item()
-    _say(f"stress factored: J = {J}, vs direct MF {ed:.3e}")
+    _say(f"stress factored {prec}: J = {J}, vs direct MF {ed:.3e}")
     assert ed <= 2e-4
+    del z
     F.free()
