@@ -207,6 +207,54 @@ def factored_leg(dev, ctx, w, psd, xf, K, steps, tol=2e-6, precs=("split16", "fp
     return res
 
 
+def ols_leg(dev, ctx, w, psd, xf, K, steps):
+    """Blocked frequency-domain (overlap-save) reconstruction of the same 256
+    series with the exact truncated kernels, fused read-out, series stored;
+    timed like the step, with its error against direct MF."""
+    g = w["grid"]
+    n = g.n
+    nbrs = w["nbrs"]
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    O = rf.Ols(ctx, K, n)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = O.info()
+    zref = torch.empty((1, n), dtype=torch.complex64, device=dev)
+    zout = torch.empty((len(nbrs), n), dtype=torch.complex64, device=dev)
+    rec = []
+
+    def step():
+        rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"]], z=zref, want_sigma=False)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = O.reconstruct(zref[0], z_out=zout, fused_thr=6.0, trig_cap=1 << 16)
+        b.record(stream)
+        rec.append((a, b))
+        return out
+
+    wall, _ = timed(step, steps, 2, stream)
+    rms = float(np.mean([a.elapsed_time(b) for a, b in rec[-steps:]]))
+    last = step()
+    zd, _ = rf.mf_ref_snr(ctx, g, xf, psd, nbrs, want_sigma=False)
+    err = (zout - zd).abs().max().item()
+    del zd
+    ms = wall / steps
+    nb = n // info["hop"]
+    parts = sum(info["parts"])
+    # per block and kernel: P complex MACs per bin, one 8192-point transform (5 B log2 B flops)
+    flops = nb * (parts * info["block"] * 8 + len(nbrs) * 5 * info["block"] * 13)
+    res = dict(block=info["block"], hop=info["hop"], partitions_max=info["pmax"], partitions_total=parts,
+               spectra_bytes=info["spectra_bytes"], build_s=t_build, step_ms=ms, recon_ms=rms,
+               value=(1 + len(nbrs)) * n / (ms * 1e-3), unit="template-samples/s", err_vs_direct_mf=err,
+               ntrig=last["ntrig"], fft_mac_flops=flops,
+               vector_fp32_frac=flops / (rms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS)
+    O.free()
+    return res
+
+
 def learned_leg(dev, w, psd, xf, K_exact, build_s, steps):
     stream = torch.cuda.Stream(dev)          # training replays a captured graph: not the null stream
     ctx = rf.Context(0, stream)
@@ -316,7 +364,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nbrs", type=int, default=24)
-    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,factored,batched,learned")
+    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,factored,ols,batched,learned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -324,7 +372,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "batched", "learned"}
+    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "ols", "batched",
+                                                        "learned"}
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -411,6 +460,9 @@ def main():
     if "factored" in legs:
         log("bench: factored reconstruction through the kernel-set basis")
         res["factored"] = factored_leg(dev, ctx, w, psd, xf, K, args.steps)
+    if "ols" in legs:
+        log("bench: blocked frequency-domain (overlap-save) reconstruction")
+        res["ols"] = ols_leg(dev, ctx, w, psd, xf, K, args.steps)
     if "batched" in legs:
         log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
@@ -458,6 +510,8 @@ def main():
         extra["err_vs_direct_mf"] = res["err_vs_direct"]
     if "factored" in res:
         extra["factored"] = res["factored"]
+    if "ols" in res:
+        extra["ols"] = res["ols"]
     if "batched" in res:
         extra["batched"] = res["batched"]
     if "learned" in res:

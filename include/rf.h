@@ -294,6 +294,37 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
                                    void* z_out, const rf_peak_args* fused);
 rf_status rf_factored_free(rf_factored* F);
 
+/* ---- blocked frequency-domain reconstruction (overlap-save) ----
+ *
+ * The correlation of sec. II.B (eq. `convolution`) with the exact truncated
+ * kernels, computed per block of H = 4096 outputs with transforms of
+ * B = 8192 points (sec. IV computes it with an FFT convolution of this kind on
+ * the CPU).  Each kernel is cut into P_k partitions of H taps aligned to a
+ * 2048-tap grid from the set's first tap; its partition spectra (B complex
+ * values each) are built once in FP64 and kept in FP32.  A reconstruction
+ * transforms every input block once (exp(-) DFT) and, per kernel and block,
+ * sums the products with the partition spectra and inverse transforms.  Not
+ * the paper's data layout.
+ */
+typedef struct rf_ols rf_ols;
+
+/* Plan for kernel set K on series of n samples (a power of two in
+ * [4096, 2^24]): partition spectra of every kernel and the block-spectrum
+ * buffers (2 x 2n complex64 at most).  Kernels of more than 4 partitions (over
+ * about 14k taps) work but read their spectra from the cache per block.
+ * Synchronises. */
+rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out);
+/* Host copies (any may be NULL): transform length B, hop H, largest partition
+ * count, partitions of each kernel [nk], bytes of partition spectra. */
+rf_status rf_ols_info(const rf_ols* O, int32_t* block, int32_t* hop, int32_t* pmax, int32_t* parts,
+                      int64_t* spectra_bytes);
+/* As snr_reconstruct (same kernels, same output and fused read-out), for the
+ * n the plan was built for; FP32 transforms and products.  Synchronises when
+ * fused. */
+rf_status snr_reconstruct_ols(rf_ctx* ctx, const rf_ols* O, const void* z_ref, int64_t n, void* z_out,
+                              const rf_peak_args* fused);
+rf_status rf_ols_free(rf_ols* O);
+
 #ifdef __cplusplus
 }
 #endif

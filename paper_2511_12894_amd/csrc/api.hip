@@ -46,27 +46,6 @@ void validate_tmpl(const rf_tmpl& t) {
            "template masses must be positive");
 }
 
-template <typename F>
-rf_status guarded(rf_ctx* ctx, F&& f) {
-  try {
-    if (ctx) {
-      hipError_t e = hipSetDevice(ctx->device);
-      if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e)};
-    }
-    f();
-    return RF_OK;
-  } catch (const Error& e) {
-    if (ctx) ctx->last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (ctx) ctx->last_error = "host allocation failed";
-    return RF_E_NOMEM;
-  } catch (...) {
-    if (ctx) ctx->last_error = "unexpected exception";
-    return RF_E_HIP;
-  }
-}
-
 // Small per-call tables: staged in a host copy owned by the context (so the
 // source outlives an asynchronous copy), then copied on the context stream.
 template <typename T>

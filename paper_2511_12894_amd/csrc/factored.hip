@@ -607,25 +607,14 @@ void fcopy(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind 
   RF_HIP(hipStreamSynchronize(ctx->stream));
 }
 
-template <typename Fn>
-rf_status fguard(rf_ctx* ctx, Fn&& f) {
-  try {
-    RF_HIP(hipSetDevice(ctx->device));
-    f();
-    return RF_OK;
-  } catch (const Error& e) {
-    ctx->last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    ctx->last_error = "host allocation failed";
-    return RF_E_NOMEM;
-  } catch (const std::exception& e) {
-    ctx->last_error = e.what();
-    return RF_E_HIP;
-  }
+}  // namespace
+
+void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count, int64_t cap) {
+  if (cap <= 0) return;
+  hipLaunchKernelGGL(k_trig_finish, dim3(nblocks(cap, 1024)), dim3(256), 0, ctx->stream, trig, count, cap);
+  RF_HIP(hipGetLastError());
 }
 
-}  // namespace
 }  // namespace rf
 
 using namespace rf;
@@ -637,7 +626,7 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
   if (!ctx) return RF_E_INVAL;
   rf_factored* F = nullptr;
   double* W = nullptr;
-  rf_status st = fguard(ctx, [&] {
+  rf_status st = guarded(ctx, [&] {
     validate_grid(grid);
     RF_CHECK(K && out, "rf_factored_build: null pointer");
     *out = nullptr;
@@ -828,7 +817,7 @@ rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_
 rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec,
                                    void* z_out, const rf_peak_args* fused) {
   if (!ctx) return RF_E_INVAL;
-  return fguard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_CHECK(F && z_ref, "snr_reconstruct_factored: null pointer");
     RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct_factored: unknown precision");
     RF_CHECK(n == F->n, "snr_reconstruct_factored: series length differs from the build");
@@ -864,11 +853,7 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
       mix16_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
     else
       mix_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
-    if (fused && fused->cap > 0) {
-      hipLaunchKernelGGL(k_trig_finish, dim3(nblocks(fused->cap, 1024)), dim3(256), 0, ctx->stream, fused->trig,
-                         po.count, fused->cap);
-      RF_HIP(hipGetLastError());
-    }
+    if (fused) trig_finish(ctx, fused->trig, po.count, fused->cap);
     if (fused) {
       peaks_finalize(ctx, packed, F->nk, fused->peaks);
       unsigned long long cnt = 0;

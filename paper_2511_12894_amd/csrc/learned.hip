@@ -575,24 +575,6 @@ void predict_into(rf_ctx* ctx, rf_surrogate* s, const rf_tmpl& ref, const rf_tmp
   RF_HIP(hipGetLastError());
 }
 
-template <typename F>
-rf_status guard(rf_ctx* ctx, F&& f) {
-  try {
-    if (ctx) RF_HIP(hipSetDevice(ctx->device));
-    f();
-    return RF_OK;
-  } catch (const Error& e) {
-    if (ctx) ctx->last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    if (ctx) ctx->last_error = "host allocation failed";
-    return RF_E_NOMEM;
-  } catch (...) {
-    if (ctx) ctx->last_error = "unexpected exception";
-    return RF_E_HIP;
-  }
-}
-
 }  // namespace
 }  // namespace rf
 
@@ -605,7 +587,7 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
                               int32_t nomega, rf_surrogate** out) {
   if (!ctx) return RF_E_INVAL;
   rf_surrogate* s = nullptr;
-  rf_status st = guard(ctx, [&] {
+  rf_status st = guarded(ctx, [&] {
     validate_grid(grid);
     RF_CHECK(refs && nbrs && omega && out, "rf_surrogate_create: null pointer");
     RF_CHECK(npair >= 8, "rf_surrogate_create: need at least 8 pairs");
@@ -745,7 +727,7 @@ rf_status rf_surrogate_info(const rf_surrogate* s, int32_t* window, int32_t* ran
 
 rf_status rf_surrogate_set_params(rf_ctx* ctx, rf_surrogate* s, const float* theta) {
   if (!ctx || !s || !theta) return RF_E_INVAL;
-  return guard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_HIP(hipMemcpyAsync(s->theta, theta, sizeof(float) * mlpdef::kParams, hipMemcpyDeviceToDevice, ctx->stream));
     fill_u32(ctx, reinterpret_cast<uint32_t*>(s->m1), 0u, mlpdef::kParams);   // +0.0f
     fill_u32(ctx, reinterpret_cast<uint32_t*>(s->m2), 0u, mlpdef::kParams);
@@ -758,7 +740,7 @@ rf_status rf_surrogate_set_params(rf_ctx* ctx, rf_surrogate* s, const float* the
 
 rf_status rf_surrogate_get_params(rf_ctx* ctx, const rf_surrogate* s, float* theta) {
   if (!ctx || !s || !theta) return RF_E_INVAL;
-  return guard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_HIP(hipMemcpyAsync(theta, s->theta, sizeof(float) * mlpdef::kParams, hipMemcpyDeviceToDevice, ctx->stream));
     RF_HIP(hipStreamSynchronize(ctx->stream));
   });
@@ -767,7 +749,7 @@ rf_status rf_surrogate_get_params(rf_ctx* ctx, const rf_surrogate* s, float* the
 rf_status rf_surrogate_grad(rf_ctx* ctx, rf_surrogate* s, const float* x, const float* t, int32_t rows,
                             float* loss_host, float* grad_out) {
   if (!ctx || !s) return RF_E_INVAL;
-  return guard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_CHECK(x && t && grad_out && rows >= 1, "rf_surrogate_grad: bad arguments");
     ensure_batch(s, rows);
     mlp_forward(ctx, s->theta, x, rows, s->pre, s->act, s->out);
@@ -789,7 +771,7 @@ rf_status rf_surrogate_grad(rf_ctx* ctx, rf_surrogate* s, const float* x, const 
 rf_status rf_surrogate_train(rf_ctx* ctx, rf_surrogate* s, const int32_t* order, int32_t steps, int32_t batch,
                              float lr, float* loss_host) {
   if (!ctx || !s) return RF_E_INVAL;
-  return guard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_CHECK(order && steps >= 1 && batch >= 1, "rf_surrogate_train: bad arguments");
     RF_CHECK(ctx->stream != nullptr, "rf_surrogate_train: needs a non-null stream (graph capture)");
     ensure_batch(s, batch);
@@ -849,7 +831,7 @@ rf_status rf_surrogate_train(rf_ctx* ctx, rf_surrogate* s, const int32_t* order,
 rf_status rf_surrogate_predict(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
                                void* coeffs) {
   if (!ctx || !s) return RF_E_INVAL;
-  return guard(ctx, [&] {
+  return guarded(ctx, [&] {
     RF_CHECK(nbr && coeffs && nk >= 1, "rf_surrogate_predict: bad arguments");
     predict_into(ctx, s, ref, nbr, nk, static_cast<double2*>(coeffs));
     RF_HIP(hipStreamSynchronize(ctx->stream));
@@ -860,7 +842,7 @@ rf_status rf_surrogate_project(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const 
                                void* coeffs) {
   if (!ctx || !s) return RF_E_INVAL;
   double2* H = nullptr;
-  rf_status st = guard(ctx, [&] {
+  rf_status st = guarded(ctx, [&] {
     RF_CHECK(nbr && coeffs && nk >= 1, "rf_surrogate_project: bad arguments");
     const int L = s->window;
     std::vector<rf_tmpl> refs(size_t(nk), ref);
@@ -883,7 +865,7 @@ rf_status rf_surrogate_kernels(rf_ctx* ctx, rf_surrogate* s, const rf_grid* grid
   rf_kernels* KE = nullptr;
   double2* coef = nullptr;
   double2* Hk = nullptr;
-  rf_status st = guard(ctx, [&] {
+  rf_status st = guarded(ctx, [&] {
     validate_grid(grid);
     RF_CHECK(psd && nbr && out && nk >= 1, "rf_surrogate_kernels: bad arguments");
     RF_CHECK(grid->fs == s->grid.fs && grid->f_low == s->grid.f_low && grid->f_high == s->grid.f_high &&

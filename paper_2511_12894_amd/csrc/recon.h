@@ -76,5 +76,8 @@ void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const
                  int ntiles, int64_t max_ksteps);
 void peaks_launch(rf_ctx* ctx, const float2* z, int nt, int64_t n, const PeakOut& po);
 void peaks_finalize(rf_ctx* ctx, const uint64_t* packed, int64_t count, rf_peak* out);
+// Trigger records written with the raw (re, im) in (absz, argz): replace them by
+// |z| and arg z as every read-out writes them (the first min(*count, cap)).
+void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count, int64_t cap);
 
 }  // namespace rf

@@ -53,6 +53,29 @@ struct rf_ctx {
 
 namespace rf {
 
+// Run f for an entry point: errors become the returned status, their message
+// the context's last error.
+template <typename F>
+rf_status guarded(rf_ctx* ctx, F&& f) {
+  try {
+    if (ctx) {
+      hipError_t e = hipSetDevice(ctx->device);
+      if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e)};
+    }
+    f();
+    return RF_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return RF_E_NOMEM;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unexpected exception";
+    return RF_E_HIP;
+  }
+}
+
 enum WsSlot {
   WS_FFT_A = 0, WS_FFT_B = 1, WS_RED = 2, WS_SPLIT = 3, WS_PEAK = 4, WS_COEF = 5, WS_BUILD = 6,
   WS_Y = 7, WS_SCALAR = 8, WS_SCAN = 9, WS_TGT = 10

@@ -28,7 +28,7 @@ EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "r
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
             "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
             "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
-            "rf_factored_free",
+            "rf_factored_free", "rf_ols_build", "rf_ols_info", "snr_reconstruct_ols", "rf_ols_free",
             "rf_surrogate_free")
 
 
@@ -115,6 +115,11 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.snr_reconstruct_factored.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(RfPeakArgs)]
     lib.rf_factored_free.argtypes = [vp]
+    lib.rf_ols_build.argtypes = [vp, vp, i64, ctypes.POINTER(vp)]
+    lib.rf_ols_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.snr_reconstruct_ols.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.rf_ols_free.argtypes = [vp]
     for name in EXPORTED:
         if name != "rf_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -504,6 +509,62 @@ class Factored:
     def free(self):
         if getattr(self, "h", None):
             self.ctx.lib.rf_factored_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Ols:
+    """rf_ols: blocked frequency-domain (overlap-save) plan of a kernel set for
+    series of n samples."""
+
+    def __init__(self, ctx: Context, kernels: Kernels, n: int):
+        self.ctx = ctx
+        self.nk = kernels.nk
+        self.n = int(n)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        ctx.check(ctx.lib.rf_ols_build(ctx.h, kernels.h, self.n, ctypes.byref(h)))
+        self.h = h
+
+    def info(self):
+        b, hop, pmax = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        parts = (ctypes.c_int32 * self.nk)()
+        nbytes = ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.rf_ols_info(self.h, ctypes.byref(b), ctypes.byref(hop), ctypes.byref(pmax), parts,
+                                                ctypes.byref(nbytes)))
+        return dict(block=b.value, hop=hop.value, pmax=pmax.value, parts=list(parts), spectra_bytes=nbytes.value)
+
+    def reconstruct(self, z_ref: torch.Tensor, z_out=None, store: bool = True, fused_thr: float | None = None,
+                    trig_cap: int = 4096):
+        n = z_ref.numel()
+        assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
+        if store and z_out is None:
+            z_out = torch.empty((self.nk, n), dtype=torch.complex64, device=z_ref.device)
+        fused = None
+        peaks = trig = None
+        cnt = ctypes.c_int64(0)
+        if fused_thr is not None:
+            peaks = torch.empty((self.nk, 2), dtype=torch.int32, device=z_ref.device)
+            trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
+            fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
+                               ctypes.pointer(cnt))
+        st = self.ctx.lib.snr_reconstruct_ols(self.ctx.h, self.h, _ptr(z_ref), n, _ptr(z_out) if store else None,
+                                              ctypes.byref(fused) if fused is not None else None)
+        if st not in (RF_OK, RF_E_OVERFLOW):
+            self.ctx.check(st)
+        out = dict(z=z_out if store else None)
+        if fused is not None:
+            out.update(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+        return out
+
+    def free(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rf_ols_free(self.h)
             self.h = None
 
     def __del__(self):

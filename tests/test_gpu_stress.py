@@ -99,3 +99,23 @@ def test_factored(rf, st, prec):
     assert ed <= 2e-4
     del z
     F.free()
+
+
+def test_ols(rf, st):
+    """Kernels of 16k-28k taps: up to 8 partitions, spectra read per block."""
+    O = rf.Ols(st["ctx"], st["K"], st["g"].n)
+    info = O.info()
+    assert info["pmax"] > 4
+    z = O.reconstruct(st["z"])["z"]
+    ed = (z - st["zd"]).abs().max().item()
+    zh = z.cpu().numpy()
+    eo = 0.0
+    for k in st["picks"]:
+        kb = st["oks"][k]
+        zo = orat.reconstruct_samples(st["zr"], kb["m_lo"], kb["taps"], st["nr"] / st["onr"][k], st["idx"])
+        eo = max(eo, np.abs(zh[k, st["idx"]] - zo).max())
+    _say(f"stress ols: partitions up to {info['pmax']}, vs direct MF {ed:.3e}, vs oracle (sampled) {eo:.3e}")
+    assert eo <= 1e-5
+    assert ed <= 2e-4
+    del z
+    O.free()
