@@ -255,6 +255,46 @@ def ols_leg(dev, ctx, w, psd, xf, K, steps):
     return res
 
 
+def bank_leg(dev, ctx, w, psd):
+    """Bank organisation (sec. III.A) on a synthetic stochastic 1-3 Msun bank at
+    f_low = 20 Hz (stand-in for the paper's minimal-match-0.97 bank): chirp-mass
+    bisection to a 10 s duration spread, symmetric-mass-ratio bisection to 500
+    templates, median-duration references; then every dependent's ratio kernel
+    built on the GPU at the realistic grid (4096 Hz, 2^21 samples, 1e-3 / s)
+    for the storage figure (template durations over kernel durations)."""
+    g = w["grid"]
+    t0 = time.perf_counter()
+    bank = synth.stochastic_bank(f0=g.f_low)
+    t_place = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tau = rf.template_durations(bank, g.f_low)
+    grp, refs = rf.bank_organise(bank, tau, max_spread=10.0, max_size=500)
+    t_org = time.perf_counter() - t0
+    sizes = np.bincount(grp)
+    spreads = [float(np.ptp(tau[grp == i])) for i in range(len(refs))]
+    dep_tau = 0.0
+    dep_taps = 0
+    t0 = time.perf_counter()
+    for gi, r in enumerate(refs):
+        members = [int(i) for i in np.nonzero(grp == gi)[0] if i != r]
+        if not members:
+            continue
+        K = rf.ratio_kernel_build(ctx, g, psd, bank[r], [bank[i] for i in members])
+        dep_taps += int(sum(K.info()["len"]))
+        dep_tau += float(tau[members].sum())
+        K.free()
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    kernel_s = dep_taps / g.fs
+    return dict(templates=len(bank), groups=len(refs), group_size_min=int(sizes.min()),
+                group_size_median=float(np.median(sizes)), group_size_max=int(sizes.max()),
+                duration_spread_max_s=max(spreads), template_duration_s=dict(min=float(tau.min()),
+                                                                             max=float(tau.max())),
+                placement_s=t_place, organise_s=t_org, kernel_build_s=t_build, dependents=len(bank) - len(refs),
+                storage_ratio_dependents=dep_tau / kernel_s, storage_ratio_bank=float(tau.sum()) / kernel_s,
+                kernel_taps_total=dep_taps)
+
+
 def learned_leg(dev, w, psd, xf, K_exact, build_s, steps):
     stream = torch.cuda.Stream(dev)          # training replays a captured graph: not the null stream
     ctx = rf.Context(0, stream)
@@ -364,7 +404,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nbrs", type=int, default=24)
-    ap.add_argument("--only", default="", help="comma list of legs to run: step,fp32,direct,factored,ols,batched,learned")
+    ap.add_argument("--only", default="",
+                    help="comma list of legs to run: step,fp32,direct,factored,ols,bank,batched,learned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -372,8 +413,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "ols", "batched",
-                                                        "learned"}
+    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "ols", "bank",
+                                                        "batched", "learned"}
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -463,6 +504,9 @@ def main():
     if "ols" in legs:
         log("bench: blocked frequency-domain (overlap-save) reconstruction")
         res["ols"] = ols_leg(dev, ctx, w, psd, xf, K, args.steps)
+    if "bank" in legs:
+        log("bench: bank organisation and storage")
+        res["bank"] = bank_leg(dev, ctx, w, psd)
     if "batched" in legs:
         log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
@@ -512,6 +556,8 @@ def main():
         extra["factored"] = res["factored"]
     if "ols" in res:
         extra["ols"] = res["ols"]
+    if "bank" in res:
+        extra["bank"] = res["bank"]
     if "batched" in res:
         extra["batched"] = res["batched"]
     if "learned" in res:

@@ -325,6 +325,27 @@ rf_status snr_reconstruct_ols(rf_ctx* ctx, const rf_ols* O, const void* z_ref, i
                               const rf_peak_args* fused);
 rf_status rf_ols_free(rf_ols* O);
 
+/* ---- template bank organisation (host only, no device work) ----
+ *
+ * Section III.A (template bank construction): sets of one reference and its
+ * dependent templates.  The bank, ordered by chirp mass, is halved again and
+ * again until every subset's durations differ by at most max_spread (10 s in
+ * the paper); subsets of more than max_size templates (500) are halved along
+ * symmetric mass ratio until none is larger; each set's reference minimises
+ * the summed absolute duration difference to the set (a median duration: the
+ * lower one for an even count, the first in the set's order among equal
+ * durations).  Odd counts put the smaller half first; sorts are stable from
+ * bank order.
+ */
+/* tau[i] = t_c - t(f_low) of template t[i] (TaylorF2, sec. II.C), seconds. */
+rf_status rf_template_durations(const rf_tmpl* t, int64_t n, double f_low, double* tau);
+/* t[n], tau[n] host inputs (any durations, e.g. from rf_template_durations);
+ * group[n] receives each template's set; reference[] (room for n entries)
+ * the bank index of each set's reference; *ngroups the number of sets.  Sets
+ * are numbered in chirp-mass order, then symmetric-mass-ratio order. */
+rf_status rf_bank_organise(const rf_tmpl* t, const double* tau, int64_t n, double max_spread, int32_t max_size,
+                           int32_t* group, int64_t* reference, int32_t* ngroups);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,5 +7,5 @@ hipcc --offload-arch=gfx950 -O3 -std=c++17 -fPIC -shared \
   -Xclang -target-feature -Xclang -packed-fp32-ops \
   -Wall -Wno-unused-result \
   -o "$out.tmp" \
-  "$here/csrc/api.hip" "$here/csrc/fft.hip" "$here/csrc/spectra.hip" "$here/csrc/recon.hip" "$here/csrc/batch.hip" "$here/csrc/learned.hip" "$here/csrc/factored.hip" "$here/csrc/ols.hip"
+  "$here/csrc/api.hip" "$here/csrc/fft.hip" "$here/csrc/spectra.hip" "$here/csrc/recon.hip" "$here/csrc/batch.hip" "$here/csrc/learned.hip" "$here/csrc/factored.hip" "$here/csrc/ols.hip" "$here/csrc/bank.hip"
 mv -f "$out.tmp" "$out"

@@ -29,7 +29,7 @@ EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "r
             "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
             "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
             "rf_factored_free", "rf_ols_build", "rf_ols_info", "snr_reconstruct_ols", "rf_ols_free",
-            "rf_surrogate_free")
+            "rf_template_durations", "rf_bank_organise", "rf_surrogate_free")
 
 
 class RfGrid(ctypes.Structure):
@@ -120,6 +120,9 @@ def load(path: str = LIB_PATH):
                                 ctypes.POINTER(i32), ctypes.POINTER(i64)]
     lib.snr_reconstruct_ols.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(RfPeakArgs)]
     lib.rf_ols_free.argtypes = [vp]
+    lib.rf_template_durations.argtypes = [ctypes.POINTER(RfTmpl), i64, dbl, ctypes.POINTER(dbl)]
+    lib.rf_bank_organise.argtypes = [ctypes.POINTER(RfTmpl), ctypes.POINTER(dbl), i64, dbl, i32,
+                                     ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32)]
     for name in EXPORTED:
         if name != "rf_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -572,3 +575,34 @@ class Ols:
             self.free()
         except Exception:
             pass
+
+
+def template_durations(bank, f_low: float):
+    """tau(f_low) of each (m1, m2) (host computation in the library)."""
+    import numpy as np
+    lib = load()
+    n = len(bank)
+    arr = (RfTmpl * max(n, 1))(*[RfTmpl(float(a), float(b)) for a, b in bank])
+    out = np.zeros(n, dtype=np.float64)
+    st = lib.rf_template_durations(arr, n, float(f_low), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st != RF_OK:
+        raise RfError(st, "rf_template_durations failed")
+    return out
+
+
+def bank_organise(bank, tau, max_spread: float = 10.0, max_size: int = 500):
+    """(group of each template, reference index of each group) from the library."""
+    import numpy as np
+    lib = load()
+    n = len(bank)
+    arr = (RfTmpl * max(n, 1))(*[RfTmpl(float(a), float(b)) for a, b in bank])
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    group = np.zeros(n, dtype=np.int32)
+    ref = np.zeros(max(n, 1), dtype=np.int64)
+    ng = ctypes.c_int32()
+    st = lib.rf_bank_organise(arr, tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, float(max_spread),
+                              int(max_size), group.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              ref.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(ng))
+    if st != RF_OK:
+        raise RfError(st, "rf_bank_organise failed")
+    return group, ref[:ng.value].copy()

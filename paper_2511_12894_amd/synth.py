@@ -226,6 +226,58 @@ def neighbour_lattice(m1: float, m2: float, f0: float, count: int):
         radius *= 2
 
 
+def stochastic_bank(f0: float = 20.0, m_range=(1.0, 3.0), seed: int = 1006, fiducial=(1.6, 1.2),
+                    sub: int = 4):
+    """Stand-in for a minimal-match-0.97 stochastic placement over m1, m2 in
+    `m_range`: candidates on a jittered grid of 1/`sub` lattice step in
+    (tau0, tau3), visited in seeded random order, are accepted when no
+    accepted point lies within one lattice step (the steps of
+    `neighbour_lattice` at the fiducial masses, taken as constant: the metric
+    is nearly flat in chirp times).  Returns a list of (m1, m2), m1 >= m2, in
+    acceptance order."""
+    lo_m, hi_m = m_range
+    t0f, t3f = chirp_times(*fiducial, f0)
+    d0 = 5.0 / 3.0 * _DMC_REL * t0f
+    d3 = 3.0 / 5.0 * _DETA_REL * t3f
+    corners = [chirp_times(a, b, f0) for a in (lo_m, hi_m) for b in (lo_m, hi_m)]
+    u0, u1 = min(c[0] for c in corners) / d0, max(c[0] for c in corners) / d0
+    v0, v1 = min(c[1] for c in corners) / d3, max(c[1] for c in corners) / d3
+    rng = np.random.default_rng(seed)
+    uu, vv = np.meshgrid(np.arange(u0, u1, 1.0 / sub), np.arange(v0, v1, 1.0 / sub), indexing="ij")
+    cand = np.column_stack([uu.ravel(), vv.ravel()]) + rng.uniform(0.0, 1.0 / sub, (uu.size, 2))
+    cand = cand[rng.permutation(len(cand))]
+    # the physical part of the mass range (vectorised masses_from_chirp_times)
+    t0, t3 = cand[:, 0] * d0, cand[:, 1] * d3
+    mt = 5.0 * t3 / (32.0 * math.pi ** 2 * f0 * t0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        eta = (math.pi * mt * f0) ** (-2.0 / 3.0) / (8.0 * f0 * t3)
+        dd = np.sqrt(np.maximum(0.0, 1.0 - 4.0 * eta))
+    m = mt / T_SUN_S
+    m1, m2 = 0.5 * m * (1.0 + dd), 0.5 * m * (1.0 - dd)
+    keep = (eta > 0.0) & (eta <= 0.25) & (mt > 0.0) & (m2 >= lo_m) & (m1 <= hi_m)
+    cells = {}
+    bank = []
+    for u, v, a, b in zip(cand[keep, 0].tolist(), cand[keep, 1].tolist(), m1[keep].tolist(), m2[keep].tolist()):
+        ms = (a, b)
+        cu, cv = int(math.floor(u)), int(math.floor(v))
+        near = False
+        for du in (-1, 0, 1):
+            for dv in (-1, 0, 1):
+                for (pu, pv) in cells.get((cu + du, cv + dv), ()):
+                    if (pu - u) ** 2 + (pv - v) ** 2 < 1.0:
+                        near = True
+                        break
+                if near:
+                    break
+            if near:
+                break
+        if near:
+            continue
+        cells.setdefault((cu, cv), []).append((u, v))
+        bank.append(ms)
+    return bank
+
+
 # ------------------------------------------------------------------ workloads
 
 def workload_small():
