@@ -86,9 +86,13 @@ def executed_taps(info, per_tile=32, align=64):
     return total
 
 
-def cpu_baseline(w, n_nbr_sample):
+def cpu_baseline(w, n_nbr_sample, n_cmp=12):
     """The FP64 oracle on the host: reference matched filter and FFT-based
-    reconstruction of a sample of neighbours (full series each)."""
+    reconstruction of a sample of neighbours (full series each).  Beside it,
+    the host analogue of the paper's cost comparison (sec. IV): direct matched
+    filtering of `n_cmp` neighbours (template generated on the fly, one
+    transform each) against the ratio filter for the same neighbours (stored
+    kernels, overlap-add convolution with the reference series)."""
     from oracle import mf as omf
     from oracle import ratio as orat
     g = w["grid"]
@@ -97,12 +101,31 @@ def cpu_baseline(w, n_nbr_sample):
     norms = [omf.norm(g.fs, g.n, g.f_low, g.f_high, w["psd"], omf.template_spectrum(g.fs, g.n, *k)) for k in nb]
     t0 = time.perf_counter()
     zr, nr = omf.grid_snr_series(g, w["xf"], w["psd"], *w["ref"])
+    t_ref = time.perf_counter() - t0
     for kb, nk in zip(kern, norms):
         orat.reconstruct(zr, kb["m_lo"], kb["taps"], nr / nk)
     dt = time.perf_counter() - t0
+    # cost comparison on the first n_cmp neighbours
+    t0 = time.perf_counter()
+    for k in nb[:n_cmp]:
+        omf.grid_snr_series(g, w["xf"], w["psd"], *k)
+    t_direct = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for kb, nk in zip(kern[:n_cmp], norms[:n_cmp]):
+        orat.reconstruct_oa(zr, kb["m_lo"], kb["taps"], nr / nk)
+    t_oa = time.perf_counter() - t0
+    group = len(w["nbrs"]) + 1
+    per_direct = t_direct / n_cmp
+    per_ratio = t_oa / n_cmp + t_ref / group        # the reference's filter shared by its group
     return dict(value=(1 + len(nb)) * g.n / dt, unit="template-samples/s", cores=1, kind="oracle",
                 sample=f"reference MF + FFT-based reconstruction of {len(nb)} of 256 neighbours, "
-                       f"full 2^21-sample series, numpy FP64 on one host core ({dt:.2f} s)")
+                       f"full 2^21-sample series, numpy FP64 on one host core ({dt:.2f} s)",
+                ratio_vs_direct=dict(templates=n_cmp, direct_s_per_template=per_direct,
+                                     ratio_s_per_template=per_ratio, reference_mf_s=t_ref,
+                                     cost_reduction=1.0 - per_ratio / per_direct,
+                                     note="host, one core: direct = template spectrum + inverse FFT; ratio = "
+                                          "overlap-add convolution of the reference series with the stored "
+                                          "kernel, reference filter shared by the 257-template group"))
 
 
 def batched_leg(dev):
@@ -295,6 +318,112 @@ def bank_leg(dev, ctx, w, psd):
                 kernel_taps_total=dep_taps)
 
 
+def stress_leg(dev, ctx):
+    """Next-generation-detector shape: 2048 s at 4096 Hz (2^23 samples), f_low
+    10 Hz, 4 references x 1024 lattice neighbours (kernels of 16k-28k taps).
+    Per reference: its matched filter + fused split-FP16 reconstruction of the
+    1024 series (peaks and triggers, series not stored: 4096 x 2^23 complex64
+    would be 275 GB), against direct FFT matched filtering of the same 4096
+    templates with the same read-out; kernel builds timed apart.  The learned
+    kernels are not used here: a surrogate trained at f_low = 20 Hz does not
+    transfer to this band (every kernel would take the exact fallback)."""
+    w = synth.workload_stress()
+    g = w["grid"]
+    psd = torch.from_numpy(w["psd"]).to(dev)
+    xf = torch.from_numpy(w["xf"]).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(w["refs"], w["groups"])]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    lens = np.concatenate([k.info()["len"] for k in ksets])
+    zref = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
+
+    def ratio():
+        for r, K in zip(w["refs"], ksets):
+            rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
+            rf.snr_reconstruct(ctx, K, zref[0], prec="split16", store=False, fused_thr=6.0, trig_cap=1 << 18)
+
+    zb = torch.empty((128, g.n), dtype=torch.complex64, device=dev)
+
+    def direct():
+        for grp, r in zip(w["groups"], w["refs"]):
+            tm = [r] + list(grp)
+            for a in range(0, len(tm), 128):
+                part = tm[a:a + 128]
+                rf.mf_ref_snr(ctx, g, xf, psd, part, z=zb, want_sigma=False)
+                rf.snr_peaks(ctx, zb[:len(part)], 6.0, trig_cap=1 << 18)
+
+    stream = torch.cuda.current_stream(dev)
+    ratio()
+    t_ratio, _ = timed(ratio, 1, 0, stream)
+    direct()
+    t_direct, _ = timed(direct, 1, 0, stream)
+    ntpl = len(lens) + len(w["refs"])
+    samples = ntpl * g.n
+    flops = 4.0 * g.n * float(lens.sum())
+    res = dict(templates=ntpl, kernel_taps_min=int(lens.min()), kernel_taps_max=int(lens.max()),
+               kernel_build_s=t_build, ratio_ms=t_ratio, direct_ms=t_direct,
+               ratio_value=samples / (t_ratio * 1e-3), direct_value=samples / (t_direct * 1e-3),
+               unit="template-samples/s", recon_tflops=flops / (t_ratio * 1e-3) / 1e12,
+               recon_fp16_frac=flops / (t_ratio * 1e-3) / 1e12 / PEAK_FP16_TFLOPS)
+    del zb, zref
+    for K in ksets:
+        K.free()
+    return res
+
+
+SWEEP_MC = (0.871, 1.219, 1.741, 2.612)
+SWEEP_Q = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+SWEEP_THR = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
+
+
+def sweep_leg(dev, ctx):
+    """SNR loss against kernel length (the paper's Fig. 3 study and its
+    chirp-mass appendix): for each chirp mass and mass ratio, one injection at
+    SNR 20 in coloured noise (512 s, 4096 Hz, f_low 20 Hz); reference of the
+    same chirp mass at q = 0.6; the target's kernel truncated at each
+    threshold; loss = |peak |z| reconstructed - peak |z| direct| / direct,
+    against tau_ratio / tau_target (kernel taps / fs over tau(f_low))."""
+    out = {}
+    for mc in SWEEP_MC:
+        rows = []
+        for q in SWEEP_Q:
+            w = synth.workload_sweep(mc, q)
+            g = w["grid"]
+            psd = torch.from_numpy(w["psd"]).to(dev)
+            xf = torch.from_numpy(w["xf"]).to(dev)
+            z, _ = rf.mf_ref_snr(ctx, g, xf, psd, [w["ref"], w["tgt"]], want_sigma=False)
+            zr = z[0].contiguous()
+            rho_m = z[1].abs().max().item()
+            tau_t = float(rf.template_durations([w["tgt"]], g.f_low)[0])
+            for thr in SWEEP_THR:
+                K = rf.ratio_kernel_build(ctx, g, psd, w["ref"], [w["tgt"]], thr=thr)
+                L = K.info()["len"][0]
+                zk = rf.snr_reconstruct(ctx, K, zr, prec="split16")["z"]
+                rho_r = zk.abs().max().item()
+                K.free()
+                rows.append(dict(q=q, thr=thr, taps=L, x=L / g.fs / tau_t, loss=abs(rho_r - rho_m) / rho_m,
+                                 rho_direct=rho_m))
+            del z, zr, xf, psd
+        # where the loss (worst over q) first stays below 1e-3 and 1e-4, in tau_ratio / tau_target
+        cross = {}
+        for level in (1e-3, 1e-4):
+            xs = []
+            for q in SWEEP_Q:
+                pts = sorted((r["x"], r["loss"]) for r in rows if r["q"] == q)
+                ok = [x for i, (x, l) in enumerate(pts) if all(l2 <= level for _, l2 in pts[i:])]
+                xs.append(ok[0] if ok else None)
+            cross[str(level)] = None if any(x is None for x in xs) else max(xs)
+        at_paper = [r for r in rows if r["thr"] == 1e-3]
+        out[str(mc)] = dict(rows=rows, x_at_loss=cross, paper_threshold=dict(
+            x_min=min(r["x"] for r in at_paper), x_max=max(r["x"] for r in at_paper),
+            loss_max=max(r["loss"] for r in at_paper)))
+        log(f"bench: sweep Mc {mc}: loss at 1e-3/s <= {out[str(mc)]['paper_threshold']['loss_max']:.2e}, "
+            f"x where loss < 1e-3: {cross['0.001']}")
+    return out
+
+
 def learned_leg(dev, w, psd, xf, K_exact, build_s, steps):
     stream = torch.cuda.Stream(dev)          # training replays a captured graph: not the null stream
     ctx = rf.Context(0, stream)
@@ -405,7 +534,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-nbrs", type=int, default=24)
     ap.add_argument("--only", default="",
-                    help="comma list of legs to run: step,fp32,direct,factored,ols,bank,batched,learned")
+                    help="comma list of legs to run: step,fp32,direct,factored,ols,bank,batched,learned "
+                         "(default: all of them), sweep and stress (only when named)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -507,6 +637,12 @@ def main():
     if "bank" in legs:
         log("bench: bank organisation and storage")
         res["bank"] = bank_leg(dev, ctx, w, psd)
+    if "stress" in legs:
+        log("bench: next-generation-detector shape (4 x 1024 templates, 2^23 samples)")
+        res["stress"] = stress_leg(dev, ctx)
+    if "sweep" in legs:
+        log("bench: SNR loss against kernel length")
+        res["sweep"] = sweep_leg(dev, ctx)
     if "batched" in legs:
         log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
@@ -558,6 +694,10 @@ def main():
         extra["ols"] = res["ols"]
     if "bank" in res:
         extra["bank"] = res["bank"]
+    if "sweep" in res:
+        extra["sweep"] = res["sweep"]
+    if "stress" in res:
+        extra["stress"] = res["stress"]
     if "batched" in res:
         extra["batched"] = res["batched"]
     if "learned" in res:

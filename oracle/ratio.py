@@ -113,6 +113,19 @@ def reconstruct(z_ref: np.ndarray, m_lo: int, taps: np.ndarray, scale: float):
     return scale * np.fft.ifft(np.fft.fft(z_ref) * np.conj(np.fft.fft(wfull)))
 
 
+def reconstruct_oa(z_ref: np.ndarray, m_lo: int, taps: np.ndarray, scale: float):
+    """Same circular correlation by overlap-add convolution (SciPy's
+    oaconvolve, the routine the paper's CPU code uses, sec. IV): the series
+    extended circularly by the kernel's span, convolved with the reversed
+    taps, 'valid' part."""
+    from scipy.signal import oaconvolve
+    n = z_ref.size
+    if taps.size == 0:
+        return np.zeros(n, dtype=np.complex128)
+    ext = z_ref[(m_lo + np.arange(n + taps.size - 1)) % n]
+    return scale * oaconvolve(ext, taps[::-1], mode="valid")
+
+
 def reconstruct_samples(z_ref, m_lo, taps, scale, sample_idx):
     """The defining sum evaluated only at the given output indices."""
     n = z_ref.size

@@ -57,16 +57,6 @@ T* upload(rf_ctx* ctx, int slot, const T* host, size_t count) {
   return d;
 }
 
-template <typename T>
-T* dev_alloc(size_t count) {
-  void* p = nullptr;
-  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{RF_E_NOMEM, "device allocation failed"};
-  }
-  return static_cast<T*>(p);
-}
-
 void sync(rf_ctx* ctx) { RF_HIP(hipStreamSynchronize(ctx->stream)); }
 
 double pow2_scale_for(double maxabs) {
@@ -87,6 +77,11 @@ void free_kernels(rf_kernels* k) {
 }  // namespace
 
 void free_kernel_set(rf_kernels* k) { free_kernels(k); }
+
+void copy_sync(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  RF_HIP(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
+  RF_HIP(hipStreamSynchronize(ctx->stream));
+}
 
 // Tiles, packed operands and device copies of a kernel set whose per-kernel
 // fields (m_lo, len, off, norm_ratio, kscale) and FP64 taps (host, concatenated

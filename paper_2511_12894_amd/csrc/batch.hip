@@ -62,16 +62,6 @@ struct rf_batch {
 namespace rf {
 namespace {
 
-template <typename T>
-T* balloc(size_t count) {
-  void* p = nullptr;
-  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{RF_E_NOMEM, "batch: device allocation failed"};
-  }
-  return static_cast<T*>(p);
-}
-
 int bucket_of(int64_t ksteps) { return ksteps <= 64 ? 0 : (ksteps <= 512 ? 1 : 2); }
 
 void free_batch(rf_batch* b) {
@@ -176,10 +166,10 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
       slot_total += int64_t(K->tiles.size()) * kTileKernels;
     }
     // global slot arrays and tiles: group r's kernels get global indices kbase[r] + k
-    b->b16 = balloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep));
+    b->b16 = dev_alloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep), "batch: device allocation failed");
     fill_u32(ctx, reinterpret_cast<uint32_t*>(b->b16 + b16_total), 0u, int64_t(kOperandPadSteps) * kB16PerStep / 2);
-    b->colscale = balloc<float>(size_t(slot_total));
-    b->slot_kernel = balloc<int32_t>(size_t(slot_total));
+    b->colscale = dev_alloc<float>(size_t(slot_total), "batch: device allocation failed");
+    b->slot_kernel = dev_alloc<int32_t>(size_t(slot_total), "batch: device allocation failed");
     int64_t b16_off = 0, slot_off = 0;
     int32_t kb = 0;
     std::vector<int32_t> host_slots;
@@ -223,26 +213,26 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
         for (int32_t q = 0; q < ntb; ++q) b->hitems.push_back(WorkItem{s, t, q, int32_t(kChunk)});
     }
     RF_CHECK(b->hitems.size() < size_t(INT32_MAX), "rf_batch_create: too many work items");
-    b->tiles = balloc<BatchTile>(b->htiles.size());
+    b->tiles = dev_alloc<BatchTile>(b->htiles.size(), "batch: device allocation failed");
     RF_HIP(hipMemcpy(b->tiles, b->htiles.data(), sizeof(BatchTile) * b->htiles.size(), hipMemcpyHostToDevice));
-    b->items = balloc<WorkItem>(b->hitems.size());
+    b->items = dev_alloc<WorkItem>(b->hitems.size(), "batch: device allocation failed");
     upload_items(b);
-    b->coef = balloc<Tf2Coef>(size_t(nref));
+    b->coef = dev_alloc<Tf2Coef>(size_t(nref), "batch: device allocation failed");
     RF_HIP(hipMemcpy(b->coef, coef.data(), sizeof(Tf2Coef) * nref, hipMemcpyHostToDevice));
-    b->moment = balloc<double>(1);
+    b->moment = dev_alloc<double>(1, "batch: device allocation failed");
     band_moment(ctx, grid, psd, b->moment);
     const size_t ns = size_t(nseg) * nref;
-    b->Y = balloc<float2>(ns * size_t(b->n));
-    b->zref = balloc<float2>(ns * size_t(b->n));
-    b->zs = balloc<__half>(ns * 4 * size_t(b->n));
-    b->maxbits = balloc<uint32_t>(ns);
-    b->zinv = balloc<float>(ns);
-    b->packed = balloc<uint64_t>(size_t(nseg) * b->ktotal + 1);
-    b->counter = balloc<uint32_t>(1);
+    b->Y = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
+    b->zref = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
+    b->zs = dev_alloc<__half>(ns * 4 * size_t(b->n), "batch: device allocation failed");
+    b->maxbits = dev_alloc<uint32_t>(ns, "batch: device allocation failed");
+    b->zinv = dev_alloc<float>(ns, "batch: device allocation failed");
+    b->packed = dev_alloc<uint64_t>(size_t(nseg) * b->ktotal + 1, "batch: device allocation failed");
+    b->counter = dev_alloc<uint32_t>(1, "batch: device allocation failed");
     b->nblocks = queue_blocks(ctx->device);
     // FFT scratch owned by the batch: the captured graph references it
-    b->fa = balloc<float2>(ns * size_t(b->n));
-    b->fb = balloc<float2>(ns * size_t(b->n));
+    b->fa = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
+    b->fb = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
     RF_HIP(hipStreamSynchronize(ctx->stream));
     *out = b;
     st = RF_OK;
@@ -314,7 +304,7 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
     po.cap = 0;
     po.thr2 = 1e30f;
     po.nk = b->ktotal;
-    WorkItem* scratch = balloc<WorkItem>(b->hitems.size());
+    WorkItem* scratch = dev_alloc<WorkItem>(b->hitems.size(), "batch: device allocation failed");
     hipEvent_t e0, e1;
     RF_HIP(hipEventCreate(&e0));
     RF_HIP(hipEventCreate(&e1));

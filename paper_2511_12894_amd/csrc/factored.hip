@@ -35,7 +35,6 @@ struct rf_factored {
   float* C = nullptr;        // [JP][KP]: (N_ref/N_k) V[k][j], zero padded
   float2* Q = nullptr;       // [n]: transform of conj(z_ref)
   float2* Qin = nullptr;     // [n]
-  float2* S = nullptr;       // [J][n]: basis spectra (zero off the band)
   float2* Y = nullptr;       // [JP][n]: basis correlations y_j (rows from J on zero)
   // split-FP16 mixing: the coefficients as hi/lo FP16 B operand fragments
   // [JP/16][8 tiles][2 planes][64 lanes][8 basis indices] after the scale cscale
@@ -48,16 +47,6 @@ struct rf_factored {
 
 namespace rf {
 namespace {
-
-template <typename T>
-T* falloc(size_t count) {
-  void* p = nullptr;
-  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{RF_E_NOMEM, "factored: device allocation failed"};
-  }
-  return static_cast<T*>(p);
-}
 
 inline unsigned nblocks(int64_t n, int64_t cap = 4096) {
   const int64_t b = (n + 255) / 256;
@@ -135,29 +124,19 @@ __global__ void k_band_gather(const double2* __restrict__ in, int64_t n, int64_t
   }
 }
 
-// S[j][b0 + i] = conj(Q[b0 + i]) Ub[j][i] / n  (FFT(z_ref) = conj(Q))
-__global__ void k_band_products(const float2* __restrict__ Q, const float2* __restrict__ Ub, int64_t n,
-                                int64_t b0, int64_t nb, int J, float inv_n, float2* __restrict__ S) {
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nb; i += int64_t(gridDim.x) * 256) {
-    const float2 q = Q[b0 + i];
-    const float xr = q.x * inv_n, xi = -q.y * inv_n;
-    for (int j = 0; j < J; ++j) {
-      const float2 u = Ub[int64_t(j) * nb + i];
-      S[int64_t(j) * n + b0 + i] = make_float2(xr * u.x - xi * u.y, xr * u.y + xi * u.x);
-    }
-  }
-}
-
-// Mixing: z~_k[m] = sum_j C[j][k] y_j[m] on v_mfma_f32_32x32x2_f32, rows = 32
-// output times, columns = 32 kernels, real and imaginary parts in separate
-// accumulators.  A workgroup of 8 waves (4 above JP = 96) holds C in LDS as
-// [j][lane][tile] so that one lane's operands of the tiles of a sweep are one
-// 8- or 16-byte read.  Each wave owns 32 consecutive times per time block, keeps
-// their y fragments for all j in registers and sweeps the kernel tiles 2 (or
-// 4) at a time: per pair of basis indices, 4 (8) independent MFMAs.  Crossings are recorded with
-// the raw (re, im) and finished by a pass over the trigger list.  Persistent
-// over time blocks; peaks kept per wave in LDS, one atomic per kernel and
-// workgroup at the end.
+// Mixing: z~_k[m] = sum_j C[j][k] y_j[m] on v_mfma_f32_32x32x2_f32 with rows =
+// 32 kernels, columns = 32 output times, real and imaginary parts in separate
+// accumulators, so that a lane holds one time of 16 kernels and every store of a
+// row of accumulators writes two whole 256-byte runs of series.  A workgroup of
+// 8 waves (4 above JP = 96) holds C in LDS as [j][sweep][lane][tile] so that one
+// lane's operands of the tiles of a sweep are one 8- or 16-byte read.  Each wave
+// owns 32 consecutive times per time block, keeps their y fragments for all j in
+// registers and sweeps the kernel tiles 2 (or 4) at a time: per pair of basis
+// indices, 4 (8) independent MFMAs.  Read-out: running peak keys of every
+// (kernel, time lane) pair as LDS atomics (two time lanes a slot from JP = 112
+// on, for room), one global atomic per kernel and workgroup at the end;
+// crossings are recorded with the raw (re, im) and finished by a pass over the
+// trigger list.  Persistent over time blocks.
 constexpr int kMixTimesMax = 256;                // n must be a multiple of this
 constexpr int kMixTiles = 8;                     // kernel tiles per set (up to 256 kernels)
 // two waves per SIMD (one hides the other's loads) sweeping 2 tiles at a time
@@ -166,53 +145,57 @@ template <int JP>
 constexpr int mix_waves() { return JP <= 96 ? 8 : 4; }
 template <int JP>
 constexpr int mix_group() { return JP <= 96 ? 2 : 4; }
+// (kernel, time lane) peak slots: 32 time lanes each while LDS allows
 template <int JP>
-constexpr bool mix_prefetch() { return false; }
+constexpr int mix_slots() { return JP <= 96 ? 32 : 16; }
 
 template <int JP, bool STORE, bool FUSED>
-__global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* __restrict__ Y, int64_t n, int J,
+__global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* __restrict__ Y, int64_t n,
                                                                 const float* __restrict__ Cg, int nk,
                                                                 float2* __restrict__ zout, PeakOut po) {
   constexpr int kMixWaves = mix_waves<JP>();
   constexpr int kMixGroup = mix_group<JP>();
   constexpr int kMixTimes = 32 * kMixWaves;
   constexpr int KP = 32 * kMixTiles;
+  constexpr int S = mix_slots<JP>();
   extern __shared__ __attribute__((aligned(16))) float smem[];
   constexpr int NG = kMixTiles / kMixGroup;                  // sweeps per time block
   float* Cs = smem;                                          // [JP][NG][32 lanes][kMixGroup]
-  Best* best = reinterpret_cast<Best*>(Cs + JP * KP);        // [kMixWaves][KP]
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(Cs + JP * KP);  // [KP][S]
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (int e = threadIdx.x; e < JP * KP; e += 64 * kMixWaves) {
     const int j = e / KP, k = e % KP, tile = k >> 5;
     Cs[((j * NG + tile / kMixGroup) * 32 + (k & 31)) * kMixGroup + tile % kMixGroup] = Cg[e];
   }
   if (FUSED)
-    for (int e = threadIdx.x; e < kMixWaves * KP; e += 64 * kMixWaves) best[e] = Best{-1.f, INT32_MAX};
+    for (int e = threadIdx.x; e < KP * S; e += 64 * kMixWaves) keys[e] = 0ull;
   __syncthreads();
   const int64_t nblk = n / kMixTimes;
   const int kr = lane >> 5;                      // k index of this lane's operand half
   const int ngroups = (nk + 32 * kMixGroup - 1) / (32 * kMixGroup);
-  // A operand: lane holds y_{2s + kr}[t0 + lane % 32] (rows J..JP-1 of Y are zero)
-  float are[JP / 2], aim[JP / 2];
+  const int slot = (lane & 31) / (32 / S);
+  // store offset of this lane from a tile's row of kernel 32 tile + acc_row(i, 0) at time t0
+  const uint32_t loff = uint32_t(4 * kr) * uint32_t(n) + uint32_t(lane & 31);
+  // B operand: lane holds y_{2s + kr}[t0 + lane % 32] (rows J..JP-1 of Y are zero)
+  float yre[JP / 2], yim[JP / 2];
   const float2* Ylane = Y + int64_t(kr) * n + 32 * wave + (lane & 31);
-  auto loadA = [&](int64_t tb, float (&r)[JP / 2], float (&im)[JP / 2]) {
+  auto loadB = [&](int64_t tb) {
     const float2* p = Ylane + tb * kMixTimes;
 #pragma unroll
     for (int s = 0; s < JP / 2; ++s) {
       const float2 v = p[int64_t(2 * s) * n];
-      r[s] = v.x;
-      im[s] = v.y;
+      yre[s] = v.x;
+      yim[s] = v.y;
     }
   };
-  // B operands of sweep g's tiles for basis pair s: C[2s + kr][(G g + t) 32 + lane % 32],
+  // A operands of sweep g's tiles for basis pair s: C[2s + kr][(G g + t) 32 + lane % 32],
   // consecutive lanes reading consecutive words
   typedef float floatG __attribute__((ext_vector_type(kMixGroup)));
   const floatG* cb = reinterpret_cast<const floatG*>(Cs) + kr * NG * 32 + (lane & 31);
-  if (int64_t(blockIdx.x) < nblk) loadA(blockIdx.x, are, aim);
   for (int64_t tbk = blockIdx.x; tbk < nblk; tbk += gridDim.x) {
     const int64_t t0 = tbk * kMixTimes + 32 * wave;
-    float nre[JP / 2], nim[JP / 2];
-    if (mix_prefetch<JP>() && tbk + gridDim.x < nblk) loadA(tbk + gridDim.x, nre, nim);
+    const int64_t m = t0 + (lane & 31);            // this lane's output time
+    loadB(tbk);
     for (int g = 0; g < ngroups; ++g) {
       floatx16 cre[kMixGroup], cim[kMixGroup];
 #pragma unroll
@@ -226,81 +209,60 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
         if (s + 1 < JP / 2) bnext = cb[((s + 1) * 2 * NG + g) * 32];
 #pragma unroll
         for (int t = 0; t < kMixGroup; ++t) {
-          cre[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(are[s], bcur[t], cre[t], 0, 0, 0);
-          cim[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim[s], bcur[t], cim[t], 0, 0, 0);
+          cre[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(bcur[t], yre[s], cre[t], 0, 0, 0);
+          cim[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(bcur[t], yim[s], cim[t], 0, 0, 0);
         }
         bcur = bnext;
       }
 #pragma unroll
       for (int t = 0; t < kMixGroup; ++t) {
-        const int k = (kMixGroup * g + t) * 32 + (lane & 31);
-        const bool live = k < nk;
-        Best bt{-1.f, INT32_MAX};
-        uint32_t cross = 0;
-        if (STORE && live) {
-          // rows i, i + 1 (i even) are consecutive times: one 16-byte store
-          float4* zrow = reinterpret_cast<float4*>(zout + int64_t(k) * n + t0);
+        // register i holds kernel kb + acc_row(i, 0) (kb carries the 4 (lane / 32) part)
+        const int kb = (kMixGroup * g + t) * 32 + 4 * kr;
+        if (STORE) {
+          float2* zt = zout + int64_t((kMixGroup * g + t) * 32) * n + t0;     // wave-uniform
 #pragma unroll
-          for (int i = 0; i < 16; i += 2)
-            zrow[acc_row(i, lane) >> 1] = make_float4(cre[t][i], cim[t][i], cre[t][i + 1], cim[t][i + 1]);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int64_t m = t0 + acc_row(i, lane);
-          const float re = cre[t][i], im = cim[t][i];
-          if (FUSED) {
-            const float a2 = abs2_rn(re, im);
-            bt = better(bt, Best{a2, int32_t(m)});
-            if (live && a2 > po.thr2) cross |= 1u << i;
-          }
-        }
-        // crossings (rare) in a rolled loop: one copy of the record code
-        if (FUSED && cross) {
-#pragma unroll 1
           for (int i = 0; i < 16; ++i)
-            if ((cross >> i) & 1u) {
-              const unsigned long long slot = atomicAdd(po.count, 1ull);
-              if (int64_t(slot) < po.cap) {
-                rf_trigger tr;              // (re, im) for now; finished by k_trig_finish
-                tr.tmpl = k;
-                tr.seg = po.seg;
-                tr.idx = int32_t(t0 + acc_row(i, lane));
-                tr.absz = cre[t][i];
-                tr.argz = cim[t][i];
-                po.trig[slot] = tr;
-              }
-            }
+            if (kb + acc_row(i, 0) < nk) (zt + int64_t(acc_row(i, 0)) * n)[loff] = make_float2(cre[t][i], cim[t][i]);
         }
         if (FUSED) {
-          const Best o{__shfl_xor(bt.a2, 32), __shfl_xor(bt.idx, 32)};
-          bt = better(bt, o);
-          if (lane < 32 && live) {
-            Best& b = best[wave * KP + k];
-            b = better(b, bt);
+          uint32_t cross = 0;
+          const uint32_t ikey = 0xFFFFFFFFu - uint32_t(m);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int k = kb + acc_row(i, 0);
+            if (k < nk) {
+              const float a2 = abs2_rn(cre[t][i], cim[t][i]);
+              atomicMax(&keys[k * S + slot], (unsigned long long)((uint64_t(__float_as_uint(a2)) << 32) | ikey));
+              if (a2 > po.thr2) cross |= 1u << i;
+            }
+          }
+          // crossings (rare) in a rolled loop: one copy of the record code
+          if (cross) {
+#pragma unroll 1
+            for (int i = 0; i < 16; ++i)
+              if ((cross >> i) & 1u) {
+                const unsigned long long sl = atomicAdd(po.count, 1ull);
+                if (int64_t(sl) < po.cap) {
+                  rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
+                  tr.tmpl = kb + acc_row(i, 0);
+                  tr.seg = po.seg;
+                  tr.idx = int32_t(m);
+                  tr.absz = cre[t][i];
+                  tr.argz = cim[t][i];
+                  po.trig[sl] = tr;
+                }
+              }
           }
         }
       }
-    }
-    if (mix_prefetch<JP>()) {
-#pragma unroll
-      for (int s = 0; s < JP / 2; ++s) {
-        are[s] = nre[s];
-        aim[s] = nim[s];
-      }
-    } else if (tbk + gridDim.x < nblk) {
-      loadA(tbk + gridDim.x, are, aim);
     }
   }
   if (FUSED) {
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += 64 * kMixWaves) {
-      Best b = best[k];
-      for (int w = 1; w < kMixWaves; ++w) b = better(b, best[w * KP + k]);
-      if (b.a2 >= 0.f) {
-        const uint64_t key = (uint64_t(__float_as_uint(b.a2)) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(b.idx));
-        atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k),
-                  (unsigned long long)key);
-      }
+      unsigned long long b = 0ull;
+      for (int s2 = 0; s2 < S; ++s2) b = max(b, keys[k * S + s2]);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
     }
   }
 }
@@ -559,7 +521,7 @@ void mix_launch_jp(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOu
   constexpr int KP = 32 * kMixTiles;
   constexpr int kMixWaves = mix_waves<JP>();
   constexpr int kMixTimes = 32 * kMixWaves;
-  const size_t lds = sizeof(float) * size_t(JP) * KP + (fused ? sizeof(Best) * kMixWaves * KP : 0);
+  const size_t lds = sizeof(float) * size_t(JP) * KP + (fused ? sizeof(unsigned long long) * KP * mix_slots<JP>() : 0);
   int dev = 0, cus = 0;
   RF_HIP(hipGetDevice(&dev));
   RF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -570,8 +532,8 @@ void mix_launch_jp(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOu
     auto kfn = k_mix<JP, S, FU>;                                                                         \
     RF_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),                                       \
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));                   \
-    hipLaunchKernelGGL(kfn, dim3(grid), dim3(64 * kMixWaves), lds, ctx->stream, F->Y, F->n, F->J, F->C,  \
-                       F->nk, zout, po);                                                                 \
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(64 * kMixWaves), lds, ctx->stream, F->Y, F->n, F->C, F->nk, \
+                       zout, po);                                                                        \
   } while (0)
   if (zout && fused) RF_MIX(true, true);
   else if (zout) RF_MIX(true, false);
@@ -596,15 +558,10 @@ void mix_launch(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& 
 
 void free_factored(rf_factored* F) {
   if (!F) return;
-  for (void* p : {(void*)F->Ub, (void*)F->C, (void*)F->Q, (void*)F->Qin, (void*)F->S, (void*)F->Y, (void*)F->Cp,
+  for (void* p : {(void*)F->Ub, (void*)F->C, (void*)F->Q, (void*)F->Qin, (void*)F->Y, (void*)F->Cp,
                   (void*)F->zmax})
     if (p) (void)hipFree(p);
   delete F;
-}
-
-void fcopy(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
-  RF_HIP(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
-  RF_HIP(hipStreamSynchronize(ctx->stream));
 }
 
 }  // namespace
@@ -657,17 +614,17 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     F->b0 = jlo;
     F->nb = jhi - jlo + 1;
     // dense kernel matrix and its Gram matrix (FP64)
-    W = falloc<double>(size_t(nk) * L);
+    W = dev_alloc<double>(size_t(nk) * L, "factored: device allocation failed");
     {
-      int64_t* meta = falloc<int64_t>(size_t(nk) * 2);
-      int32_t* lend = falloc<int32_t>(size_t(nk));
+      int64_t* meta = dev_alloc<int64_t>(size_t(nk) * 2, "factored: device allocation failed");
+      int32_t* lend = dev_alloc<int32_t>(size_t(nk), "factored: device allocation failed");
       std::vector<int64_t> h(size_t(nk) * 2);
       for (int k = 0; k < nk; ++k) {
         h[k] = K->off[k];
         h[nk + k] = K->m_lo[k];
       }
-      fcopy(ctx, meta, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice);
-      fcopy(ctx, lend, K->len.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice);
+      copy_sync(ctx, meta, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice);
+      copy_sync(ctx, lend, K->len.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice);
       hipLaunchKernelGGL(k_dense, dim3(nblocks(L, 1024), unsigned(nk)), dim3(256), 0, ctx->stream, K->taps64, meta,
                          meta + nk, lend, M0, L, W);
       RF_HIP(hipGetLastError());
@@ -675,10 +632,10 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
       (void)hipFree(meta);
       (void)hipFree(lend);
     }
-    double* G = falloc<double>(size_t(nk) * nk);
+    double* G = dev_alloc<double>(size_t(nk) * nk, "factored: device allocation failed");
     dgemm(ctx, W, L, 0, W, L, 1, G, nk, nk, nk, L);             // G = W W^T
     std::vector<double> gh(size_t(nk) * nk);
-    fcopy(ctx, gh.data(), G, sizeof(double) * gh.size(), hipMemcpyDeviceToHost);
+    copy_sync(ctx, gh.data(), G, sizeof(double) * gh.size(), hipMemcpyDeviceToHost);
     (void)hipFree(G);
     std::vector<double> lam, V;
     sym_eig(gh, nk, lam, V);
@@ -711,15 +668,15 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     std::vector<double> vj(size_t(nk) * J);
     for (int k = 0; k < nk; ++k)
       for (int j = 0; j < J; ++j) vj[size_t(k) * J + j] = V[size_t(k) * nk + j];
-    double* Vd = falloc<double>(vj.size());
-    fcopy(ctx, Vd, vj.data(), sizeof(double) * vj.size(), hipMemcpyHostToDevice);
-    double* Bm = falloc<double>(size_t(J) * L);
+    double* Vd = dev_alloc<double>(vj.size(), "factored: device allocation failed");
+    copy_sync(ctx, Vd, vj.data(), sizeof(double) * vj.size(), hipMemcpyHostToDevice);
+    double* Bm = dev_alloc<double>(size_t(J) * L, "factored: device allocation failed");
     dgemm(ctx, Vd, J, 1, W, L, 0, Bm, L, J, L, nk);
     (void)hipFree(W);
     W = nullptr;
     (void)hipFree(Vd);
     // basis spectra on the band bins, FP64 transforms in batches
-    F->Ub = falloc<float2>(size_t(J) * F->nb);
+    F->Ub = dev_alloc<float2>(size_t(J) * F->nb, "factored: device allocation failed");
     {
       const int per = int(std::max<int64_t>(1, std::min<int64_t>(J, (int64_t(1) << 25) / n)));
       double2* buf = static_cast<double2*>(ctx->ws[WS_BUILD].ensure(sizeof(double2) * size_t(n) * per));
@@ -739,11 +696,11 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     }
     // largest L1 norm of a basis vector (bounds the correlations for the FP16 split)
     {
-      double* l1 = falloc<double>(size_t(J));
+      double* l1 = dev_alloc<double>(size_t(J), "factored: device allocation failed");
       hipLaunchKernelGGL(k_row_l1, dim3(unsigned(J)), dim3(256), 0, ctx->stream, Bm, L, l1);
       RF_HIP(hipGetLastError());
       std::vector<double> l1h(J);
-      fcopy(ctx, l1h.data(), l1, sizeof(double) * J, hipMemcpyDeviceToHost);
+      copy_sync(ctx, l1h.data(), l1, sizeof(double) * J, hipMemcpyDeviceToHost);
       (void)hipFree(l1);
       F->l1max = float(*std::max_element(l1h.begin(), l1h.end()) * (1.0 + 1e-6));
     }
@@ -759,8 +716,8 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
         ch[size_t(j) * F->KP + k] = float(c);
         cmax = std::max(cmax, std::fabs(c));
       }
-    F->C = falloc<float>(ch.size());
-    fcopy(ctx, F->C, ch.data(), sizeof(float) * ch.size(), hipMemcpyHostToDevice);
+    F->C = dev_alloc<float>(ch.size(), "factored: device allocation failed");
+    copy_sync(ctx, F->C, ch.data(), sizeof(float) * ch.size(), hipMemcpyHostToDevice);
     // the same, split into FP16 hi + lo after a power-of-two scale (largest
     // scaled value in [2^13, 2^14)), in the B operand layout of the 32x32x16
     // product: lane l of k-step ks, tile t holds C[16 ks + 8 (l / 32) + q][32 t + l % 32]
@@ -782,16 +739,14 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
               cp[base] = hi;
               cp[base + 64 * 8] = lo;
             }
-      F->Cp = falloc<_Float16>(cp.size());
-      fcopy(ctx, F->Cp, cp.data(), sizeof(_Float16) * cp.size(), hipMemcpyHostToDevice);
+      F->Cp = dev_alloc<_Float16>(cp.size(), "factored: device allocation failed");
+      copy_sync(ctx, F->Cp, cp.data(), sizeof(_Float16) * cp.size(), hipMemcpyHostToDevice);
     }
-    F->zmax = falloc<uint32_t>(1);
-    // run buffers; the band products never touch the off-band bins, zeroed once
-    F->Q = falloc<float2>(size_t(n));
-    F->Qin = falloc<float2>(size_t(n));
-    F->S = falloc<float2>(size_t(J) * n);
-    F->Y = falloc<float2>(size_t(F->JP) * n);     // rows J..JP-1 stay zero (mixing pads)
-    fill_u64(ctx, reinterpret_cast<uint64_t*>(F->S), 0ull, int64_t(J) * n);
+    F->zmax = dev_alloc<uint32_t>(1, "factored: device allocation failed");
+    // run buffers; rows J..JP-1 of Y stay zero (the mixing reads them as padding)
+    F->Q = dev_alloc<float2>(size_t(n), "factored: device allocation failed");
+    F->Qin = dev_alloc<float2>(size_t(n), "factored: device allocation failed");
+    F->Y = dev_alloc<float2>(size_t(F->JP) * n, "factored: device allocation failed");
     fill_u64(ctx, reinterpret_cast<uint64_t*>(F->Y), 0ull, int64_t(F->JP) * n);
     RF_HIP(hipStreamSynchronize(ctx->stream));
     *out = F;
@@ -845,10 +800,8 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
                        n, F->Qin, F->zmax);
     RF_HIP(hipGetLastError());
     fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
-    hipLaunchKernelGGL(k_band_products, dim3(nblocks(F->nb)), dim3(256), 0, ctx->stream, F->Q, F->Ub, n, F->b0,
-                       F->nb, F->J, float(1.0 / double(n)), F->S);
-    RF_HIP(hipGetLastError());
-    fft_inverse_f32(ctx, F->S, F->Y, n, F->J);
+    // basis correlations: the band products formed inside the first transform pass
+    fft_inverse_band_f32(ctx, F->Q, F->Ub, F->b0, F->nb, float(1.0 / double(n)), F->Y, n, F->J);
     if (prec == RF_PREC_SPLIT_FP16)
       mix16_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
     else

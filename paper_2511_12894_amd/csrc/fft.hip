@@ -10,6 +10,8 @@
 // run of 16 consecutive complex values; the P-point DFT of a column runs in
 // LDS as a short in-workgroup Stockham sequence of radix-8/4/2 register
 // butterflies.  Twiddles come from sincospi of exact dyadic arguments.
+#include <type_traits>
+
 #include "rf_internal.h"
 
 namespace rf {
@@ -126,10 +128,19 @@ __device__ inline void inner_dft(typename C2<T>::t (*s)[P + 1], const typename C
   }
 }
 
-template <typename T, int P>
+// Input of a first pass formed on the fly: transform y of the batch reads
+// conj(Q[f]) Ub[y][f - b0] / n on the band bins f in [b0, b0 + nb), zero elsewhere.
+struct BandIn {
+  const float2* Q;
+  const float2* Ub;
+  int64_t b0, nb;
+  float inv_n;
+};
+
+template <typename T, int P, bool BAND>
 __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* __restrict__ in,
                                                        typename C2<T>::t* __restrict__ out,
-                                                       int64_t n, int64_t ns) {
+                                                       int64_t n, int64_t ns, BandIn bin) {
   using V = typename C2<T>::t;
   __shared__ V s[kCols][P + 1];
   __shared__ V tw[P];
@@ -148,7 +159,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
     const int c = e % kCols, r = e / kCols;
     const int64_t j = j0 + c;
-    V v = in[j + int64_t(r) * ncols];
+    V v;
+    if constexpr (BAND) {
+      const int64_t i = j + int64_t(r) * ncols - bin.b0;
+      v = V{0, 0};
+      if (i >= 0 && i < bin.nb) {
+        const float2 q = bin.Q[bin.b0 + i];
+        const float2 u = bin.Ub[int64_t(blockIdx.y) * bin.nb + i];
+        const float xr = q.x * bin.inv_n, xi = -q.y * bin.inv_n;
+        v = V{xr * u.x - xi * u.y, xr * u.y + xi * u.x};
+      }
+    } else {
+      v = in[j + int64_t(r) * ncols];
+    }
     if (ns > 1) {
       const int64_t k = j & (ns - 1);
       T sn, cs;
@@ -184,15 +207,15 @@ std::vector<int> plan_passes(int lg) {
   return bits;
 }
 
-template <typename T>
+template <typename T, bool BAND = false>
 void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int64_t ns, int batch, hipStream_t st) {
+                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}) {
   const int64_t P = int64_t(1) << bits;
   dim3 grid(unsigned((n / P) / kCols), unsigned(batch));
   switch (bits) {
-#define RF_FFT_CASE(B)                                                                       \
-  case B:                                                                                    \
-    hipLaunchKernelGGL((k_fft_pass<T, (1 << B)>), grid, dim3(kThreads), 0, st, in, out, n, ns); \
+#define RF_FFT_CASE(B)                                                                                    \
+  case B:                                                                                                 \
+    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), BAND>), grid, dim3(kThreads), 0, st, in, out, n, ns, bin); \
     break;
     RF_FFT_CASE(4)
     RF_FFT_CASE(5)
@@ -208,7 +231,7 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
 
 template <typename T>
 void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in) {
+                 int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in, const BandIn* band = nullptr) {
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
@@ -227,6 +250,14 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   int64_t ns = 1;
   for (int i = 0; i < s; ++i) {
     V* dst = (i == s - 1) ? out : ((i % 2 == 0) ? wa : wb);
+    if constexpr (std::is_same<T, float>::value) {
+      if (i == 0 && band) {
+        launch_pass<T, true>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
+        ns <<= bits[i];
+        src = dst;
+        continue;
+      }
+    }
     launch_pass<T>(bits[i], src, dst, n, ns, batch, ctx->stream);
     ns <<= bits[i];
     src = dst;
@@ -241,6 +272,12 @@ void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int 
 }
 void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch) {
   fft_inverse<double>(ctx, in, out, n, batch, nullptr, nullptr);
+}
+void fft_inverse_band_f32(rf_ctx* ctx, const float2* Q, const float2* Ub, int64_t b0, int64_t nb, float inv_n,
+                          float2* out, int64_t n, int batch) {
+  RF_CHECK(b0 >= 0 && nb >= 0 && b0 + nb <= n, "fft: band outside the transform");
+  const BandIn band{Q, Ub, b0, nb, inv_n};
+  fft_inverse<float>(ctx, nullptr, out, n, batch, nullptr, nullptr, &band);
 }
 
 }  // namespace rf

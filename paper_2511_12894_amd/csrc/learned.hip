@@ -72,16 +72,6 @@ struct rf_surrogate {
 namespace rf {
 namespace {
 
-template <typename T>
-T* salloc(size_t count) {
-  void* p = nullptr;
-  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{RF_E_NOMEM, "surrogate: device allocation failed"};
-  }
-  return static_cast<T*>(p);
-}
-
 inline unsigned gblocks(int64_t n, unsigned cap = 4096) {
   int64_t b = (n + 255) / 256;
   return unsigned(std::max<int64_t>(1, std::min<int64_t>(b, cap)));
@@ -405,12 +395,6 @@ void herm_eig(std::vector<cd> A, int n, std::vector<double>& w, std::vector<cd>&
   V.swap(Vs);
 }
 
-// copies on the context's stream (which need not synchronise with the null stream)
-void copy_sync(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
-  RF_HIP(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
-  RF_HIP(hipStreamSynchronize(ctx->stream));
-}
-
 std::vector<cd> to_host(rf_ctx* ctx, const double2* d, size_t n) {
   std::vector<double2> h(n);
   copy_sync(ctx, h.data(), d, sizeof(double2) * n, hipMemcpyDeviceToHost);
@@ -421,7 +405,7 @@ std::vector<cd> to_host(rf_ctx* ctx, const double2* d, size_t n) {
 double2* to_dev(rf_ctx* ctx, const std::vector<cd>& v) {
   std::vector<double2> h(v.size());
   for (size_t i = 0; i < v.size(); ++i) h[i] = make_double2(v[i].real(), v[i].imag());
-  double2* d = salloc<double2>(v.size());
+  double2* d = dev_alloc<double2>(v.size(), "surrogate: device allocation failed");
   copy_sync(ctx, d, h.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice);
   return d;
 }
@@ -542,15 +526,15 @@ void ensure_batch(rf_surrogate* s, int B) {
       (void)hipFree(*p);
       *p = nullptr;
     }
-  s->xb = salloc<float>(size_t(B) * kIn);
-  s->tb = salloc<float>(size_t(B) * kOut);
+  s->xb = dev_alloc<float>(size_t(B) * kIn, "surrogate: device allocation failed");
+  s->tb = dev_alloc<float>(size_t(B) * kOut, "surrogate: device allocation failed");
   for (int i = 0; i < 3; ++i) {
-    s->pre[i] = salloc<float>(size_t(B) * kHid);
-    s->act[i] = salloc<float>(size_t(B) * kHid);
+    s->pre[i] = dev_alloc<float>(size_t(B) * kHid, "surrogate: device allocation failed");
+    s->act[i] = dev_alloc<float>(size_t(B) * kHid, "surrogate: device allocation failed");
   }
-  s->out = salloc<float>(size_t(B) * kOut);
-  s->d0 = salloc<float>(size_t(B) * kHid);
-  s->d1 = salloc<float>(size_t(B) * kHid);
+  s->out = dev_alloc<float>(size_t(B) * kOut, "surrogate: device allocation failed");
+  s->d0 = dev_alloc<float>(size_t(B) * kHid, "surrogate: device allocation failed");
+  s->d1 = dev_alloc<float>(size_t(B) * kHid, "surrogate: device allocation failed");
   s->B = B;
   if (s->exec) {
     (void)hipGraphExecDestroy(s->exec);
@@ -619,16 +603,16 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
     std::vector<float> xs(feat.size());
     for (int p = 0; p < npair; ++p)
       for (int j = 0; j < 4; ++j) xs[size_t(p) * 4 + j] = float((feat[size_t(p) * 4 + j] - s->feat_mean[j]) / s->feat_std[j]);
-    s->X = salloc<float>(xs.size());
+    s->X = dev_alloc<float>(xs.size(), "surrogate: device allocation failed");
     copy_sync(ctx, s->X, xs.data(), sizeof(float) * xs.size(), hipMemcpyHostToDevice);
 
     // exact analytic kernels on the window: H [npair][L]
-    double2* H = salloc<double2>(size_t(npair) * L);
+    double2* H = dev_alloc<double2>(size_t(npair) * L, "surrogate: device allocation failed");
     window_kernels(ctx, grid, refs, nbrs, npair, L, H);
     // randomized range finder: Y = A Om with A = H^T [L][npair] (the spectrum decays fast
     // enough that no power iteration is needed; one would cube the condition number)
     const int r2 = nomega;
-    double2* Om = salloc<double2>(size_t(npair) * r2);
+    double2* Om = dev_alloc<double2>(size_t(npair) * r2, "surrogate: device allocation failed");
     {
       std::vector<double2> oh(size_t(npair) * r2);
       std::vector<double> od(size_t(npair) * r2);
@@ -636,14 +620,14 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
       for (size_t i = 0; i < od.size(); ++i) oh[i] = make_double2(od[i], 0.0);
       copy_sync(ctx, Om, oh.data(), sizeof(double2) * oh.size(), hipMemcpyHostToDevice);
     }
-    double2* Y = salloc<double2>(size_t(L) * r2);
+    double2* Y = dev_alloc<double2>(size_t(L) * r2, "surrogate: device allocation failed");
     zgemm(ctx, H, L, 1, 0, Om, r2, 0, 0, Y, r2, L, r2, npair);       // Y = H^T Om
     // orthonormal basis of range(Y) by Cholesky-QR done twice, each pass through the
     // eigen-decomposition of the Gram matrix: Q1 = Y V diag(lam^-1/2) keeps the
     // directions with lam > 1e-14 lam_max (condition of Y below 1e7), and the second
     // pass restores orthogonality to rounding level
     auto chol_qr = [&](const double2* Yin, int ncol, bool cut, int* kept) {
-      double2* G = salloc<double2>(size_t(ncol) * ncol);
+      double2* G = dev_alloc<double2>(size_t(ncol) * ncol, "surrogate: device allocation failed");
       zgemm(ctx, Yin, ncol, 1, 1, Yin, ncol, 0, 0, G, ncol, ncol, ncol, L);   // G = Y^H Y
       std::vector<double> lam;
       std::vector<cd> Vg;
@@ -656,7 +640,7 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
       for (int i = 0; i < ncol; ++i)
         for (int c = 0; c < k; ++c) S[size_t(i) * k + c] = Vg[size_t(i) * ncol + c] / std::sqrt(lam[c]);
       double2* Sd = to_dev(ctx, S);
-      double2* Qo = salloc<double2>(size_t(L) * k);
+      double2* Qo = dev_alloc<double2>(size_t(L) * k, "surrogate: device allocation failed");
       zgemm(ctx, Yin, ncol, 0, 0, Sd, k, 0, 0, Qo, k, L, k, ncol);
       RF_HIP(hipStreamSynchronize(ctx->stream));
       (void)hipFree(Sd);
@@ -668,9 +652,9 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
     double2* Q = chol_qr(Q1, kr, false, &kr2);
     (void)hipFree(Q1);
     RF_CHECK(kr2 == kr, "rf_surrogate_create: basis lost rank in re-orthogonalisation");
-    double2* Bm = salloc<double2>(size_t(kr) * npair);
+    double2* Bm = dev_alloc<double2>(size_t(kr) * npair, "surrogate: device allocation failed");
     zgemm(ctx, Q, kr, 1, 1, H, L, 1, 0, Bm, npair, kr, npair, L);    // B = Q^H H^T
-    double2* M2 = salloc<double2>(size_t(kr) * kr);
+    double2* M2 = dev_alloc<double2>(size_t(kr) * kr, "surrogate: device allocation failed");
     zgemm(ctx, Bm, npair, 0, 0, Bm, npair, 1, 1, M2, kr, kr, kr, npair);   // B B^H
     std::vector<double> mu;
     std::vector<cd> W;
@@ -680,32 +664,32 @@ rf_status rf_surrogate_create(rf_ctx* ctx, const rf_grid* grid, const rf_tmpl* r
     for (int i = 0; i < kr; ++i)
       for (int c = 0; c < std::min(rank, kr); ++c) Wr[size_t(i) * rank + c] = W[size_t(i) * kr + c];
     double2* Wd = to_dev(ctx, Wr);
-    s->U = salloc<double2>(size_t(L) * rank);
+    s->U = dev_alloc<double2>(size_t(L) * rank, "surrogate: device allocation failed");
     zgemm(ctx, Q, kr, 0, 0, Wd, rank, 0, 0, s->U, rank, L, rank, kr);
     s->kr = kr;
     s->svals.clear();
     for (int c = 0; c < kr; ++c) s->svals.push_back(std::sqrt(std::max(0.0, mu[c])));
     // coefficients c_p = U^H h_p  ->  C [npair][rank] = (W^H B)^T
-    double2* Cf = salloc<double2>(size_t(npair) * rank);
+    double2* Cf = dev_alloc<double2>(size_t(npair) * rank, "surrogate: device allocation failed");
     // c_p[j] = sum_i conj(W[i][j]) B[i][p]
     zgemm(ctx, Bm, npair, 1, 0, Wd, rank, 0, 1, Cf, rank, npair, rank, kr);
     std::vector<cd> ch = to_host(ctx, Cf, size_t(npair) * rank);
     double mx = 0;
     for (const cd& v : ch) mx = std::max(mx, std::abs(v));
     s->out_scale = mx > 0 ? mx : 1.0;
-    s->T = salloc<float>(size_t(npair) * mlpdef::kOut);
+    s->T = dev_alloc<float>(size_t(npair) * mlpdef::kOut, "surrogate: device allocation failed");
     hipLaunchKernelGGL(k_to_targets, dim3(unsigned(npair)), dim3(64), 0, ctx->stream, Cf, npair, rank,
                        1.0 / s->out_scale, s->T);
     RF_HIP(hipGetLastError());
     RF_HIP(hipStreamSynchronize(ctx->stream));
     for (void* p : {(void*)H, (void*)Om, (void*)Y, (void*)Q, (void*)Bm, (void*)M2, (void*)Wd, (void*)Cf})
       (void)hipFree(p);
-    s->theta = salloc<float>(mlpdef::kParams);
-    s->grad = salloc<float>(mlpdef::kParams);
-    s->m1 = salloc<float>(mlpdef::kParams);
-    s->m2 = salloc<float>(mlpdef::kParams);
-    s->counter = salloc<int32_t>(2);
-    s->lpart = salloc<float>(kMseBlocks);
+    s->theta = dev_alloc<float>(mlpdef::kParams, "surrogate: device allocation failed");
+    s->grad = dev_alloc<float>(mlpdef::kParams, "surrogate: device allocation failed");
+    s->m1 = dev_alloc<float>(mlpdef::kParams, "surrogate: device allocation failed");
+    s->m2 = dev_alloc<float>(mlpdef::kParams, "surrogate: device allocation failed");
+    s->counter = dev_alloc<int32_t>(2, "surrogate: device allocation failed");
+    s->lpart = dev_alloc<float>(kMseBlocks, "surrogate: device allocation failed");
     *out = s;
   });
   if (st != RF_OK && s) free_surrogate(s);
@@ -756,7 +740,7 @@ rf_status rf_surrogate_grad(rf_ctx* ctx, rf_surrogate* s, const float* x, const 
     const int64_t n = int64_t(rows) * mlpdef::kOut;
     float* dout = s->out;     // gradient written in place of the outputs
     hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, ctx->stream, s->out, t, dout, s->lpart, n);
-    float* lh = salloc<float>(1);
+    float* lh = dev_alloc<float>(1, "surrogate: device allocation failed");
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, ctx->stream, s->lpart, kMseBlocks, n, lh,
                        (const int32_t*)nullptr);
     mlp_backward(ctx, s->theta, x, rows, s->pre, s->act, dout, s->d0, s->d1, grad_out);
@@ -777,7 +761,7 @@ rf_status rf_surrogate_train(rf_ctx* ctx, rf_surrogate* s, const int32_t* order,
     ensure_batch(s, batch);
     if (s->hist_cap < steps) {
       if (s->loss_hist) (void)hipFree(s->loss_hist);
-      s->loss_hist = salloc<float>(size_t(steps));
+      s->loss_hist = dev_alloc<float>(size_t(steps), "surrogate: device allocation failed");
       s->hist_cap = steps;
       if (s->exec) {
         (void)hipGraphExecDestroy(s->exec);
@@ -846,7 +830,7 @@ rf_status rf_surrogate_project(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const 
     RF_CHECK(nbr && coeffs && nk >= 1, "rf_surrogate_project: bad arguments");
     const int L = s->window;
     std::vector<rf_tmpl> refs(size_t(nk), ref);
-    H = salloc<double2>(size_t(nk) * L);
+    H = dev_alloc<double2>(size_t(nk) * L, "surrogate: device allocation failed");
     window_kernels(ctx, &s->grid, refs.data(), nbr, nk, L, H);
     // c[k][j] = sum_q conj(U[q][j]) H[k][q]
     zgemm(ctx, H, L, 0, 0, s->U, s->rank, 0, 1, static_cast<double2*>(coeffs), s->rank, nk, s->rank, L);
@@ -878,17 +862,17 @@ rf_status rf_surrogate_kernels(rf_ctx* ctx, rf_surrogate* s, const rf_grid* grid
     // coefficients (predicted by the network unless given) and kernels on the window
     const double2* cf = static_cast<const double2*>(coeffs);
     if (!cf) {
-      coef = salloc<double2>(size_t(nk) * s->rank);
+      coef = dev_alloc<double2>(size_t(nk) * s->rank, "surrogate: device allocation failed");
       predict_into(ctx, s, ref, nbr, nk, coef);
       cf = coef;
     }
-    Hk = salloc<double2>(size_t(nk) * L);
+    Hk = dev_alloc<double2>(size_t(nk) * L, "surrogate: device allocation failed");
     zgemm(ctx, cf, s->rank, 0, 0, s->U, s->rank, 1, 0, Hk, L, nk, L, s->rank);   // Hk = C U^T
     // truncation as for the exact kernels
     const double thr_tap = unit == RF_THR_PER_SECOND ? thr / grid->fs : thr;
     std::vector<int32_t> lo(nk), hi(nk);
     std::vector<uint32_t> mx(nk);
-    int32_t* lo_d = salloc<int32_t>(size_t(nk) * 3);
+    int32_t* lo_d = dev_alloc<int32_t>(size_t(nk) * 3, "surrogate: device allocation failed");
     int32_t* hi_d = lo_d + nk;
     uint32_t* mx_d = reinterpret_cast<uint32_t*>(hi_d + nk);
     fill_u32(ctx, reinterpret_cast<uint32_t*>(lo_d), 0x7FFFFFFFu, nk);
@@ -968,10 +952,10 @@ rf_status rf_surrogate_kernels(rf_ctx* ctx, rf_surrogate* s, const rf_grid* grid
       RF_CHECK(check_grid->fs == grid->fs && check_grid->f_low == grid->f_low && check_grid->f_high == grid->f_high,
                "rf_surrogate_kernels: check grid must share fs and band");
       const int64_t nc = check_grid->n;
-      float2* zr = salloc<float2>(size_t(nc));
-      float2* zs = salloc<float2>(size_t(nk) * nc);
-      float2* zd = salloc<float2>(size_t(nk) * nc);
-      float* e = salloc<float>(nk);
+      float2* zr = dev_alloc<float2>(size_t(nc), "surrogate: device allocation failed");
+      float2* zs = dev_alloc<float2>(size_t(nk) * nc, "surrogate: device allocation failed");
+      float2* zd = dev_alloc<float2>(size_t(nk) * nc, "surrogate: device allocation failed");
+      float* e = dev_alloc<float>(nk, "surrogate: device allocation failed");
       rf_status s1 = mf_ref_snr(ctx, check_grid, check_xf, check_psd, &ref, 1, zr, nullptr);
       if (s1 == RF_OK) s1 = snr_reconstruct(ctx, K, zr, nc, RF_PREC_SPLIT_FP16, zs, nullptr);
       if (s1 == RF_OK) s1 = mf_ref_snr(ctx, check_grid, check_xf, check_psd, nbr, nk, zd, nullptr);

@@ -397,21 +397,6 @@ __global__ __launch_bounds__(kOT, 1) void k_ols_mix(const float2* __restrict__ X
   }
 }
 
-template <typename T>
-T* oalloc(size_t count) {
-  void* p = nullptr;
-  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error{RF_E_NOMEM, "overlap-save: device allocation failed"};
-  }
-  return static_cast<T*>(p);
-}
-
-void ocopy(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
-  RF_HIP(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
-  RF_HIP(hipStreamSynchronize(ctx->stream));
-}
-
 void free_ols(rf_ols* O) {
   if (!O) return;
   for (void* p : {(void*)O->W, O->meta, (void*)O->X})
@@ -472,7 +457,7 @@ rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out
     for (int ph = 0; ph < 2; ++ph)
       if (used[ph]) O->phase_slot[ph] = O->nphase++;
     O->wtotal = total;
-    O->W = oalloc<float2>(size_t(std::max<int64_t>(total, 1)) * kOB);
+    O->W = dev_alloc<float2>(size_t(std::max<int64_t>(total, 1)) * kOB, "overlap-save: device allocation failed");
     // partition spectra in FP64 batches
     if (total > 0) {
       const int per = 128;
@@ -484,7 +469,7 @@ rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out
       auto flush = [&] {
         const int cnt = int(h.size() / 5);
         if (!cnt) return;
-        ocopy(ctx, pk, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice);
+        copy_sync(ctx, pk, h.data(), sizeof(int64_t) * h.size(), hipMemcpyHostToDevice);
         hipLaunchKernelGGL(k_ols_place, dim3(kOB / 256, unsigned(cnt)), dim3(256), 0, ctx->stream, K->taps64, pk,
                            M0, buf);
         RF_HIP(hipGetLastError());
@@ -512,9 +497,9 @@ rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out
     std::vector<OlsKernel> mk(nk);
     for (int k = 0; k < nk; ++k)
       mk[k] = OlsKernel{O->wofs[k], O->P[k], O->P[k] ? O->phase_slot[O->phase[k]] : 0, O->e[k], 0};
-    O->meta = oalloc<OlsKernel>(size_t(nk));
-    ocopy(ctx, O->meta, mk.data(), sizeof(OlsKernel) * nk, hipMemcpyHostToDevice);
-    O->X = oalloc<float2>(size_t(O->nphase) * size_t(n / kOH) * kOB);
+    O->meta = dev_alloc<OlsKernel>(size_t(nk), "overlap-save: device allocation failed");
+    copy_sync(ctx, O->meta, mk.data(), sizeof(OlsKernel) * nk, hipMemcpyHostToDevice);
+    O->X = dev_alloc<float2>(size_t(O->nphase) * size_t(n / kOH) * kOB, "overlap-save: device allocation failed");
     *out = O;
   });
   if (st != RF_OK && O) free_ols(O);

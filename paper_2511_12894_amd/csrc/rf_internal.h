@@ -76,6 +76,21 @@ rf_status guarded(rf_ctx* ctx, F&& f) {
   }
 }
 
+// Device allocation of `count` elements (at least one); RF_E_NOMEM on failure.
+template <typename T>
+T* dev_alloc(size_t count, const char* what = "device allocation failed") {
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * (count > 0 ? count : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{RF_E_NOMEM, what};
+  }
+  return static_cast<T*>(p);
+}
+
+// Copy on the context's stream (which need not synchronise with the null
+// stream) and wait for it.
+void copy_sync(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+
 enum WsSlot {
   WS_FFT_A = 0, WS_FFT_B = 1, WS_RED = 2, WS_SPLIT = 3, WS_PEAK = 4, WS_COEF = 5, WS_BUILD = 6,
   WS_Y = 7, WS_SCALAR = 8, WS_SCAN = 9, WS_TGT = 10
@@ -113,6 +128,11 @@ double tf2_t(const Tf2Coef& c, double f);      // t(f)  = Psi'(f) / (2 pi)
 void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int batch,
                      float2* wsa = nullptr, float2* wsb = nullptr);
 void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch);
+// The same (FP32) for `batch` inputs formed on the fly, input y being
+// conj(Q[f]) Ub[y][f - b0] * inv_n on the bins f in [b0, b0 + nb) and zero
+// elsewhere (Ub: [batch][nb]); nothing else is read.
+void fft_inverse_band_f32(rf_ctx* ctx, const float2* Q, const float2* Ub, int64_t b0, int64_t nb, float inv_n,
+                          float2* out, int64_t n, int batch);
 
 // sum over the band of f^(-7/3) / S(f) -> *moment (device double), FP64, fixed order
 void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment);

@@ -278,6 +278,12 @@ def stochastic_bank(f0: float = 20.0, m_range=(1.0, 3.0), seed: int = 1006, fidu
     return bank
 
 
+def masses_from_mc_q(mc: float, q: float):
+    """(m1, m2), m1 >= m2, of chirp mass `mc` and mass ratio q = m2 / m1."""
+    m1 = mc * (1.0 + q) ** 0.2 * q ** -0.6
+    return m1, q * m1
+
+
 # ------------------------------------------------------------------ workloads
 
 def workload_small():
@@ -415,3 +421,19 @@ def surrogate_random_inputs(seed: int, npair: int, nomega: int, steps: int, batc
     need = steps * batch
     order = np.concatenate([rng.permutation(npair) for _ in range(need // npair + 1)])[:need]
     return omega, theta, order.reshape(steps, batch).astype(np.int32)
+
+
+def workload_sweep(mc: float, q: float, snr: float = 20.0, seed: int = 1007, duration: float = 512.0,
+                   fs: float = 4096.0, f_low: float = 20.0, t0: float = 400.0):
+    """Accuracy sweep case (the paper's SNR-loss study): 512 s at 4096 Hz,
+    f_low = 20 Hz, coloured noise plus one injection of chirp mass `mc` and
+    mass ratio q at optimal SNR `snr`, coalescing at t0; the reference of the
+    study has the same chirp mass and q = 0.6."""
+    n = int(round(duration * fs))
+    grid = make_grid(fs, n, f_low)
+    psd = make_psd(grid)
+    tgt = masses_from_mc_q(mc, q)
+    xf = noise(grid, psd, seed=seed + int(round(1000 * q)))
+    xf = inject(grid, psd, xf, tgt[0], tgt[1], snr, t0, 0.0)
+    return dict(name=f"sweep-mc{mc}-q{q}", grid=grid, psd=psd, xf=xf, ref=masses_from_mc_q(mc, 0.6), tgt=tgt,
+                t0=t0)

@@ -302,6 +302,11 @@ def test_reconstruct_fft_equals_bruteforce():
     np.testing.assert_allclose(a, b, atol=1e-12)
     idx = np.array([0, 5, 500, 511])
     np.testing.assert_allclose(ratio.reconstruct_samples(z, -11, taps, 0.8, idx), b[idx], atol=1e-12)
+    np.testing.assert_allclose(ratio.reconstruct_oa(z, -11, taps, 0.8), b, atol=1e-12)
+    # a kernel wider than the segment wraps more than once
+    wide = rng.standard_normal(1100)
+    np.testing.assert_allclose(ratio.reconstruct_oa(z, 7, wide, 1.0), ratio.reconstruct_bruteforce(z, 7, wide, 1.0),
+                               atol=1e-10)
     # definition written out for one output sample
     m = 3
     direct = 0.8 * sum(z[(m - 11 + l) % 512] * taps[l] for l in range(37))
