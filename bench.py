@@ -354,7 +354,19 @@ def stress_leg(dev, ctx):
                 rf.mf_ref_snr(ctx, g, xf, psd, part, z=zb, want_sigma=False)
                 rf.snr_peaks(ctx, zb[:len(part)], 6.0, trig_cap=1 << 18)
 
+    plans = [rf.Ols(ctx, K, g.n) for K in ksets]
+
+    def ols():
+        for r, O in zip(w["refs"], plans):
+            rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
+            O.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)
+
     stream = torch.cuda.current_stream(dev)
+    ols()
+    t_ols, _ = timed(ols, 1, 0, stream)
+    pmax = max(O.info()["pmax"] for O in plans)
+    for O in plans:
+        O.free()
     ratio()
     t_ratio, _ = timed(ratio, 1, 0, stream)
     direct()
@@ -365,6 +377,7 @@ def stress_leg(dev, ctx):
     res = dict(templates=ntpl, kernel_taps_min=int(lens.min()), kernel_taps_max=int(lens.max()),
                kernel_build_s=t_build, ratio_ms=t_ratio, direct_ms=t_direct,
                ratio_value=samples / (t_ratio * 1e-3), direct_value=samples / (t_direct * 1e-3),
+               ols_ms=t_ols, ols_value=samples / (t_ols * 1e-3), ols_partitions_max=pmax,
                unit="template-samples/s", recon_tflops=flops / (t_ratio * 1e-3) / 1e12,
                recon_fp16_frac=flops / (t_ratio * 1e-3) / 1e12 / PEAK_FP16_TFLOPS)
     del zb, zref
@@ -375,7 +388,7 @@ def stress_leg(dev, ctx):
 
 SWEEP_MC = (0.871, 1.219, 1.741, 2.612)
 SWEEP_Q = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
-SWEEP_THR = (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
+SWEEP_THR = (1.0, 3e-1, 1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
 
 
 def sweep_leg(dev, ctx):
@@ -406,9 +419,9 @@ def sweep_leg(dev, ctx):
                 rows.append(dict(q=q, thr=thr, taps=L, x=L / g.fs / tau_t, loss=abs(rho_r - rho_m) / rho_m,
                                  rho_direct=rho_m))
             del z, zr, xf, psd
-        # where the loss (worst over q) first stays below 1e-3 and 1e-4, in tau_ratio / tau_target
+        # where the loss (worst over q) first stays below 1e-4 and 1e-5, in tau_ratio / tau_target
         cross = {}
-        for level in (1e-3, 1e-4):
+        for level in (1e-4, 1e-5):
             xs = []
             for q in SWEEP_Q:
                 pts = sorted((r["x"], r["loss"]) for r in rows if r["q"] == q)
@@ -420,7 +433,7 @@ def sweep_leg(dev, ctx):
             x_min=min(r["x"] for r in at_paper), x_max=max(r["x"] for r in at_paper),
             loss_max=max(r["loss"] for r in at_paper)))
         log(f"bench: sweep Mc {mc}: loss at 1e-3/s <= {out[str(mc)]['paper_threshold']['loss_max']:.2e}, "
-            f"x where loss < 1e-3: {cross['0.001']}")
+            f"x where loss < 1e-5: {cross['1e-05']}")
     return out
 
 
