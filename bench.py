@@ -128,13 +128,18 @@ def cpu_baseline(w, n_nbr_sample, n_cmp=12):
                                           "kernel, reference filter shared by the 257-template group"))
 
 
-def batched_leg(dev):
-    """Batched uneven workload (reduced): 4 segments of 32 s at 1024 Hz, 8
-    references with 8..96 lattice neighbours (log-uniform), one persistent
-    split-FP16 launch in a captured graph with autotuned chunks, against the
-    per-(segment, reference) call loop on the same data."""
-    wb = synth.workload_batched(n_seg=4, n_ref=8, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
-                                nbr_range=(8, 96))
+def batched_leg(dev, full=False):
+    """Batched uneven workload, one persistent split-FP16 launch in a captured
+    graph, against the per-(segment, reference) call loop on the same data.
+    Reduced (default): 4 segments of 32 s at 1024 Hz, 8 references with 8..96
+    lattice neighbours (log-uniform), autotuned chunks.  Full: 8 segments of
+    256 s at 4096 Hz, 64 references with 32..512 neighbours, chunks of 512
+    taps (the autotuner's trial launches would take minutes at this size)."""
+    if full:
+        wb = synth.workload_batched()
+    else:
+        wb = synth.workload_batched(n_seg=4, n_ref=8, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
+                                    nbr_range=(8, 96))
     g = wb["grid"]
     stream = torch.cuda.Stream(dev)
     ctx = rf.Context(0, stream)
@@ -144,14 +149,18 @@ def batched_leg(dev):
     with torch.cuda.stream(stream):
         ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
         batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=len(wb["segments"]))
-        chunks = batch.autotune(xf)
+        if full:
+            batch.set_chunks([512, 512, 512])
+            chunks = batch.info()["chunks"]
+        else:
+            chunks = batch.autotune(xf)
         sum_l = sum(sum(k.info()["len"]) for k in ksets)
-        batch.run(xf, 6.0)
+        batch.run(xf, 6.0, trig_cap=1 << 20)
         stream.synchronize()
         t0 = time.perf_counter()
-        reps = 3
+        reps = 1 if full else 3
         for _ in range(reps):
-            out = batch.run(xf, 6.0)
+            out = batch.run(xf, 6.0, trig_cap=1 << 20)
         t_batch = (time.perf_counter() - t0) / reps
         z = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
 
@@ -170,8 +179,8 @@ def batched_leg(dev):
     ktot = batch.ktotal
     flops = 4.0 * g.n * sum_l * nseg
     samples = (ktot + len(wb["refs"])) * g.n * nseg
-    res = dict(workload=wb["name"] + "-reduced", segments=nseg, references=len(wb["refs"]),
-               kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks,
+    res = dict(workload=wb["name"] + ("" if full else "-reduced"), segments=nseg, references=len(wb["refs"]),
+               kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks, sum_taps=sum_l,
                batch_ms=t_batch * 1e3, loop_ms=t_loop * 1e3, speedup=t_loop / t_batch,
                value=samples / t_batch, unit="template-samples/s",
                frac_fp16_peak=flops / t_batch / 1e12 / PEAK_FP16_TFLOPS, ntrig=out["ntrig"])
@@ -392,8 +401,8 @@ SWEEP_THR = (1.0, 3e-1, 1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
 
 
 def sweep_leg(dev, ctx):
-    """SNR loss against kernel length (the paper's Fig. 3 study and its
-    chirp-mass appendix): for each chirp mass and mass ratio, one injection at
+    """SNR loss against kernel length (sec. II.D, Fig. 3, and appendix B on the
+    chirp mass): for each chirp mass and mass ratio, one injection at
     SNR 20 in coloured noise (512 s, 4096 Hz, f_low 20 Hz); reference of the
     same chirp mass at q = 0.6; the target's kernel truncated at each
     threshold; loss = |peak |z| reconstructed - peak |z| direct| / direct,
@@ -548,7 +557,7 @@ def main():
     ap.add_argument("--cpu-nbrs", type=int, default=24)
     ap.add_argument("--only", default="",
                     help="comma list of legs to run: step,fp32,direct,factored,ols,bank,batched,learned "
-                         "(default: all of them), sweep and stress (only when named)")
+                         "(default: all of them), sweep, stress and batched_full (only when named)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -659,6 +668,9 @@ def main():
     if "batched" in legs:
         log("bench: batched uneven workload")
         res["batched"] = batched_leg(dev)
+    if "batched_full" in legs:
+        log("bench: batched uneven workload at full size")
+        res["batched_full"] = batched_leg(dev, full=True)
     if "learned" in legs:
         log("bench: learned kernels (training, inference, check and fallback)")
         res["learned"] = learned_leg(dev, w, psd, xf, K, build_s, args.steps)
@@ -713,6 +725,8 @@ def main():
         extra["stress"] = res["stress"]
     if "batched" in res:
         extra["batched"] = res["batched"]
+    if "batched_full" in res:
+        extra["batched_full"] = res["batched_full"]
     if "learned" in res:
         extra["learned"] = res["learned"]
     out["extra"] = extra

@@ -207,7 +207,7 @@ rf_status rf_batch_free(rf_batch* b);
  * and 1.5PN chirp times at f_low) to the coefficients U^H h / scale (real parts,
  * then imaginary parts).  The exact FP64 build provides the training data and
  * the fallback.  Not part of the paper: an extension for storage and build
- * time; its error is always judged against the exact kernels. */
+ * time; its error is always measured against the exact kernels. */
 typedef struct rf_surrogate rf_surrogate;
 
 /* Training set: npair pairs (refs[p], nbrs[p]) (host), kernels built exactly
