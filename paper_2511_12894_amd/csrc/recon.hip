@@ -641,7 +641,7 @@ void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const 
   else                                                                                          \
     hipLaunchKernelGGL((k_recon_f16<S, F>), grid, dim3(256), 0, ctx->stream,                    \
                        static_cast<const __half*>(zsrc), n, tiles, K->b16, K->colscale16,       \
-                       K->slot_kernel, zinv, zout, po, int(kChunk));
+                       K->slot_kernel, zinv, zout, po, int(kChunkMax));
   if (store && fused) {
     RF_RECON(true, true)
   } else if (store) {
