@@ -133,8 +133,9 @@ def batched_leg(dev, full=False):
     graph, against the per-(segment, reference) call loop on the same data.
     Reduced (default): 4 segments of 32 s at 1024 Hz, 8 references with 8..96
     lattice neighbours (log-uniform), autotuned chunks.  Full: 8 segments of
-    256 s at 4096 Hz, 64 references with 32..512 neighbours, chunks of 512
-    taps (the autotuner's trial launches would take minutes at this size)."""
+    256 s at 4096 Hz, 64 references with 32..512 neighbours, chunks of 512 /
+    1024 / 1024 taps per length bucket (the autotuner's trial launches would
+    take minutes at this size)."""
     if full:
         wb = synth.workload_batched()
     else:
@@ -150,7 +151,7 @@ def batched_leg(dev, full=False):
         ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
         batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=len(wb["segments"]))
         if full:
-            batch.set_chunks([512, 512, 512])
+            batch.set_chunks([512, 1024, 1024])
             chunks = batch.info()["chunks"]
         else:
             chunks = batch.autotune(xf)
