@@ -86,7 +86,7 @@ def test_full_rank_equals_the_exact_kernels(rf, ctx, small, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("J", [3, 8])
+@pytest.mark.parametrize("J", [1, 3, 8])
 def test_rank_j_matches_the_oracle_projection(rf, ctx, small, J, prec):
     w = small["w"]
     F = rf.Factored(ctx, small["K"], w["grid"], tol=0.0, jmax=J)

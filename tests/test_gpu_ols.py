@@ -156,6 +156,52 @@ def test_trigger_overflow_keeps_the_count(rf, ctx, real64):
     O.free()
 
 
+def test_empty_and_delta_kernels(rf, ctx, small):
+    """A threshold no kernel reaches leaves them all empty (zero series, peak 0
+    at sample 0); at 500 / s the reference itself keeps the central taps of
+    its band-limited delta while farther neighbours may keep none: every
+    series against the oracle with the same truncation."""
+    w = small["w"]
+    g = w["grid"]
+    psd = small["psd"]
+    K0 = rf.ratio_kernel_build(ctx, g, psd, w["ref"], w["nbrs"][:3], thr=1e9)
+    assert K0.info()["len"] == [0, 0, 0]
+    O = rf.Ols(ctx, K0, g.n)
+    out = O.reconstruct(small["z"], fused_thr=1.0)
+    assert torch.count_nonzero(out["z"]).item() == 0
+    v, i = rf.decode_peaks(out["peaks"])
+    assert list(v) == [0.0, 0.0, 0.0] and list(i) == [0, 0, 0] and out["ntrig"] == 0
+    O.free()
+    K0.free()
+    nbrs = [w["nbrs"][0], w["ref"], w["nbrs"][5]]
+    K = rf.ratio_kernel_build(ctx, g, psd, w["ref"], nbrs, thr=500.0)
+    lens = K.info()["len"]
+    assert lens[1] >= 1
+    O = rf.Ols(ctx, K, g.n)
+    z = O.reconstruct(small["z"])["z"].cpu().numpy()
+    for k, nb in enumerate(nbrs):
+        kb = orat.build_kernel(g, w["ref"], nb, threshold=500.0)
+        nk = omf.norm(g.fs, g.n, g.f_low, g.f_high, w["psd"], omf.template_spectrum(g.fs, g.n, *nb))
+        zo = orat.reconstruct(small["zr"], kb["m_lo"], kb["taps"], small["nr"] / nk)
+        assert np.abs(z[k] - zo).max() <= 1e-5, (k, lens)
+    O.free()
+    K.free()
+
+
+def test_kernels_built_on_a_shorter_period(rf, ctx, small):
+    """Kernels built with n_build = n / 4 applied to the full segment: the same
+    series as the dense reconstruction of that kernel set."""
+    w = small["w"]
+    g = w["grid"]
+    K = rf.ratio_kernel_build(ctx, g, small["psd"], w["ref"], w["nbrs"][:6], n_build=g.n // 4)
+    O = rf.Ols(ctx, K, g.n)
+    z = O.reconstruct(small["z"])["z"]
+    zd = rf.snr_reconstruct(ctx, K, small["z"], prec="fp32")["z"]
+    assert (z - zd).abs().max().item() <= 1e-5
+    O.free()
+    K.free()
+
+
 def test_argument_errors(rf, ctx, small):
     g = small["w"]["grid"]
     h = __import__("ctypes").c_void_p()
