@@ -309,10 +309,10 @@ rf_status rf_factored_free(rf_factored* F);
 typedef struct rf_ols rf_ols;
 
 /* Plan for kernel set K on series of n samples (a power of two in
- * [4096, 2^24]): partition spectra of every kernel and the block-spectrum
- * buffers (2 x 2n complex64 at most).  Kernels of more than 4 partitions (over
- * about 14k taps) work but read their spectra from the cache per block.
- * Synchronises. */
+ * [4096, 2^24], at least the kernels' build length): partition spectra of
+ * every kernel and the block-spectrum buffers (2 x 2n complex64 at most).
+ * Kernels of more than 4 partitions (over about 14k taps) work but read their
+ * spectra from the cache per block.  Synchronises. */
 rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out);
 /* Host copies (any may be NULL): transform length B, hop H, largest partition
  * count, partitions of each kernel [nk], bytes of partition spectra. */

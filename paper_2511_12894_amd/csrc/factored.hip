@@ -593,6 +593,7 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     const int nk = K->nk;
     const int64_t n = grid->n;
     RF_CHECK(n % kMixTimesMax == 0, "rf_factored_build: n must be a multiple of 256");
+    RF_CHECK(n >= K->n_build, "rf_factored_build: grid shorter than the kernels' build length");
     int64_t M0 = INT64_MAX, M1 = INT64_MIN;
     for (int k = 0; k < nk; ++k)
       if (K->len[k] > 0) {

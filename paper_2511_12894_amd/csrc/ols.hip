@@ -423,6 +423,7 @@ rf_status rf_ols_build(rf_ctx* ctx, const rf_kernels* K, int64_t n, rf_ols** out
     *out = nullptr;
     RF_CHECK(K->device == ctx->device, "rf_ols_build: kernel set on another device");
     RF_CHECK(is_pow2(n) && n >= kOH && n <= (int64_t(1) << 24), "rf_ols_build: n must be a power of two in [4096, 2^24]");
+    RF_CHECK(n >= K->n_build, "rf_ols_build: n shorter than the kernels' build length");
     const int nk = K->nk;
     RF_CHECK(nk >= 1, "rf_ols_build: empty kernel set");
     O = new rf_ols();

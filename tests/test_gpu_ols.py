@@ -205,7 +205,7 @@ def test_kernels_built_on_a_shorter_period(rf, ctx, small):
 def test_argument_errors(rf, ctx, small):
     g = small["w"]["grid"]
     h = __import__("ctypes").c_void_p()
-    for bad in (g.n + 1, 2048, 1 << 25):
+    for bad in (g.n + 1, 2048, 1 << 25, g.n // 2):        # the last: shorter than the kernels' build
         st = ctx.lib.rf_ols_build(ctx.h, small["K"].h, bad, __import__("ctypes").byref(h))
         assert st == rf.RF_E_INVAL, bad
     O = rf.Ols(ctx, small["K"], g.n)
