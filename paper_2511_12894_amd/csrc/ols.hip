@@ -24,9 +24,10 @@
 // consecutive blocks); a thread owns the 16 frequencies j + 512 q, which are
 // exactly the inputs of the first radix-16 stage of a Stockham inverse
 // transform, so the products never pass through LDS.  The 8192-point transform
-// then takes two more radix-16 stages in LDS and the half of the final radix-2
-// stage that gives the H valid outputs, written straight to the series (runs of
-// 512 consecutive samples) and fed to the fused read-out.  Kernels of at most four partitions keep their
+// then takes two more radix-16 stages in LDS (two buffers used in turn, three
+// barriers a block) and the half of the final radix-2 stage that gives the H
+// valid outputs, written straight to the series (runs of 512 consecutive
+// samples) and fed to the fused read-out.  Kernels of at most four partitions keep their
 // spectra in registers for the whole work item; longer ones read them from the
 // cache per block.  Workgroups of one wave of items share the run of blocks,
 // so the block spectra come from L2.
@@ -182,29 +183,34 @@ __device__ inline void twiddle_powers(float2* v, float2 w1, float2 w4) {
 }
 
 // Stockham inverse transform of 8192 points after its first radix-16 stage
-// (which wrote s[pad(16 j + q)]): radix 16 at sub-lengths 16 and 256 in LDS,
-// then the half of the final radix-2 stage that gives outputs t < 4096:
-// out[i] = output j + 512 i, i < 8.  With full = true the other half too
-// (out[8 + i] = output 4096 + j + 512 i).
+// (which wrote a[pad(16 j + q)] and was followed by a barrier): radix 16 at
+// sub-lengths 16 (a -> b) and 256 (b -> a) in LDS, one barrier after each
+// (ping-pong buffers: a stage never overwrites what another thread still
+// reads), then the half of the final radix-2 stage that gives outputs
+// t < 4096 from a: out[i] = output j + 512 i, i < 8.  With full = true the
+// other half too (out[8 + i] = output 4096 + j + 512 i).  Buffer b is free on
+// return; a until every thread has passed the next barrier.
 template <bool FULL>
-__device__ inline void finish_transform(float2* s, const Twiddle& tw, float2 (&out)[FULL ? 16 : 8]) {
+__device__ inline void finish_transform(float2* a, float2* b, const Twiddle& tw, float2 (&out)[FULL ? 16 : 8]) {
   const int j = threadIdx.x;
 #pragma unroll
   for (int st = 0; st < 2; ++st) {
     const int ns = st == 0 ? 16 : 256;
     const int step = st == 0 ? 32 : 2;          // B / (ns R)
     const int k = j & (ns - 1);
+    const float2* src = st == 0 ? a : b;
+    float2* dst = st == 0 ? b : a;
     float2 v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = s[pad(j + 512 * q)];
+    for (int q = 0; q < 16; ++q) v[q] = src[pad(j + 512 * q)];
     twiddle_powers(v, twiddle(tw, k * step), twiddle(tw, 4 * k * step));
     dft16(v);
-    __syncthreads();
     const int d = (j / ns) * ns * 16 + k;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s[pad(d + q * ns)] = v[q];
+    for (int q = 0; q < 16; ++q) dst[pad(d + q * ns)] = v[q];
     __syncthreads();
   }
+  const float2* s = a;
   // radix 2 at sub-length 4096: output t = a + w^t b, t + 4096 = a - w^t b
   const float2 wj = twiddle(tw, j);
 #pragma unroll
@@ -231,7 +237,7 @@ __device__ inline void load16(const float2* p, float2 (&v)[16]) {
 // workgroup per (block c, phase set), stored thread-major.
 __global__ __launch_bounds__(kOT) void k_ols_blocks(const float2* __restrict__ z, int64_t n, int64_t M0,
                                                     int phase0, float2* __restrict__ X) {
-  __shared__ float2 s[kPadN];
+  __shared__ float2 s[2][kPadN];
   __shared__ Twiddle tw;
   const int j = threadIdx.x;
   const int64_t c = blockIdx.x;
@@ -244,10 +250,10 @@ __global__ __launch_bounds__(kOT) void k_ols_blocks(const float2* __restrict__ z
   for (int q = 0; q < 16; ++q) v[q] = conj2(z[(base + j + 512 * q) & (n - 1)]);
   dft16(v);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) s[pad(16 * j + q)] = v[q];
+  for (int q = 0; q < 16; ++q) s[0][pad(16 * j + q)] = v[q];
   __syncthreads();
   float2 o[16];
-  finish_transform<true>(s, tw, o);
+  finish_transform<true>(s[0], s[1], tw, o);
   float2* out = X + (int64_t(blockIdx.y) * nb + c) * kOB;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -288,9 +294,10 @@ template <bool WREG, bool STORE, bool FUSED>
 __global__ __launch_bounds__(kOT, 1) void k_ols_mix(const float2* __restrict__ X, const float2* __restrict__ W,
                                                     const OlsKernel* __restrict__ meta, int nk, int64_t n,
                                                     float2* __restrict__ zout, PeakOut po) {
-  __shared__ float2 s[kPadN];
+  __shared__ float2 s[2][kPadN];
   __shared__ Twiddle tw;
   __shared__ Best wbest[kOT / 64];
+  int par = 0;                    // buffer roles swap every block
   const int j = threadIdx.x;
   const int64_t nb = n / kOH;
   const int64_t nchunks = (nb + kOChunk - 1) / kOChunk;
@@ -338,12 +345,16 @@ __global__ __launch_bounds__(kOT, 1) void k_ols_mix(const float2* __restrict__ X
         }
       }
       dft16(v);
-      __syncthreads();            // the previous block's last stage has read s
+      // a = the buffer the previous block's transform left free (its last
+      // stage read the other one); one barrier before the next stage reads it
+      float2* a = s[par];
+      float2* bb = s[par ^ 1];
+      par ^= 1;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s[pad(16 * j + q)] = v[q];
+      for (int q = 0; q < 16; ++q) a[pad(16 * j + q)] = v[q];
       __syncthreads();
       float2 o[8];
-      finish_transform<false>(s, tw, o);
+      finish_transform<false>(a, bb, tw, o);
       const int64_t m0 = b * kOH + j;            // outputs m0 + 512 i, i < 8
       if (STORE) {
         float2* zr = zout + int64_t(k) * n + m0;
