@@ -15,12 +15,14 @@
 // A workgroup owns 256 output times x 32 kernels; each of its four wavefronts
 // owns 64 times as two 32 x 32 MFMA tiles (real and imaginary part each).  The
 // Hankel operand comes from a sliding window of z_ref staged in LDS (double
-// buffered, refilled from registers loaded during the previous chunk); B is
-// pre-packed in fragment order, so each operand is one coalesced load.
-// Software pipelining: a four-slot register ring keeps the loads of step s + 3
-// in flight while step s runs on the matrix cores.  Accumulation restarts per
-// chunk and is added into a second FP32 total, bounding the rounding growth
-// over long kernels.
+// buffered: the next chunk's window is loaded into registers and stored to
+// the idle buffer while the current chunk computes); B is pre-packed in
+// fragment order, so each operand is one coalesced load.  Software
+// pipelining: register rings keep the loads of later steps in flight while
+// step s runs on the matrix cores, and the loads are issued one behind each
+// matrix instruction rather than in a block.  The matrix-core accumulators
+// are folded into an FP64 running total at fixed intervals, bounding the
+// rounding growth over long kernels.
 //
 // Two arithmetic forms: FP32 operands on the FP32 matrix cores
 // (v_mfma_f32_32x32x2_f32), and split FP16 (z = z_hi + z_lo, w = w_hi + w_lo
@@ -97,7 +99,7 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
 // Window of a chunk: samples z[(n0 + m0 + t0 + i) mod n], i < ch + kTimes + 32
 // (32 extra so that the prefetch of three steps ahead stays inside the buffer).
 constexpr int kWin = kChunk + kTimes + 32;
-constexpr int kWinMax = kChunkMax + kTimes + 64;   // F fragments are read up to 5 steps past a chunk
+constexpr int kWinMax = kChunkMax + kTimes + 64;   // F fragments are read up to 4 steps past a chunk
 constexpr int kStage = (kWin + 255) / 256;
 static_assert(kWin % 2 == 0, "window pairs");
 
@@ -212,6 +214,17 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
         for (int ri = 0; ri < 2; ++ri)
           acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x2f32(aa[tb][ri], bb, acc[tb][ri], 0, 0, 0);
     };
+    // the loads of a later step issue one behind each matrix instruction
+    auto interleave = [] {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
+      for (int i = 0; i < 3; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    };
     load(0, bq[0], aq[0]);
     load(1, bq[1], aq[1]);
     load(2, bq[2], aq[2]);
@@ -221,17 +234,17 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     for (int s64 = 0; s64 < nst; s64 += 64) {
       for (int s = s64; s < s64 + 64; s += 4) {
         load(s + 3, bq[3], aq[3]);
-        __builtin_amdgcn_sched_barrier(0);
         mma(bq[0], aq[0]);
+        interleave();
         load(s + 4, bq[0], aq[0]);
-        __builtin_amdgcn_sched_barrier(0);
         mma(bq[1], aq[1]);
+        interleave();
         load(s + 5, bq[1], aq[1]);
-        __builtin_amdgcn_sched_barrier(0);
         mma(bq[2], aq[2]);
+        interleave();
         load(s + 6, bq[2], aq[2]);
-        __builtin_amdgcn_sched_barrier(0);
         mma(bq[3], aq[3]);
+        interleave();
       }
       fold64(tot, acc);
     }
@@ -307,9 +320,11 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // Window refill in 4-position blocks: block k of every copy sg holds samples
   // 4k + sg .. 4k + sg + 3, 16 contiguous halves (32 bytes) in the interleaved
   // layout, so block k needs samples 4k .. 4k + 6, two aligned 4-sample loads
-  // per plane.  Thread t handles block t, staged in registers while the
-  // previous chunk computes, and block t + 256 (chunks above 736 taps only)
-  // loaded at refill time.
+  // per plane.  Thread t handles block t and, for chunks above 736 taps, block
+  // t + 256.  The next chunk's window goes into the idle buffer in two rounds
+  // early in the chunk, each loaded into the same staging registers several
+  // steps before it is stored, so no refill load is waited for at the chunk
+  // boundary.
   const int nblk = win_len / 4;
   uint2 stage[4][2];
   auto load_blk = [&](int64_t t0, int k, uint2 (&v)[4][2]) {
@@ -335,21 +350,17 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       dst[1] = make_uint4(w1, w2, o1, o2);
     }
   };
-  auto gather = [&](int64_t t0) {
-    if (int(threadIdx.x) < nblk) load_blk(t0, threadIdx.x, stage);
+  auto gather = [&](int64_t t0, int k) {
+    if (k < nblk) load_blk(t0, k, stage);
   };
-  auto put = [&](int64_t t0, int buf) {
-    if (int(threadIdx.x) < nblk) store_blk(buf, threadIdx.x, stage);
-    const int k = threadIdx.x + 256;
-    if (k < nblk) {
-      uint2 v[4][2];
-      load_blk(t0, k, v);
-      store_blk(buf, k, v);
-    }
+  auto put = [&](int buf, int k) {
+    if (k < nblk) store_blk(buf, k, stage);
   };
   if (nch > 0) {
-    gather(0);
-    put(0, 0);
+    gather(0, threadIdx.x);
+    put(0, threadIdx.x);
+    gather(0, threadIdx.x + 256);
+    put(0, threadIdx.x + 256);
   }
   __syncthreads();
   // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
@@ -368,7 +379,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
     const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
     const int buf = c & 1;
     const bool more = c + 1 < nch;
-    if (more) gather(t0 + chunk);
+    if (more) gather(t0 + chunk, threadIdx.x);
     const _Float16* wb[4];
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
@@ -397,20 +408,49 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
           }
     };
 #pragma unroll
-    for (int j = 0; j < 5; ++j) loadF(j, f[j]);
-    // F runs five steps ahead, B six (slots step % 8)
+    for (int j = 0; j < 4; ++j) loadF(j, f[j]);
+    // F runs four steps ahead, B six (slots step % 8); the LDS counter holds
+    // at most 15 fragment reads in flight, so more would only wait by count
     auto steps = [&](int q, auto count) {
 #pragma unroll
       for (int h = 0; h < decltype(count)::value; ++h) {
-        loadF(q + h + 5, f[(h + 5) & 7]);
+        loadF(q + h + 4, f[(h + 4) & 7]);
         loadB(s0 + q + h + 6, bh[(h + 6) & 7], bl[(h + 6) & 7]);
-        __builtin_amdgcn_sched_barrier(0);
         mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
+        // one load issued behind each of the step's first six MFMAs (the
+        // four fragment reads, then the two operand loads), then the other
+        // six: every load issues while a matrix instruction runs
+        for (int i = 0; i < 4; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+        }
+        for (int i = 0; i < 2; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
         __builtin_amdgcn_sched_barrier(0);
       }
     };
-    // acc is folded every 32 steps and at the chunk's end
+    // acc is folded after every 32 steps and at the chunk's end.  A chunk of
+    // 32 or 64 steps that is followed by another starts with two refill
+    // rounds of 16 steps each in straight-line code, so that each round's
+    // staging registers are waited for only by count, behind the operand
+    // loads issued since.
     int q = 0;
+    auto refill_rounds = [&](auto P) {
+      constexpr int p = decltype(P)::value;
+      steps(0, P);
+      put(buf ^ 1, threadIdx.x);
+      gather(t0 + chunk, threadIdx.x + 256);
+      steps(p, P);
+      put(buf ^ 1, threadIdx.x + 256);
+      q = 2 * p;
+    };
+    if (more && nst >= 32) {
+      refill_rounds(std::integral_constant<int, 16>{});
+      fold64(acc);
+    }
     for (; q + 32 <= nst; q += 32) {
       steps(q, std::integral_constant<int, 32>{});
       fold64(acc);
@@ -419,7 +459,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
       fold64(acc);
     }
-    if (more) put(t0 + chunk, buf ^ 1);
+    if (more && nst < 32) put(buf ^ 1, threadIdx.x);   // 16-step chunks: one round (at most 256 blocks)
     __syncthreads();
   }
   fold64(cor);
