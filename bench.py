@@ -694,7 +694,7 @@ def main():
                            "kernel": "k_recon_f16 (split-FP16 reconstruction)",
                            "mfma_products_frac": 3 * ach / PEAK_FP16_TFLOPS,
                            "executed_over_useful_taps": exec_taps / sum_l,
-                           "mfma_busy_frac": 3 * 4.0 * n * exec_taps / t_rec / 1e12 / PEAK_FP16_TFLOPS}
+                           "executed_frac_of_peak": 3 * 4.0 * n * exec_taps / t_rec / 1e12 / PEAK_FP16_TFLOPS}
     out["config"] = {"workload": w["name"], "n": n, "fs": g.fs, "f_low": g.f_low, "f_high": g.f_high,
                      "neighbours": len(nbrs), "threshold_per_s": 1e-3, "kernel_taps_min": int(lens.min()),
                      "kernel_taps_max": int(lens.max()), "kernel_taps_sum": sum_l,
