@@ -334,7 +334,9 @@ def stress_leg(dev, ctx):
     Per reference: its matched filter + fused split-FP16 reconstruction of the
     1024 series (peaks and triggers, series not stored: 4096 x 2^23 complex64
     would be 275 GB), against direct FFT matched filtering of the same 4096
-    templates with the same read-out; kernel builds timed apart.  The learned
+    templates with the same read-out, the blocked frequency-domain form and the
+    factored form (four 256-kernel sets per reference, peaks checked against
+    direct matched filtering); kernel builds timed apart.  The learned
     kernels are not used here: a surrogate trained at f_low = 20 Hz does not
     transfer to this band (every kernel would take the exact fallback)."""
     w = synth.workload_stress()
@@ -381,6 +383,48 @@ def stress_leg(dev, ctx):
     t_ratio, _ = timed(ratio, 1, 0, stream)
     direct()
     t_direct, _ = timed(direct, 1, 0, stream)
+    # peaks of every neighbour by direct matched filtering (untimed), for the factored form's check
+    pk_direct = []
+    for grp in w["groups"]:
+        for a in range(0, len(grp), 128):
+            part = list(grp[a:a + 128])
+            rf.mf_ref_snr(ctx, g, xf, psd, part, z=zb, want_sigma=False)
+            pk_direct.append(rf.decode_peaks(rf.snr_peaks(ctx, zb[:len(part)], 1e9)["peaks"])[0])
+    pk_direct = np.concatenate(pk_direct)
+    # factored form: the library's basis covers up to 256 kernels, so each reference's 1024
+    # neighbours form four sets of 256 (consecutive lattice points), each with its own basis
+    t0 = time.perf_counter()
+    fsets = []
+    for r, grp in zip(w["refs"], w["groups"]):
+        sets = []
+        for a in range(0, len(grp), 256):
+            Kg = rf.ratio_kernel_build(ctx, g, psd, r, list(grp[a:a + 256]))
+            sets.append((Kg, rf.Factored(ctx, Kg, g, tol=2e-6)))
+        fsets.append(sets)
+    torch.cuda.synchronize()
+    t_fbuild = time.perf_counter() - t0
+    fpk = []
+
+    def factored(collect=False):
+        for r, sets in zip(w["refs"], fsets):
+            rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
+            for Kg, F in sets:
+                o = F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)
+                if collect:
+                    fpk.append(rf.decode_peaks(o["peaks"])[0])
+
+    factored(collect=True)
+    t_fact, _ = timed(factored, 1, 0, stream)
+    jinfo = [F.info() for sets in fsets for _, F in sets]
+    for sets in fsets:
+        for Kg, F in sets:
+            F.free()
+            Kg.free()
+    fact = dict(sets=len(jinfo), J_min=min(i["J"] for i in jinfo), J_max=max(i["J"] for i in jinfo),
+                resid_max=float(max(max(i["resid"]) for i in jinfo)), build_s=t_fbuild, ms=t_fact,
+                value=(len(lens) + len(w["refs"])) * g.n / (t_fact * 1e-3),
+                peak_err_vs_direct=float(np.abs(np.concatenate(fpk) - pk_direct).max()))
+    fact["within_2e-4"] = fact["peak_err_vs_direct"] <= 2e-4
     ntpl = len(lens) + len(w["refs"])
     samples = ntpl * g.n
     flops = 4.0 * g.n * float(lens.sum())
@@ -389,7 +433,7 @@ def stress_leg(dev, ctx):
                ratio_value=samples / (t_ratio * 1e-3), direct_value=samples / (t_direct * 1e-3),
                ols_ms=t_ols, ols_value=samples / (t_ols * 1e-3), ols_partitions_max=pmax,
                unit="template-samples/s", recon_tflops=flops / (t_ratio * 1e-3) / 1e12,
-               recon_fp16_frac=flops / (t_ratio * 1e-3) / 1e12 / PEAK_FP16_TFLOPS)
+               recon_fp16_frac=flops / (t_ratio * 1e-3) / 1e12 / PEAK_FP16_TFLOPS, factored=fact)
     del zb, zref
     for K in ksets:
         K.free()
@@ -529,6 +573,7 @@ def _learned(dev, ctx, stream, w, psd, xf, K_exact, build_s, steps):
     wall, _ = timed(step, max(2, steps // 2), 1, stream)
     ms = wall / max(2, steps // 2)
     sum_exact = int(sum(K_exact.info()["len"]))
+    sum_final = int(sum(KN.info()["len"]))
     res.update(
         network=dict(build_with_check_s=t_net, fallback=int(sum(fb)), fallback_frac=sum(fb) / len(nbrs),
                      check_err_median=float(np.median(cerr)), check_err_max=float(np.max(cerr)),
@@ -541,7 +586,9 @@ def _learned(dev, ctx, stream, w, psd, xf, K_exact, build_s, steps):
                            svd_coefficients=16 * 64 * len(nbrs), basis_fp64=16 * 64 * window,
                            network_params=4 * rf.N_MLP_PARAMS,
                            bank_exact_fp32_est=4 * npair * sum_exact // len(nbrs)),
-        learned_split16_step_ms=ms, learned_split16_value=(1 + len(nbrs)) * n / (ms * 1e-3))
+        learned_split16_step_ms=ms, learned_split16_value=(1 + len(nbrs)) * n / (ms * 1e-3),
+        # 4 flops per kept tap and sample over the whole step (reference MF included): a lower bound
+        learned_split16_roofline_frac=4.0 * n * sum_final / (ms * 1e-3) / 1e12 / PEAK_FP16_TFLOPS)
     KN.free()
     KP.free()
     S.free()
@@ -713,6 +760,12 @@ def main():
         dms = res["direct"]["wall_ms"] / max(2, args.steps // 2)
         extra["direct_fft_mf_ms"] = dms
         extra["direct_fft_mf_value"] = samples / (dms * 1e-3)
+        # HBM roofline on the algorithmic 12 B per template-sample (half the spectrum read as 8 B
+        # complex values, the 8 B series written); the peak read-out's pass is not counted
+        extra["direct_fft_mf_roofline"] = {"bound": "hbm", "bytes_per_template_sample": 12,
+                                           "achieved": 12 * samples / (dms * 1e-3) / 1e9,
+                                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                           "frac": 12 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS}
         extra["err_vs_direct_mf"] = res["err_vs_direct"]
     if "factored" in res:
         extra["factored"] = res["factored"]
