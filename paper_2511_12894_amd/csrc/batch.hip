@@ -38,7 +38,7 @@ struct rf_batch {
   std::vector<rf::WorkItem> hitems;
   int64_t max_ksteps = 0;
   // per-call buffers
-  float2* Y = nullptr;                 // [nseg][nref][n]
+  float2* q = nullptr;                 // [nseg][band bins]: conditioned data
   float2* zref = nullptr;              // [nseg][nref][n]
   float2* fa = nullptr;                // FFT scratch owned by the batch
   float2* fb = nullptr;
@@ -68,7 +68,7 @@ void free_batch(rf_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   for (void* p : {(void*)b->coef, (void*)b->moment, (void*)b->tiles, (void*)b->items, (void*)b->b16,
-                  (void*)b->colscale, (void*)b->slot_kernel, (void*)b->Y, (void*)b->zref, (void*)b->zs,
+                  (void*)b->colscale, (void*)b->slot_kernel, (void*)b->q, (void*)b->zref, (void*)b->zs,
                   (void*)b->maxbits, (void*)b->zinv, (void*)b->packed, (void*)b->counter,
                   (void*)b->fa, (void*)b->fb})
     if (p) (void)hipFree(p);
@@ -86,9 +86,9 @@ void upload_items(rf_batch* b) {
 
 // reference series of every (segment, reference) and their FP16 split
 void enqueue_reference(rf_ctx* ctx, rf_batch* b, const void* xf) {
-  mf_spectrum(ctx, &b->grid, static_cast<const double2*>(xf), b->psd, b->coef, b->moment, b->Y,
-              b->nref, b->nseg);
-  fft_inverse_f32(ctx, b->Y, b->zref, b->n, b->nseg * b->nref, b->fa, b->fb);
+  condition_data(ctx, &b->grid, static_cast<const double2*>(xf), b->psd, b->q, b->nseg);
+  fft_inverse_tmpl_f32(ctx, &b->grid, b->q, b->coef, b->nref, b->moment, b->zref, b->nseg * b->nref, b->fa,
+                       b->fb);
   split_launch(ctx, b->zref, b->n, b->maxbits, b->zs, b->zinv, b->nseg * b->nref);
 }
 
@@ -222,7 +222,9 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     b->moment = dev_alloc<double>(1, "batch: device allocation failed");
     band_moment(ctx, grid, psd, b->moment);
     const size_t ns = size_t(nseg) * nref;
-    b->Y = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
+    int64_t jlo, jhi;
+    band_limits(grid, &jlo, &jhi);
+    b->q = dev_alloc<float2>(size_t(nseg) * size_t(jhi - jlo + 1), "batch: device allocation failed");
     b->zref = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
     b->zs = dev_alloc<__half>(ns * 4 * size_t(b->n), "batch: device allocation failed");
     b->maxbits = dev_alloc<uint32_t>(ns, "batch: device allocation failed");

@@ -9,7 +9,10 @@
 // A workgroup owns 16 consecutive columns, so each global read and write is a
 // run of 16 consecutive complex values; the P-point DFT of a column runs in
 // LDS as a short in-workgroup Stockham sequence of radix-8/4/2 register
-// butterflies.  Twiddles come from sincospi of exact dyadic arguments.
+// butterflies.  Twiddles come from sincospi of exact dyadic arguments.  A
+// first pass may form its input on the fly instead of reading it: the
+// band-limited products of the factored reconstruction, or a matched filter's
+// weighted template spectrum (FP64 phase), so neither is ever stored.
 #include <type_traits>
 
 #include "rf_internal.h"
@@ -137,10 +140,24 @@ struct BandIn {
   float inv_n;
 };
 
-template <typename T, int P, bool BAND>
+// Input of a first pass formed from a template's phase series: transform y
+// reads sqrt(4 df / I) f^(-7/6) q[y / nt][f - jlo] exp(+i Psi_{y % nt}(f)) on the
+// band bins f in [jlo, jhi] (FP64 phase and weighting), zero elsewhere.
+struct TmplIn {
+  const float2* q;
+  const Tf2Coef* coef;
+  const double* moment;
+  int64_t jlo, jhi;
+  double df;
+  int nt;
+};
+
+enum PassInput { kPlain = 0, kBand = 1, kTmpl = 2 };
+
+template <typename T, int P, int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* __restrict__ in,
                                                        typename C2<T>::t* __restrict__ out,
-                                                       int64_t n, int64_t ns, BandIn bin) {
+                                                       int64_t n, int64_t ns, BandIn bin, TmplIn tin) {
   using V = typename C2<T>::t;
   __shared__ V s[kCols][P + 1];
   __shared__ V tw[P];
@@ -154,13 +171,40 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
     sc_pi(T(2 * m) / T(P), &sn, &cs);
     tw[m] = V{cs, sn};
   }
+  Tf2Coef tc{};
+  double tg = 0.0;
+  if constexpr (MODE == kTmpl) {
+    tc = tin.coef[blockIdx.y % tin.nt];
+    tg = sqrt(4.0 * tin.df / *tin.moment);
+  }
   // load 16 columns, apply the inter-pass twiddle exp(+2 pi i r k / (ns P))
   const int64_t L = ns * P;
   for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
     const int c = e % kCols, r = e / kCols;
     const int64_t j = j0 + c;
     V v;
-    if constexpr (BAND) {
+    if constexpr (MODE == kTmpl) {
+      const int64_t fj = j + int64_t(r) * ncols;
+      v = V{0, 0};
+      if (fj >= tin.jlo && fj <= tin.jhi) {
+        const double f = double(fj) * tin.df;
+        // f^(1/3): the FP32 root refined by one Newton step (about 46 bits)
+        double cf = double(cbrtf(float(f)));
+        const float cf32 = float(cf);
+        cf -= double(float(cf * cf * cf - f) / (3.0f * cf32 * cf32));
+        // the phase in FP64 (it reaches ~1e5 rad), reduced to [-pi, pi] in FP64; the
+        // exponential of the reduced angle and the amplitude need only FP32
+        const double psi = tf2_phase(tc, tc.cbrt_piM * cf);
+        const double k = rint(psi * 0.15915494309189533577);
+        const float ang = float(fma(-k, 6.28318530717958647693, psi));
+        float sn, cs;
+        sincosf(ang, &sn, &cs);
+        // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
+        const float a = float(tg) / (float(f) * sqrtf(float(cf)));
+        const float2 q = tin.q[int64_t(blockIdx.y / tin.nt) * (tin.jhi - tin.jlo + 1) + (fj - tin.jlo)];
+        v = V{a * (q.x * cs - q.y * sn), a * (q.x * sn + q.y * cs)};
+      }
+    } else if constexpr (MODE == kBand) {
       const int64_t i = j + int64_t(r) * ncols - bin.b0;
       v = V{0, 0};
       if (i >= 0 && i < bin.nb) {
@@ -207,15 +251,16 @@ std::vector<int> plan_passes(int lg) {
   return bits;
 }
 
-template <typename T, bool BAND = false>
+template <typename T, int MODE = kPlain>
 void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}) {
+                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}, TmplIn tin = TmplIn{}) {
   const int64_t P = int64_t(1) << bits;
   dim3 grid(unsigned((n / P) / kCols), unsigned(batch));
   switch (bits) {
-#define RF_FFT_CASE(B)                                                                                    \
-  case B:                                                                                                 \
-    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), BAND>), grid, dim3(kThreads), 0, st, in, out, n, ns, bin); \
+#define RF_FFT_CASE(B)                                                                            \
+  case B:                                                                                         \
+    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), MODE>), grid, dim3(kThreads), 0, st, in, out, n, ns, \
+                       bin, tin);                                                                 \
     break;
     RF_FFT_CASE(4)
     RF_FFT_CASE(5)
@@ -231,7 +276,8 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
 
 template <typename T>
 void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in, const BandIn* band = nullptr) {
+                 int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in, const BandIn* band = nullptr,
+                 const TmplIn* tmpl = nullptr) {
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
@@ -251,8 +297,11 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   for (int i = 0; i < s; ++i) {
     V* dst = (i == s - 1) ? out : ((i % 2 == 0) ? wa : wb);
     if constexpr (std::is_same<T, float>::value) {
-      if (i == 0 && band) {
-        launch_pass<T, true>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
+      if (i == 0 && (band || tmpl)) {
+        if (band)
+          launch_pass<T, kBand>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
+        else
+          launch_pass<T, kTmpl>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, BandIn{}, *tmpl);
         ns <<= bits[i];
         src = dst;
         continue;
@@ -272,6 +321,19 @@ void fft_inverse_f32(rf_ctx* ctx, const float2* in, float2* out, int64_t n, int 
 }
 void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, int batch) {
   fft_inverse<double>(ctx, in, out, n, batch, nullptr, nullptr);
+}
+void fft_inverse_tmpl_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
+                          const double* moment, float2* out, int batch, float2* wsa, float2* wsb) {
+  RF_CHECK(nt >= 1 && batch % nt == 0, "fft: batch must be a multiple of the template count");
+  TmplIn t{};
+  t.q = q;
+  t.coef = coef;
+  t.moment = moment;
+  band_limits(g, &t.jlo, &t.jhi);
+  t.df = g->fs / double(g->n);
+  t.nt = nt;
+  RF_CHECK(t.jlo >= 1 && t.jhi < g->n, "fft: band outside the transform");
+  fft_inverse<float>(ctx, nullptr, out, g->n, batch, wsa, wsb, nullptr, &t);
 }
 void fft_inverse_band_f32(rf_ctx* ctx, const float2* Q, const float2* Ub, int64_t b0, int64_t nb, float inv_n,
                           float2* out, int64_t n, int batch) {

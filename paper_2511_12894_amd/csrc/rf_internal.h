@@ -117,6 +117,18 @@ struct Tf2Coef {
   double cbrt_piM; // (pi M)^(1/3)
 };
 Tf2Coef tf2_coef(const rf_tmpl& t);
+
+// Psi at v = (pi M f)^(1/3), FP64 (the phase reaches ~1e5 rad in band).
+__device__ inline double tf2_phase(const Tf2Coef& c, double v) {
+  const double lv = log(v);
+  const double v2 = v * v;
+  const double iv = 1.0 / v;
+  const double iv5 = iv * iv * iv * iv * iv;
+  const double poly =
+      1.0 + v2 * (c.a2 + v * (c.a3 + v * (c.a4 + v * ((c.a5c + c.a5l * lv) +
+                                                       v * ((c.a6c + c.a6l * lv) + v * c.a7)))));
+  return -0.25 * 3.14159265358979323846 + c.pref * poly * iv5;
+}
 double tf2_dtdf(const Tf2Coef& c, double f);   // t'(f) = Psi''(f) / (2 pi)
 double tf2_t(const Tf2Coef& c, double f);      // t(f)  = Psi'(f) / (2 pi)
 
@@ -134,15 +146,24 @@ void fft_inverse_f64(rf_ctx* ctx, const double2* in, double2* out, int64_t n, in
 void fft_inverse_band_f32(rf_ctx* ctx, const float2* Q, const float2* Ub, int64_t b0, int64_t nb, float inv_n,
                           float2* out, int64_t n, int batch);
 
+// Matched-filter series of `batch` templates, the first pass forming its input on
+// the fly (the template spectrum is never stored): input y is
+// sqrt(4 df / I) f^(-7/6) q[y / nt][f - jlo] exp(+i Psi_t(f)) on the band bins
+// f in [jlo, jhi] and zero elsewhere, with t = y % nt, coef[t] its phase series
+// and I = *moment; q: [batch / nt][jhi - jlo + 1] (condition_data).
+void fft_inverse_tmpl_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
+                          const double* moment, float2* out, int batch, float2* wsa = nullptr,
+                          float2* wsb = nullptr);
+// Conditioned data q[seg][j - jlo] = x~_j / S_j on the band bins (FP64
+// arithmetic, complex64 store) for nseg segments (xf: [nseg][n/2+1]).
+void condition_data(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd, float2* q,
+                    int nseg = 1);
+
 // sum over the band of f^(-7/3) / S(f) -> *moment (device double), FP64, fixed order
 void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* moment);
 // band bins j with f_low <= j fs / n <= f_high: [jlo, jhi]
 void band_limits(const rf_grid* g, int64_t* jlo, int64_t* jhi);
 
-// Y[t][j] for the nt templates (FP64 arithmetic, complex64 store), using *moment
-// Y[seg][t][j] for nseg data segments (xf: [nseg][n/2+1]) and nt templates.
-void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
-                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt, int nseg = 1);
 
 // One-sided ratio spectra for nb-point kernels, nk targets (FP64), scaled by c_j / nb.
 struct RatioParam {

@@ -1,7 +1,8 @@
-// FP64 frequency-domain work: TaylorF2 template spectra fused with the
-// matched-filter weighting (section II.A), band moment for the template norms,
-// windowed ratio spectra (sections II.B-II.C), and the kernel support scan and
-// tap gather of the truncation (section II.D).
+// FP64 frequency-domain work: the TaylorF2 phase coefficients (the template
+// spectra themselves are formed inside the first transform pass of the matched
+// filter), data conditioning x~ / S and the band moment for the template norms
+// (section II.A), windowed ratio spectra (sections II.B-II.C), and the kernel
+// support scan and tap gather of the truncation (section II.D).
 #include <algorithm>
 #include <cmath>
 
@@ -80,16 +81,6 @@ double tf2_dtdf(const Tf2Coef& c, double f) {
 
 namespace {
 
-__device__ inline double tf2_phase(const Tf2Coef& c, double v) {
-  const double lv = log(v);
-  const double v2 = v * v;
-  const double iv = 1.0 / v;
-  const double iv5 = iv * iv * iv * iv * iv;
-  const double poly =
-      1.0 + v2 * (c.a2 + v * (c.a3 + v * (c.a4 + v * ((c.a5c + c.a5l * lv) +
-                                                       v * ((c.a6c + c.a6l * lv) + v * c.a7)))));
-  return -0.25 * 3.14159265358979323846 + c.pref * poly * iv5;
-}
 
 constexpr int kRedThreads = 256;
 constexpr int kRedBlocks = 1024;
@@ -130,36 +121,18 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_partials(const double* __re
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-// Y[t][j] = (4 df / N_t) x~_j conj(h~_t(f_j)) / S_j on the band, 0 elsewhere,
-// with N_t = amp_t sqrt(4 df I) and h~ = amp f^(-7/6) exp(-i Psi).
-__global__ __launch_bounds__(256) void k_mf_spectrum(const double2* __restrict__ xf,
-                                                     const double* __restrict__ psd,
-                                                     const Tf2Coef* __restrict__ coef,
-                                                     const double* __restrict__ moment, float2* Y,
-                                                     int64_t n, int64_t jlo, int64_t jhi, double df) {
-  // blockIdx.y: template, blockIdx.z: data segment (spectra of n/2+1 bins each)
-  const Tf2Coef c = coef[blockIdx.y];
-  float2* y = Y + (int64_t(blockIdx.z) * gridDim.y + blockIdx.y) * n;
-  xf += int64_t(blockIdx.z) * (n / 2 + 1);
-  const double nh = c.amp * sqrt(4.0 * df * (*moment));
-  const double g = 4.0 * df / nh * c.amp;
-  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
-       j += int64_t(gridDim.x) * blockDim.x) {
-    float2 out = make_float2(0.f, 0.f);
-    if (j >= jlo && j <= jhi) {
-      const double f = double(j) * df;
-      const double v = c.cbrt_piM * cbrt(f);
-      const double psi = tf2_phase(c, v);
-      double sn, cs;
-      sincos(psi, &sn, &cs);
-      // f^(-7/6) = 1 / (f * sqrt(cbrt(f)))
-      const double a = g / (f * sqrt(v / c.cbrt_piM) * psd[j]);
-      const double2 x = xf[j];
-      // x * conj(h) = x * amp f^-7/6 * exp(+i psi)
-      out.x = float(a * (x.x * cs - x.y * sn));
-      out.y = float(a * (x.x * sn + x.y * cs));
-    }
-    y[j] = out;
+// q[seg][j - jlo] = x~_j / S_j on the band bins (the data conditioning of
+// section II.A, shared by every template filtered against the segment).
+__global__ __launch_bounds__(256) void k_condition(const double2* __restrict__ xf,
+                                                   const double* __restrict__ psd, float2* q,
+                                                   int64_t n, int64_t jlo, int64_t nb) {
+  xf += int64_t(blockIdx.y) * (n / 2 + 1);
+  q += int64_t(blockIdx.y) * nb;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nb;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 x = xf[jlo + i];
+    const double s = 1.0 / psd[jlo + i];
+    q[i] = make_float2(float(x.x * s), float(x.y * s));
   }
 }
 
@@ -299,15 +272,13 @@ void band_moment(rf_ctx* ctx, const rf_grid* g, const double* psd, double* momen
   RF_HIP(hipGetLastError());
 }
 
-void mf_spectrum(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd,
-                 const Tf2Coef* coef_dev, const double* moment, float2* Y, int nt, int nseg) {
+void condition_data(rf_ctx* ctx, const rf_grid* g, const double2* xf, const double* psd, float2* q,
+                    int nseg) {
   int64_t jlo, jhi;
   band_limits(g, &jlo, &jhi);
-  const double df = g->fs / double(g->n);
-  dim3 grid(blocks_for(g->n, 256, unsigned(std::max(64, 4096 / (nt * nseg)))), unsigned(nt),
-            unsigned(nseg));
-  hipLaunchKernelGGL(k_mf_spectrum, grid, dim3(256), 0, ctx->stream, xf, psd, coef_dev, moment, Y,
-                     g->n, jlo, jhi, df);
+  const int64_t nb = jhi - jlo + 1;
+  dim3 grid(blocks_for(nb, 256, unsigned(std::max(64, 2048 / nseg))), unsigned(nseg));
+  hipLaunchKernelGGL(k_condition, grid, dim3(256), 0, ctx->stream, xf, psd, q, g->n, jlo, nb);
   RF_HIP(hipGetLastError());
 }
 
