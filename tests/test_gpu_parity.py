@@ -218,6 +218,28 @@ def test_snr_peaks_matches_oracle(rf, ctx):
     assert abs(v[3] - pv) <= 1e-6 * pv
 
 
+@pytest.mark.parametrize("n, offset", [(4097, 0), (4096, 1)])
+def test_snr_peaks_unaligned_series(rf, ctx, n, offset):
+    """Series whose rows are not 16-byte aligned (odd length, or a base pointer
+    one element in) take the one-sample-per-load path: same decisions as the
+    oracle's."""
+    nt = 3
+    z = _planted_series(nt, n, 13)
+    flat = torch.zeros(nt * n + offset, dtype=torch.complex64, device="cuda")
+    flat[offset:] = torch.from_numpy(z.reshape(-1)).cuda()
+    zt = flat[offset:].view(nt, n)
+    assert (zt.data_ptr() % 16 != 0) or (n % 2 == 1)
+    out = rf.snr_peaks(ctx, zt, 4.0, trig_cap=1 << 14)
+    v, idx = rf.decode_peaks(out["peaks"])
+    a2, oidx = _oracle_peaks_f32(z)
+    np.testing.assert_array_equal(idx, oidx)
+    np.testing.assert_allclose(v, np.sqrt(a2[np.arange(nt), oidx]), rtol=2e-7)
+    thr2 = np.float32(4.0) * np.float32(4.0)
+    expect = sorted((k, int(m)) for k in range(nt) for m in np.nonzero(a2[k] > thr2)[0])
+    got = sorted((t[0], t[2]) for t in rf.decode_triggers(out["trig"], out["ntrig"]))
+    assert got == expect
+
+
 def test_trigger_overflow_reports_true_count(rf, ctx):
     z = _planted_series(3, 4096, 9)
     out = rf.snr_peaks(ctx, torch.from_numpy(z).cuda(), 2.0, trig_cap=5)
