@@ -211,13 +211,13 @@ rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const dou
     Tf2Coef* coef_dev = upload(ctx, WS_COEF, coef.data(), coef.size());
     double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
     band_moment(ctx, grid, psd, moment);
-    // conditioned data once, then the templates in batches (FFT scratch near 512 MiB); each
+    // conditioned data once, then the templates in batches (FFT scratch up to 2 GiB); each
     // template's spectrum is formed inside the first transform pass and never stored
     int64_t jlo, jhi;
     band_limits(grid, &jlo, &jhi);
     float2* q = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(jhi - jlo + 1)));
     condition_data(ctx, grid, static_cast<const double2*>(xf), psd, q);
-    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 26) / n)));
+    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
     float2* zo = static_cast<float2*>(z);
     for (int t0 = 0; t0 < nt; t0 += per) {
       const int cnt = std::min(per, nt - t0);
