@@ -101,7 +101,9 @@ const char* rf_last_error(const rf_ctx* ctx);
  *   tmpl  host [nt] templates; nt >= 1
  *   z     device complex64 [nt][n] (written)
  *   sigma host double [nt] or NULL: N_h of each template (then the call syncs)
- * FP64 template phase and spectrum, FP32 FFT. */
+ * FP64 template phase (reduced to [-pi, pi] in FP64), FP32 exponential,
+ * amplitude and FFT; each template's spectrum is formed inside the first
+ * transform pass and never stored. */
 rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
                      const rf_tmpl* tmpl, int32_t nt, void* z, double* sigma);
 
