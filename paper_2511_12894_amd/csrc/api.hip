@@ -69,7 +69,7 @@ double pow2_scale_for(double maxabs) {
 void free_kernels(rf_kernels* k) {
   if (!k) return;
   for (void* p : {(void*)k->taps64, (void*)k->tiles_dev, (void*)k->b32, (void*)k->b16,
-                  (void*)k->colscale32, (void*)k->colscale16, (void*)k->slot_kernel})
+                  (void*)k->colscale32, (void*)k->colscale16, (void*)k->slot_kernel, (void*)k->gflag})
     if (p) (void)hipFree(p);
   delete k;
 }
@@ -100,7 +100,7 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
   const int ntiles = (nk + kTileKernels - 1) / kTileKernels;
   std::vector<int32_t> slot(size_t(ntiles) * kTileKernels, -1);
   std::vector<float> cs32(slot.size(), 0.f), cs16(slot.size(), 0.f);
-  int64_t b32_total = 0, b16_total = 0;
+  int64_t b32_total = 0, b16_total = 0, gflag_total = 0;
   K->tiles.clear();
   K->max_ksteps = 0;
   for (int t = 0; t < ntiles; ++t) {
@@ -127,8 +127,10 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
     }
     T.b32_off = b32_total;
     T.b16_off = b16_total;
+    T.gflag_off = gflag_total;
     b32_total += T.ksteps * kB32PerStep;
     b16_total += T.ksteps * kB16PerStep;
+    gflag_total += (T.ksteps + 15) / 16;
     K->max_ksteps = std::max(K->max_ksteps, T.ksteps);
     K->tiles.push_back(T);
   }
@@ -140,6 +142,9 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
   K->b16 = dev_alloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep));
   fill_u32(ctx, reinterpret_cast<uint32_t*>(K->b32 + b32_total), 0u, int64_t(kOperandPadSteps) * kB32PerStep);
   fill_u32(ctx, reinterpret_cast<uint32_t*>(K->b16 + b16_total), 0u, int64_t(kOperandPadSteps) * kB16PerStep / 2);
+  K->gflag_total = gflag_total;
+  K->gflag = dev_alloc<uint32_t>(size_t(std::max<int64_t>(gflag_total, 1)));
+  fill_u32(ctx, K->gflag, 0u, std::max<int64_t>(gflag_total, 1));
   RF_HIP(hipMemcpy(K->tiles_dev, K->tiles.data(), sizeof(TileDev) * K->tiles.size(), hipMemcpyHostToDevice));
   RF_HIP(hipMemcpy(K->slot_kernel, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
   RF_HIP(hipMemcpy(K->colscale32, cs32.data(), sizeof(float) * cs32.size(), hipMemcpyHostToDevice));
@@ -376,6 +381,32 @@ rf_status rf_kernels_info(const rf_kernels* k, int32_t* nk, int64_t* m_lo, int32
     if (norm_ratio) norm_ratio[i] = k->norm_ratio[i];
     if (df_low) df_low[i] = k->df_low[i];
   }
+  return RF_OK;
+}
+
+rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* corr_steps, int64_t* all_steps) {
+  if (!k || chunk < 256 || chunk > 1024 || chunk % 256 != 0) return RF_E_INVAL;
+  if (hipSetDevice(k->device) != hipSuccess) return RF_E_HIP;
+  std::vector<uint32_t> flags(size_t(std::max<int64_t>(k->gflag_total, 1)), 0u);
+  if (k->gflag_total > 0 && hipMemcpy(flags.data(), k->gflag, sizeof(uint32_t) * size_t(k->gflag_total),
+                                      hipMemcpyDeviceToHost) != hipSuccess)
+    return RF_E_HIP;
+  int64_t corr = 0, all = 0;
+  for (const rf::TileDev& T : k->tiles) {
+    const int64_t ntaps = T.ksteps * 16;
+    for (int64_t t0 = 0; t0 < ntaps; t0 += chunk) {
+      const int64_t ch = std::min<int64_t>(chunk, ntaps - t0);
+      // the 1024-tap blocks the chunk lies in decide, as in the kernels
+      const int64_t a = t0 / 1024 * 1024;
+      const int64_t b = std::min<int64_t>((t0 + chunk + 1023) / 1024 * 1024, ntaps);
+      uint32_t need = 0;
+      for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= flags[size_t(T.gflag_off + g)];
+      all += ch / 16;
+      if (need) corr += ch / 16;
+    }
+  }
+  if (corr_steps) *corr_steps = corr;
+  if (all_steps) *all_steps = all;
   return RF_OK;
 }
 

@@ -43,6 +43,7 @@ struct rf_batch {
   float2* fa = nullptr;                // FFT scratch owned by the batch
   float2* fb = nullptr;
   __half* zs = nullptr;                // [nseg][nref][4][n]
+  uint32_t* gflag = nullptr;           // granule flags of every set's tiles
   uint32_t* maxbits = nullptr;         // [nseg * nref]
   float* zinv = nullptr;               // [nseg * nref]
   uint64_t* packed = nullptr;          // [nseg * ktotal] + trigger count
@@ -69,7 +70,7 @@ void free_batch(rf_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   for (void* p : {(void*)b->coef, (void*)b->moment, (void*)b->tiles, (void*)b->items, (void*)b->b16,
                   (void*)b->colscale, (void*)b->slot_kernel, (void*)b->q, (void*)b->zref, (void*)b->zs,
-                  (void*)b->maxbits, (void*)b->zinv, (void*)b->packed, (void*)b->counter,
+                  (void*)b->maxbits, (void*)b->zinv, (void*)b->packed, (void*)b->counter, (void*)b->gflag,
                   (void*)b->fa, (void*)b->fb})
     if (p) (void)hipFree(p);
   delete b;
@@ -106,7 +107,7 @@ void enqueue_run(rf_ctx* ctx, rf_batch* b, const void* xf, float thr, rf_peak* p
   po.seg = 0;
   po.nk = b->ktotal;
   queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, b->items, int(b->hitems.size()),
-               b->counter, b->b16, b->colscale, b->slot_kernel, b->zinv, po);
+               b->counter, b->b16, b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
   peaks_finalize(ctx, b->packed, np, peaks);
 }
 
@@ -152,7 +153,7 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     b->n = grid->n;
     b->psd = psd;
     std::vector<Tf2Coef> coef(nref);
-    int64_t b16_total = 0, slot_total = 0;
+    int64_t b16_total = 0, slot_total = 0, gflag_total = 0;
     for (int r = 0; r < nref; ++r) {
       RF_CHECK(refs[r].m1 > 0 && refs[r].m2 > 0, "rf_batch_create: template masses must be positive");
       coef[r] = tf2_coef(refs[r]);
@@ -164,13 +165,15 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
         b16_total += T.ksteps * kB16PerStep;
       }
       slot_total += int64_t(K->tiles.size()) * kTileKernels;
+      gflag_total += K->gflag_total;
     }
     // global slot arrays and tiles: group r's kernels get global indices kbase[r] + k
     b->b16 = dev_alloc<__half>(size_t(b16_total + int64_t(kOperandPadSteps) * kB16PerStep), "batch: device allocation failed");
     fill_u32(ctx, reinterpret_cast<uint32_t*>(b->b16 + b16_total), 0u, int64_t(kOperandPadSteps) * kB16PerStep / 2);
     b->colscale = dev_alloc<float>(size_t(slot_total), "batch: device allocation failed");
     b->slot_kernel = dev_alloc<int32_t>(size_t(slot_total), "batch: device allocation failed");
-    int64_t b16_off = 0, slot_off = 0;
+    b->gflag = dev_alloc<uint32_t>(size_t(std::max<int64_t>(gflag_total, 1)), "batch: device allocation failed");
+    int64_t b16_off = 0, slot_off = 0, gflag_off = 0;
     int32_t kb = 0;
     std::vector<int32_t> host_slots;
     for (int r = 0; r < nref; ++r) {
@@ -187,16 +190,21 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
       for (const TileDev& T : K->tiles) own = std::max(own, T.b16_off + T.ksteps * kB16PerStep);
       if (own > 0)
         RF_HIP(hipMemcpy(b->b16 + b16_off, K->b16, sizeof(__half) * own, hipMemcpyDeviceToDevice));
+      if (K->gflag_total > 0)
+        RF_HIP(hipMemcpy(b->gflag + gflag_off, K->gflag, sizeof(uint32_t) * K->gflag_total,
+                         hipMemcpyDeviceToDevice));
       for (const TileDev& T : K->tiles) {
         BatchTile bt{};
         bt.t = T;
         bt.t.b16_off += b16_off;
+        bt.t.gflag_off += gflag_off;
         bt.t.first += int32_t(slot_off);
         bt.ref = r;
         b->htiles.push_back(bt);
         b->max_ksteps = std::max(b->max_ksteps, T.ksteps);
       }
       b16_off += own;
+      gflag_off += K->gflag_total;
       slot_off += nslots;
       kb += K->nk;
     }
@@ -328,7 +336,7 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
           fill_u64(ctx, b->packed, 0ull, np + 1);
           RF_HIP(hipEventRecord(e0, ctx->stream));
           queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, scratch, int(sub.size()),
-                       b->counter, b->b16, b->colscale, b->slot_kernel, b->zinv, po);
+                       b->counter, b->b16, b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
           RF_HIP(hipEventRecord(e1, ctx->stream));
           RF_HIP(hipEventSynchronize(e1));
           RF_HIP(hipEventElapsedTime(&ms, e0, e1));

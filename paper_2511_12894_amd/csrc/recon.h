@@ -69,8 +69,8 @@ void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __
 int queue_blocks(int device);
 void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
                   const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
-                  const __half* b16, const float* colscale, const int32_t* slot_kernel,
-                  const float* zinv_all, const PeakOut& po);
+                  const __half* b16, const uint32_t* gflag, const float* colscale,
+                  const int32_t* slot_kernel, const float* zinv_all, const PeakOut& po);
 void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const int64_t* mlo_dev,
                  const int32_t* len_dev, const double* kscale_dev, const TileDev* tiles_dev,
                  int ntiles, int64_t max_ksteps);

@@ -280,7 +280,8 @@ __device__ inline half8 lds_frag(const _Float16* p) {
 template <bool STORE, bool FUSED>
 __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
                                       int64_t n, const TileDev& T, int64_t n0, int chunk,
-                                      const __half* b16, const float* __restrict__ colscale,
+                                      const __half* b16, const uint32_t* __restrict__ gflag,
+                                      const float* __restrict__ colscale,
                                       const int32_t* __restrict__ slot_kernel, float zinv,
                                       float2* __restrict__ zout, const PeakOut& po) {
   const int win_len = chunk + kTimes + 32;
@@ -321,10 +322,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // 4k + sg .. 4k + sg + 3, 16 contiguous halves (32 bytes) in the interleaved
   // layout, so block k needs samples 4k .. 4k + 6, two aligned 4-sample loads
   // per plane.  Thread t handles block t and, for chunks above 736 taps, block
-  // t + 256.  The next chunk's window goes into the idle buffer in two rounds
-  // early in the chunk, each loaded into the same staging registers several
-  // steps before it is stored, so no refill load is waited for at the chunk
-  // boundary.
+  // t + 256, both through the same staging registers (two rounds per chunk).
   const int nblk = win_len / 4;
   uint2 stage[4][2];
   auto load_blk = [&](int64_t t0, int k, uint2 (&v)[4][2]) {
@@ -356,112 +354,151 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   auto put = [&](int buf, int k) {
     if (k < nblk) store_blk(buf, k, stage);
   };
-  if (nch > 0) {
-    gather(0, threadIdx.x);
-    put(0, threadIdx.x);
-    gather(0, threadIdx.x + 256);
-    put(0, threadIdx.x + 256);
-  }
-  __syncthreads();
   // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
   // multiple of 4; in the interleaved layout 4 positions are 16 halves)
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
-  // B ring (slot = step % 8, six steps ahead); it runs on across chunks
-  half8 bh[8], bl[8];
-  auto loadB = [&](int64_t st, half8& h, half8& l) {   // st <= ksteps + 5: inside the padding
-    h = B[st * 128];
-    l = B[st * 128 + 64];
+  // Chunk c takes the correction products if its tile has a flagged granule
+  // (a scaled tap of at least 1/2) in the 1024-tap blocks (from the tile's first
+  // tap) that the chunk lies in: the same steps get them whatever the chunk
+  // size (256, 512 or 1024), so every chunk size gives the same sums.
+  auto flagged = [&](int c) {
+    const int64_t a = (int64_t(c) * chunk / 1024) * 1024;
+    const int64_t e = (int64_t(c + 1) * chunk + 1023) / 1024 * 1024;
+    const int64_t b = e < ntaps ? e : ntaps;
+    uint32_t need = 0;
+    for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= gflag[T.gflag_off + g];
+    return __builtin_amdgcn_readfirstlane(int(need)) != 0;
   };
-#pragma unroll
-  for (int j = 0; j < 6; ++j) loadB(j, bh[j], bl[j]);
-  for (int c = 0; c < nch; ++c) {
-    const int64_t t0 = int64_t(c) * chunk;
-    const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
-    const int buf = c & 1;
-    const bool more = c + 1 < nch;
-    if (more) gather(t0 + chunk, threadIdx.x);
-    const _Float16* wb[4];
-#pragma unroll
-    for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
-    const int64_t s0 = t0 / 16;
-    const int nst = ch / 16;                // multiple of 8 (tiles span 128-tap multiples)
-    half8 f[8][4];                          // F ring [slot][plane], slot = step % 8
-    auto loadF = [&](int j, half8 (&ff)[4]) {
-#pragma unroll
-      for (int pl = 0; pl < 4; ++pl) ff[pl] = lds_frag(wb[pl] + 64 * j);
+  // B ring (slot = step % 8, six steps ahead); it runs on across consecutive chunks
+  half8 bh[8], bl[8];
+  // Two passes over the item's window chunks.  Pass 1 (CORR false): the
+  // hi*hi product of every chunk into `acc`, folded into the FP64 total every
+  // 32 steps; it reads the hi planes and the hi operand only.  Pass 2 (CORR
+  // true): the two correction products of the flagged chunks into `cor`.
+  // Each pass restarts the window and the rings; nothing but the FP64 total
+  // and `cor` lives across them.
+  auto pass = [&](auto corr_tag) {
+    constexpr bool CORR = decltype(corr_tag)::value;
+    auto next_chunk = [&](int c) {
+      ++c;
+      if constexpr (CORR)
+        while (c < nch && !flagged(c)) ++c;
+      return c;
     };
-    // step s: time block 0 uses F(s), time block 1 uses F(s + 2); the three
-    // split products, consecutive MFMAs feeding independent accumulators
-    auto mma = [&](const half8 (&f0)[4], const half8 (&f1)[4], const half8& h, const half8& l) {
-#pragma unroll
-      for (int part = 0; part < 3; ++part)
-#pragma unroll
-        for (int tb = 0; tb < 2; ++tb)
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
-            const half8 bv = part == 1 ? l : h;
-            if (part == 0)
-              acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
-            else
-              cor[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, cor[tb][ri], 0, 0, 0);
-          }
+    auto loadB = [&](int64_t st, half8& h, half8& l) {   // st <= ksteps + 5: inside the padding
+      if (CORR) l = B[st * 128 + 64];
+      h = B[st * 128];
     };
-#pragma unroll
-    for (int j = 0; j < 4; ++j) loadF(j, f[j]);
-    // F runs four steps ahead, B six (slots step % 8); the LDS counter holds
-    // at most 15 fragment reads in flight, so more would only wait by count
-    auto steps = [&](int q, auto count) {
-#pragma unroll
-      for (int h = 0; h < decltype(count)::value; ++h) {
-        loadF(q + h + 4, f[(h + 4) & 7]);
-        loadB(s0 + q + h + 6, bh[(h + 6) & 7], bl[(h + 6) & 7]);
-        mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
-        // one load issued behind each of the step's first six MFMAs (the
-        // four fragment reads, then the two operand loads), then the other
-        // six: every load issues while a matrix instruction runs
-        for (int i = 0; i < 4; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-        }
-        for (int i = 0; i < 2; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    };
-    // acc is folded after every 32 steps and at the chunk's end.  A chunk of
-    // 32 or 64 steps that is followed by another starts with two refill
-    // rounds of 16 steps each in straight-line code, so that each round's
-    // staging registers are waited for only by count, behind the operand
-    // loads issued since.
-    int q = 0;
-    auto refill_rounds = [&](auto P) {
-      constexpr int p = decltype(P)::value;
-      steps(0, P);
-      put(buf ^ 1, threadIdx.x);
-      gather(t0 + chunk, threadIdx.x + 256);
-      steps(p, P);
-      put(buf ^ 1, threadIdx.x + 256);
-      q = 2 * p;
-    };
-    if (more && nst >= 32) {
-      refill_rounds(std::integral_constant<int, 16>{});
-      fold64(acc);
-    }
-    for (; q + 32 <= nst; q += 32) {
-      steps(q, std::integral_constant<int, 32>{});
-      fold64(acc);
-    }
-    if (q < nst) {
-      for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
-      fold64(acc);
-    }
-    if (more && nst < 32) put(buf ^ 1, threadIdx.x);   // 16-step chunks: one round (at most 256 blocks)
+    int c = next_chunk(-1);
+    if (c >= nch) return;
+    gather(int64_t(c) * chunk, threadIdx.x);
+    put(0, threadIdx.x);
+    gather(int64_t(c) * chunk, threadIdx.x + 256);
+    put(0, threadIdx.x + 256);
     __syncthreads();
-  }
+    int buf = 0;
+    int prev = -2;                          // chunk the B ring last ran through
+    while (c < nch) {
+      const int64_t t0 = int64_t(c) * chunk;
+      const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
+      const int cn = next_chunk(c);
+      const bool more = cn < nch;
+      const int64_t tn = int64_t(cn) * chunk;
+      if (more) gather(tn, threadIdx.x);
+      const int64_t s0 = t0 / 16;
+      if (prev != c - 1) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) loadB(s0 + j, bh[j], bl[j]);
+      }
+      const _Float16* wb[4];
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) wb[pl] = &win[buf][pl][win_index(sigma, p0)];
+      const int nst = ch / 16;              // multiple of 8 (tiles span 128-tap multiples)
+      half8 f[8][4];                        // F ring [slot][plane], slot = step % 8
+      auto loadF = [&](int j, half8 (&ff)[4]) {
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          if (CORR || pl % 2 == 0) ff[pl] = lds_frag(wb[pl] + 64 * j);
+      };
+      // step s: time block 0 uses F(s), time block 1 uses F(s + 2); pass 1 the
+      // hi*hi product, pass 2 the hi*lo and lo*hi products, consecutive MFMAs
+      // feeding independent accumulators
+      auto mma = [&](const half8 (&f0)[4], const half8 (&f1)[4], const half8& h, const half8& l) {
+#pragma unroll
+        for (int part = CORR ? 1 : 0; part < (CORR ? 3 : 1); ++part)
+#pragma unroll
+          for (int tb = 0; tb < 2; ++tb)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) {
+              const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
+              const half8 bv = part == 1 ? l : h;
+              if (part == 0)
+                acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[tb][ri], 0, 0, 0);
+              else
+                cor[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, cor[tb][ri], 0, 0, 0);
+            }
+      };
+#pragma unroll
+      for (int j = 0; j < 4; ++j) loadF(j, f[j]);
+      // F runs four steps ahead, B six (slots step % 8); the LDS counter holds
+      // at most 15 fragment reads in flight, so more would only wait by count
+      auto steps = [&](int q, auto count) {
+#pragma unroll
+        for (int h = 0; h < decltype(count)::value; ++h) {
+          loadF(q + h + 4, f[(h + 4) & 7]);
+          loadB(s0 + q + h + 6, bh[(h + 6) & 7], bl[(h + 6) & 7]);
+          mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
+          // the step's loads issued one behind each of its first MFMAs, so that
+          // every load issues while a matrix instruction runs
+          if constexpr (CORR) {
+            for (int i = 0; i < 4; ++i) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            }
+            for (int i = 0; i < 2; ++i) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+          } else {
+            for (int i = 0; i < 2; ++i) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      };
+      // The next visited chunk's window goes to the idle buffer in two rounds:
+      // block t (loaded at this chunk's start) after the first 32 steps, block
+      // t + 256 (loaded then) at the chunk's end.
+      bool round1 = false;
+      int q = 0;
+      for (; q + 32 <= nst; q += 32) {
+        steps(q, std::integral_constant<int, 32>{});
+        if (!CORR) fold64(acc);
+        if (more && !round1) {
+          put(buf ^ 1, threadIdx.x);
+          gather(tn, threadIdx.x + 256);
+          round1 = true;
+        }
+      }
+      if (q < nst) {
+        for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
+        if (!CORR) fold64(acc);
+      }
+      if (more) put(buf ^ 1, threadIdx.x + (round1 ? 256 : 0));
+      __syncthreads();
+      prev = c;
+      c = cn;
+      buf ^= 1;
+    }
+  };
+  pass(std::false_type{});
+  pass(std::true_type{});
   fold64(cor);
   floatx16 totf[2][2];
 #pragma unroll
@@ -477,13 +514,14 @@ template <bool STORE, bool FUSED>
 __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__ zs, int64_t n,
                                                       const TileDev* __restrict__ tiles,
                                                       const __half* b16,
+                                                      const uint32_t* __restrict__ gflag,
                                                       const float* __restrict__ colscale,
                                                       const int32_t* __restrict__ slot_kernel,
                                                       const float* __restrict__ zinv,
                                                       float2* __restrict__ zout, PeakOut po, int chunk) {
   __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWinMax];
   recon_f16_item<STORE, FUSED>(win, zs, n, tiles[blockIdx.y], int64_t(blockIdx.x) * kTimes, chunk, b16,
-                               colscale, slot_kernel, *zinv, zout, po);
+                               gflag, colscale, slot_kernel, *zinv, zout, po);
 }
 
 // Persistent form over a work list: every workgroup takes items
@@ -495,6 +533,7 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
                                                             const WorkItem* __restrict__ items,
                                                             int32_t nitems, uint32_t* counter,
                                                             const __half* b16,
+                                                            const uint32_t* __restrict__ gflag,
                                                             const float* __restrict__ colscale,
                                                             const int32_t* __restrict__ slot_kernel,
                                                             const float* __restrict__ zinv_all,
@@ -513,7 +552,7 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
     PeakOut p = po;
     p.seg = w.seg;
     recon_f16_item<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock) * kTimes, w.chunk,
-                                b16, colscale, slot_kernel, zinv_all[sr], nullptr, p);
+                                b16, gflag, colscale, slot_kernel, zinv_all[sr], nullptr, p);
   }
 }
 
@@ -582,11 +621,12 @@ __global__ void k_pack_b32(const double* __restrict__ taps64, const int64_t* __r
 
 // FP16 operand of a tile: per 16-tap step s, the hi fragment then the lo
 // fragment; lane l holds 8 halves w_{slot l%32}[m0 + 16 s + 8 (l/32) + 0..7]
-// (scaled by the kernel's power-of-two s_k).
+// (scaled by the kernel's power-of-two s_k).  Also marks the tile's 256-tap
+// granules holding a scaled tap of magnitude >= 1/2 (gflag, zeroed before).
 __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __restrict__ off,
                            const int64_t* __restrict__ mlo, const int32_t* __restrict__ len,
                            const double* __restrict__ kscale, const TileDev* __restrict__ tiles,
-                           const int32_t* __restrict__ slot_kernel, __half* b16) {
+                           const int32_t* __restrict__ slot_kernel, __half* b16, uint32_t* gflag) {
   const TileDev T = tiles[blockIdx.y];
   const int64_t total = T.ksteps * kB16PerStep;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
@@ -598,6 +638,8 @@ __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __r
     if (slot < T.count) {
       const int k = slot_kernel[T.first + slot];
       const double v = tap_of(taps64, off, mlo, len, k, T.m0 + 16 * s + 8 * (lane >> 5) + ee) * kscale[k];
+      // a tap of at least half an FP16 unit (scaled) needs the correction products
+      if (part == 0 && fabs(v) >= 0.5) gflag[T.gflag_off + s / 16] = 1u;
       const __half hi = __float2half_rn(float(v));
       out = part == 0 ? __half2float(hi) : float(v - double(__half2float(hi)));
     }
@@ -706,8 +748,8 @@ void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const 
                        K->slot_kernel, zout, po);                                               \
   else                                                                                          \
     hipLaunchKernelGGL((k_recon_f16<S, F>), grid, dim3(256), 0, ctx->stream,                    \
-                       static_cast<const __half*>(zsrc), n, tiles, K->b16, K->colscale16,       \
-                       K->slot_kernel, zinv, zout, po, int(kChunkMax));
+                       static_cast<const __half*>(zsrc), n, tiles, K->b16, K->gflag,            \
+                       K->colscale16, K->slot_kernel, zinv, zout, po, int(kChunkMax));
   if (store && fused) {
     RF_RECON(true, true)
   } else if (store) {
@@ -739,11 +781,11 @@ int queue_blocks(int device) {
 
 void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
                   const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
-                  const __half* b16, const float* colscale, const int32_t* slot_kernel,
-                  const float* zinv_all, const PeakOut& po) {
+                  const __half* b16, const uint32_t* gflag, const float* colscale,
+                  const int32_t* slot_kernel, const float* zinv_all, const PeakOut& po) {
   fill_u32(ctx, counter, 0u, 1);
   hipLaunchKernelGGL(k_recon_f16_queue, dim3(unsigned(nblocks)), dim3(256), 0, ctx->stream, zs_all, n,
-                     nref, tiles, items, nitems, counter, b16, colscale, slot_kernel, zinv_all, po);
+                     nref, tiles, items, nitems, counter, b16, gflag, colscale, slot_kernel, zinv_all, po);
   RF_HIP(hipGetLastError());
 }
 
@@ -756,7 +798,7 @@ void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const
   RF_HIP(hipGetLastError());
   dim3 g16(nblk(max_ksteps * kB16PerStep, 4096), unsigned(ntiles));
   hipLaunchKernelGGL(k_pack_b16, g16, dim3(256), 0, ctx->stream, K->taps64, off_dev, mlo_dev,
-                     len_dev, kscale_dev, tiles_dev, K->slot_kernel, K->b16);
+                     len_dev, kscale_dev, tiles_dev, K->slot_kernel, K->b16, K->gflag);
   RF_HIP(hipGetLastError());
 }
 

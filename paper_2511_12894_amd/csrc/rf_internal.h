@@ -200,6 +200,7 @@ struct TileDev {
   int64_t ksteps;   // 16-tap steps covering it
   int64_t b32_off;  // offsets of the tile in the packed operand buffers
   int64_t b16_off;
+  int64_t gflag_off; // offset of the tile's granule flags (one per 256 taps)
   int32_t first;    // first slot of the tile in the slot arrays
   int32_t count;    // live kernels in the tile
 };
@@ -227,4 +228,10 @@ struct rf_kernels {
   float* colscale32 = nullptr;       // per slot: N_ref / N_k
   float* colscale16 = nullptr;       // per slot: N_ref / N_k / s_k
   int32_t* slot_kernel = nullptr;    // per slot: kernel index (-1 empty)
+  // per tile and 256-tap granule: 1 if some kernel of the tile has a tap there of at
+  // least half an FP16 unit after its scale s_k (|w| s_k >= 1/2, i.e. above 2^-15..2^-14
+  // of its largest tap), else 0; the split form's correction products are skipped in
+  // window chunks without such a granule
+  uint32_t* gflag = nullptr;
+  int64_t gflag_total = 0;
 };

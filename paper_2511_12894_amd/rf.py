@@ -22,7 +22,7 @@ RF_PREC_FP32, RF_PREC_SPLIT_FP16 = 0, 1
 PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "ratio_kernel_build",
-            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_free", "snr_reconstruct",
+            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
             "rf_batch_autotune", "rf_batch_run", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.rf_kernels_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                     ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.rf_kernels_taps_fp64.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+    lib.rf_kernels_split_steps.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rf_kernels_free.argtypes = [vp]
     lib.snr_reconstruct.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
     lib.snr_peaks.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
@@ -190,6 +191,12 @@ class Kernels:
         n = ctypes.c_int32()
         self.ctx.check(self.ctx.lib.rf_kernels_info(self.h, ctypes.byref(n), m_lo, ln, nr, dfl))
         return dict(m_lo=list(m_lo), len=list(ln), norm_ratio=list(nr), df_low=list(dfl))
+
+    def split_steps(self, chunk: int = 1024):
+        """(steps with the correction products, all steps) of the split-FP16 form."""
+        c, a = ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.rf_kernels_split_steps(self.h, int(chunk), ctypes.byref(c), ctypes.byref(a)))
+        return c.value, a.value
 
     def taps(self, k: int):
         import numpy as np
