@@ -289,9 +289,9 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
   // hi*hi products accumulate in `acc`, folded into the FP64 total every 32
-  // steps (at most 32 FP32 roundings at the size of |z| per fold); the two
-  // correction products, 2^-11 smaller, accumulate in `cor` over the whole
-  // item, folded once at its end.
+  // steps where the kernels' large taps are (at most 32 FP32 roundings at the
+  // size of |z| per fold); the two correction products, 2^-11 smaller,
+  // accumulate in `cor` over the whole item, folded once at its end.
   floatx16 acc[2][2], cor[2][2];
   Tot64 tot;
 #pragma unroll
@@ -373,7 +373,8 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   half8 bh[8], bl[8];
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
   // hi*hi product of every chunk into `acc`, folded into the FP64 total every
-  // 32 steps; it reads the hi planes and the hi operand only.  Pass 2 (CORR
+  // 32 steps of the flagged chunks and at the pass's end; it reads the hi
+  // planes and the hi operand only.  Pass 2 (CORR
   // true): the two correction products of the flagged chunks into `cor`.
   // Each pass restarts the window and the rings; nothing but the FP64 total
   // and `cor` lives across them.
@@ -475,11 +476,14 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       // The next visited chunk's window goes to the idle buffer in two rounds:
       // block t (loaded at this chunk's start) after the first 32 steps, block
       // t + 256 (loaded then) at the chunk's end.
+      // pass 1 folds acc every 32 steps in flagged chunks only: elsewhere every
+      // tap is below 2^-14 of its kernel's largest and the FP32 sum stays tiny
+      const bool fold_here = !CORR && flagged(c);
       bool round1 = false;
       int q = 0;
       for (; q + 32 <= nst; q += 32) {
         steps(q, std::integral_constant<int, 32>{});
-        if (!CORR) fold64(acc);
+        if (fold_here) fold64(acc);
         if (more && !round1) {
           put(buf ^ 1, threadIdx.x);
           gather(tn, threadIdx.x + 256);
@@ -488,7 +492,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       }
       if (q < nst) {
         for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
-        if (!CORR) fold64(acc);
+        if (fold_here) fold64(acc);
       }
       if (more) put(buf ^ 1, threadIdx.x + (round1 ? 256 : 0));
       __syncthreads();
@@ -498,6 +502,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
     }
   };
   pass(std::false_type{});
+  fold64(acc);
   pass(std::true_type{});
   fold64(cor);
   floatx16 totf[2][2];
