@@ -29,7 +29,11 @@
 // after power-of-two scaling; hi*hi + hi*lo + lo*hi with
 // v_mfma_f32_32x32x16_f16, FP32 accumulation).  In the split form the second
 // time block's Hankel fragment at step s is the first block's fragment at step
-// s + 2, so one LDS fragment load per plane and step serves both blocks.
+// s + 2, so one LDS fragment load per plane and step serves both blocks.  The
+// split form takes the two correction products only in the 1024-tap blocks of
+// a tile where some kernel has a tap of at least half an FP16 unit after its
+// scale (the kernels are a narrow peak with a long low tail; elsewhere hi*hi
+// alone is within 1e-6), in a second pass over those blocks.
 //
 // Optional fused read-out: instead of (or besides) storing the series, the
 // epilogue folds every output into the per-kernel peak (|z|^2 compared in FP32,
@@ -374,10 +378,9 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
   // hi*hi product of every chunk into `acc`, folded into the FP64 total every
   // 32 steps of the flagged chunks and at the pass's end; it reads the hi
-  // planes and the hi operand only.  Pass 2 (CORR
-  // true): the two correction products of the flagged chunks into `cor`.
-  // Each pass restarts the window and the rings; nothing but the FP64 total
-  // and `cor` lives across them.
+  // planes and the hi operand only.  Pass 2 (CORR true): the two correction
+  // products of the flagged chunks into `cor`.  Each pass restarts the window
+  // and the rings; only the FP64 total carries over from pass 1.
   auto pass = [&](auto corr_tag) {
     constexpr bool CORR = decltype(corr_tag)::value;
     auto next_chunk = [&](int c) {
