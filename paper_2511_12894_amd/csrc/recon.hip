@@ -102,6 +102,13 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
 
 // Window of a chunk: samples z[(n0 + m0 + t0 + i) mod n], i < ch + kTimes + 32
 // (32 extra so that the prefetch of three steps ahead stays inside the buffer).
+// Steps between folds of the matrix-core accumulator into the FP64 total: FP32
+// form 16 two-tap steps (32 taps), split form 8 sixteen-tap steps (128 taps)
+// where the kernels' large taps are.  At |z| ~ 20 the FP32 roundings of longer
+// partial sums reached 1.1e-5 (split) and 1.4e-5 (FP32) on some outputs.
+constexpr int kFoldF32 = 16;
+constexpr int kFoldF16 = 8;
+
 constexpr int kWin = kChunk + kTimes + 32;
 constexpr int kWinMax = kChunkMax + kTimes + 64;   // F fragments are read up to 4 steps past a chunk
 constexpr int kStage = (kWin + 255) / 256;
@@ -233,10 +240,10 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     load(1, bq[1], aq[1]);
     load(2, bq[2], aq[2]);
     // FP32 products enter the accumulator two at a time: it is folded into the
-    // FP64 total every 64 steps (128 taps), so only FP32 roundings of partial
-    // sums over 128 taps reach the result, whatever the kernel length
-    for (int s64 = 0; s64 < nst; s64 += 64) {
-      for (int s = s64; s < s64 + 64; s += 4) {
+    // FP64 total every kFoldF32 steps, so only FP32 roundings of partial sums
+    // over 32 taps reach the result, whatever the kernel length
+    for (int s64 = 0; s64 < nst; s64 += kFoldF32) {
+      for (int s = s64; s < s64 + kFoldF32; s += 4) {
         load(s + 3, bq[3], aq[3]);
         mma(bq[0], aq[0]);
         interleave();
@@ -292,9 +299,9 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
-  // hi*hi products accumulate in `acc`, folded into the FP64 total every 32
-  // steps where the kernels' large taps are (at most 32 FP32 roundings at the
-  // size of |z| per fold); the two correction products, 2^-11 smaller,
+  // hi*hi products accumulate in `acc`, folded into the FP64 total every
+  // kFoldF16 steps where the kernels' large taps are (at most 8 FP32 roundings
+  // at the size of |z| per fold); the two correction products, 2^-11 smaller,
   // accumulate in `cor` over the whole item, folded once at its end.
   floatx16 acc[2][2], cor[2][2];
   Tot64 tot;
@@ -377,8 +384,8 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   half8 bh[8], bl[8];
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
   // hi*hi product of every chunk into `acc`, folded into the FP64 total every
-  // 32 steps of the flagged chunks and at the pass's end; it reads the hi
-  // planes and the hi operand only.  Pass 2 (CORR true): the two correction
+  // kFoldF16 steps of the flagged chunks and at the pass's end; it reads the
+  // hi planes and the hi operand only.  Pass 2 (CORR true): the two correction
   // products of the flagged chunks into `cor`.  Each pass restarts the window
   // and the rings; only the FP64 total carries over from pass 1.
   auto pass = [&](auto corr_tag) {
@@ -479,23 +486,27 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       // The next visited chunk's window goes to the idle buffer in two rounds:
       // block t (loaded at this chunk's start) after the first 32 steps, block
       // t + 256 (loaded then) at the chunk's end.
-      // pass 1 folds acc every 32 steps in flagged chunks only: elsewhere every
-      // tap is below 2^-14 of its kernel's largest and the FP32 sum stays tiny
+      // pass 1 folds acc every kFoldF16 steps in flagged chunks only: elsewhere
+      // every tap is below 2^-14 of its kernel's largest and the FP32 sum stays tiny
       const bool fold_here = !CORR && flagged(c);
       bool round1 = false;
       int q = 0;
-      for (; q + 32 <= nst; q += 32) {
-        steps(q, std::integral_constant<int, 32>{});
+      constexpr int P = CORR ? 32 : kFoldF16;
+      for (; q + P <= nst; q += P) {
+        steps(q, std::integral_constant<int, P>{});
         if (fold_here) fold64(acc);
-        if (more && !round1) {
+        if (more && !round1 && q + P >= 32) {
           put(buf ^ 1, threadIdx.x);
           gather(tn, threadIdx.x + 256);
           round1 = true;
         }
       }
       if (q < nst) {
-        for (; q < nst; q += 8) steps(q, std::integral_constant<int, 8>{});
-        if (fold_here) fold64(acc);
+        for (; q < nst; q += 8) {
+          steps(q, std::integral_constant<int, 8>{});
+          if (fold_here && (q + 8) % kFoldF16 == 0) fold64(acc);
+        }
+        if (fold_here && nst % kFoldF16 != 0) fold64(acc);
       }
       if (more) put(buf ^ 1, threadIdx.x + (round1 ? 256 : 0));
       __syncthreads();
