@@ -149,7 +149,11 @@ rf_status rf_kernels_free(rf_kernels* k);
  *   z_k[m] = (N_ref / N_k) sum_{s = m_lo}^{m_hi} z_ref[(m + s) mod n] w_k[s].
  *   z_ref  device complex64 [n] (from mf_ref_snr of the reference)
  *   n      segment length (power of two, >= the kernels' n_build)
- *   prec   RF_PREC_FP32 or RF_PREC_SPLIT_FP16
+ *   prec   RF_PREC_FP32 (FP32 operands, FP32 partial sums of 32 taps added in
+ *          FP64) or RF_PREC_SPLIT_FP16 (z and w split into FP16 hi + lo parts
+ *          after power-of-two scales; hi*hi everywhere, hi*lo + lo*hi where a
+ *          kernel of the tile has large taps, see rf_kernels_split_steps; FP32
+ *          partial sums of at most 128 taps added in FP64)
  *   z_out  device complex64 [nk][n], or NULL to skip the series
  *   fused  NULL, or peak/trigger read-out of every series (then the call syncs);
  *          at least one of z_out and fused must be non-NULL.
