@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void k_row_l1(const double* __restrict__ Bm, i
   part[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    if (int(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = part[0];

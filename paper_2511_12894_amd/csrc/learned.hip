@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, cons
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    if (int(threadIdx.x) < k) sh[threadIdx.x] += sh[threadIdx.x + k];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -239,10 +239,10 @@ constexpr int kMseBlocks = 64;
 __global__ void k_loss_final(const float* __restrict__ part, int np, int64_t n, float* hist,
                              const int32_t* counter) {
   __shared__ float sh[64];
-  sh[threadIdx.x] = threadIdx.x < np ? part[threadIdx.x] : 0.f;
+  sh[threadIdx.x] = int(threadIdx.x) < np ? part[threadIdx.x] : 0.f;
   __syncthreads();
   for (int k = 32; k > 0; k >>= 1) {
-    if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    if (int(threadIdx.x) < k) sh[threadIdx.x] += sh[threadIdx.x + k];
     __syncthreads();
   }
   if (threadIdx.x == 0) hist[counter ? *counter : 0] = sh[0] / float(n);

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kRedThreads) void k_moment_partial(const double* __
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_partials(const double* __re
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    if (int(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sh[0];
