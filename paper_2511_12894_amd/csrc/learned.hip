@@ -299,6 +299,7 @@ __global__ void k_window(const double2* __restrict__ out, int64_t nb, int L, dou
 __global__ void k_to_targets(const double2* __restrict__ c, int n, int rank, double inv_scale,
                              float* __restrict__ T) {
   const int p = blockIdx.x;
+  if (p >= n) return;
   for (int j = threadIdx.x; j < rank; j += blockDim.x) {
     const double2 v = c[int64_t(p) * rank + j];
     T[int64_t(p) * 2 * rank + j] = float(v.x * inv_scale);
@@ -310,6 +311,7 @@ __global__ void k_to_targets(const double2* __restrict__ c, int n, int rank, dou
 __global__ void k_from_outputs(const float* __restrict__ o, int n, int rank, double scale,
                                double2* __restrict__ c) {
   const int p = blockIdx.x;
+  if (p >= n) return;
   for (int j = threadIdx.x; j < rank; j += blockDim.x)
     c[int64_t(p) * rank + j] = make_double2(double(o[int64_t(p) * 2 * rank + j]) * scale,
                                             double(o[int64_t(p) * 2 * rank + rank + j]) * scale);
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(256) void k_rowmaxdiff(const float2* __restrict__ a
   sh[threadIdx.x] = mx;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + k]);
+    if (int(threadIdx.x) < k) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + k]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
