@@ -93,10 +93,12 @@ def _decode(rf, out, nseg, ktot):
     return np.stack([v.reshape(nseg, ktot), i.reshape(nseg, ktot)], axis=-1).astype(np.float64), trig
 
 
-def test_batch_matches_per_call_exactly(rf, work, setup):
-    """Same chunk size as the per-call path: bit-identical peaks and triggers."""
+@pytest.mark.parametrize("chunk", [256, 512, 1024])
+def test_batch_matches_per_call_exactly(rf, work, setup, chunk):
+    """Any window chunk size gives the per-call path's sums (the same folds and
+    the same steps with correction products): bit-identical peaks and triggers."""
     b = setup["batch"]
-    b.set_chunks([512, 512, 512])
+    b.set_chunks([chunk, chunk, chunk])
     _say(f"batch info {b.info()}")
     out = b.run(setup["xf"], 6.0)
     got_p, got_t = _decode(rf, out, 2, b.ktotal)
