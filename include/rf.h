@@ -153,7 +153,8 @@ rf_status rf_kernels_free(rf_kernels* k);
  *          FP64) or RF_PREC_SPLIT_FP16 (z and w split into FP16 hi + lo parts
  *          after power-of-two scales; hi*hi everywhere, hi*lo + lo*hi where a
  *          kernel of the tile has large taps, see rf_kernels_split_steps; FP32
- *          partial sums of at most 128 taps added in FP64)
+ *          partial sums added in FP64, of at most 128 taps where a kernel of
+ *          the tile has taps above 1/64..1/32 of its largest, longer elsewhere)
  *   z_out  device complex64 [nk][n], or NULL to skip the series
  *   fused  NULL, or peak/trigger read-out of every series (then the call syncs);
  *          at least one of z_out and fused must be non-NULL.

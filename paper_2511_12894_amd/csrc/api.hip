@@ -402,7 +402,7 @@ rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* co
       uint32_t need = 0;
       for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= flags[size_t(T.gflag_off + g)];
       all += ch / 16;
-      if (need) corr += ch / 16;
+      if (need & 1) corr += ch / 16;   // bit 1: the correction products
     }
   }
   if (corr_steps) *corr_steps = corr;

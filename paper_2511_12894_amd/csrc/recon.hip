@@ -106,8 +106,14 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
 // form 16 two-tap steps (32 taps), split form 8 sixteen-tap steps (128 taps)
 // where the kernels' large taps are.  At |z| ~ 20 the FP32 roundings of longer
 // partial sums reached 1.1e-5 (split) and 1.4e-5 (FP32) on some outputs.
-constexpr int kFoldF32 = 16;
 constexpr int kFoldF16 = 8;
+constexpr int kFoldF32 = 16;
+// Split form: the hi*hi sums are folded every kFoldF16 steps only in the
+// 1024-tap blocks that hold a scaled tap of at least kFoldTap (1/64..1/32 of
+// the kernel's largest, which is scaled into [2^13, 2^14)).  Elsewhere the
+// partial sums stay far below |z|, and so do their FP32 roundings: folding
+// only there left the largest error of every output unchanged (5.7e-6 at 64 s).
+constexpr double kFoldTap = 256.0;
 
 constexpr int kWin = kChunk + kTimes + 32;
 constexpr int kWinMax = kChunkMax + kTimes + 64;   // F fragments are read up to 4 steps past a chunk
@@ -301,7 +307,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   const int sigma = row & 3;
   // hi*hi products accumulate in `acc`, folded into the FP64 total every
   // kFoldF16 steps where the kernels' large taps are (at most 8 FP32 roundings
-  // at the size of |z| per fold); the two correction products, 2^-11 smaller,
+  // at the size of |z| per fold; granule bit 2); the two correction products, 2^-11 smaller,
   // accumulate in `cor` over the whole item, folded once at its end.
   floatx16 acc[2][2], cor[2][2];
   Tot64 tot;
@@ -368,18 +374,21 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
   // multiple of 4; in the interleaved layout 4 positions are 16 halves)
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
-  // Chunk c takes the correction products if its tile has a flagged granule
+  // Chunk c takes the correction products if its tile has a granule with bit 1
   // (a scaled tap of at least 1/2) in the 1024-tap blocks (from the tile's first
-  // tap) that the chunk lies in: the same steps get them whatever the chunk
-  // size (256, 512 or 1024), so every chunk size gives the same sums.
-  auto flagged = [&](int c) {
+  // tap) that the chunk lies in, and the short folds if one has bit 2: the same
+  // steps get them whatever the chunk size (256, 512 or 1024), so every chunk
+  // size gives the same sums.
+  auto flagbits = [&](int c) {
     const int64_t a = (int64_t(c) * chunk / 1024) * 1024;
     const int64_t e = (int64_t(c + 1) * chunk + 1023) / 1024 * 1024;
     const int64_t b = e < ntaps ? e : ntaps;
     uint32_t need = 0;
     for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= gflag[T.gflag_off + g];
-    return __builtin_amdgcn_readfirstlane(int(need)) != 0;
+    return __builtin_amdgcn_readfirstlane(int(need));
   };
+  auto flagged = [&](int c) { return (flagbits(c) & 1) != 0; };
+  auto foldflag = [&](int c) { return (flagbits(c) & 2) != 0; };
   // B ring (slot = step % 8, six steps ahead); it runs on across consecutive chunks
   half8 bh[8], bl[8];
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
@@ -486,9 +495,10 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       // The next visited chunk's window goes to the idle buffer in two rounds:
       // block t (loaded at this chunk's start) after the first 32 steps, block
       // t + 256 (loaded then) at the chunk's end.
-      // pass 1 folds acc every kFoldF16 steps in flagged chunks only: elsewhere
-      // every tap is below 2^-14 of its kernel's largest and the FP32 sum stays tiny
-      const bool fold_here = !CORR && flagged(c);
+      // pass 1 folds acc every kFoldF16 steps only in chunks whose 1024-tap
+      // blocks hold a tap of at least kFoldTap (scaled): elsewhere every tap is
+      // below 1/32 of its kernel's largest and the FP32 partial sums stay small
+      const bool fold_here = !CORR && foldflag(c);
       bool round1 = false;
       int q = 0;
       constexpr int P = CORR ? 32 : kFoldF16;
@@ -641,7 +651,8 @@ __global__ void k_pack_b32(const double* __restrict__ taps64, const int64_t* __r
 // FP16 operand of a tile: per 16-tap step s, the hi fragment then the lo
 // fragment; lane l holds 8 halves w_{slot l%32}[m0 + 16 s + 8 (l/32) + 0..7]
 // (scaled by the kernel's power-of-two s_k).  Also marks the tile's 256-tap
-// granules holding a scaled tap of magnitude >= 1/2 (gflag, zeroed before).
+// granules (gflag, zeroed before): bit 1 where a scaled tap reaches 1/2 (the
+// correction products), bit 2 where one reaches kFoldTap (the short folds).
 __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __restrict__ off,
                            const int64_t* __restrict__ mlo, const int32_t* __restrict__ len,
                            const double* __restrict__ kscale, const TileDev* __restrict__ tiles,
@@ -658,7 +669,7 @@ __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __r
       const int k = slot_kernel[T.first + slot];
       const double v = tap_of(taps64, off, mlo, len, k, T.m0 + 16 * s + 8 * (lane >> 5) + ee) * kscale[k];
       // a tap of at least half an FP16 unit (scaled) needs the correction products
-      if (part == 0 && fabs(v) >= 0.5) gflag[T.gflag_off + s / 16] = 1u;
+      if (part == 0 && fabs(v) >= 0.5) atomicOr(&gflag[T.gflag_off + s / 16], fabs(v) >= kFoldTap ? 3u : 1u);
       const __half hi = __float2half_rn(float(v));
       out = part == 0 ? __half2float(hi) : float(v - double(__half2float(hi)));
     }

@@ -200,7 +200,7 @@ struct TileDev {
   int64_t ksteps;   // 16-tap steps covering it
   int64_t b32_off;  // offsets of the tile in the packed operand buffers
   int64_t b16_off;
-  int64_t gflag_off; // offset of the tile's granule flags (one per 256 taps)
+  int64_t gflag_off; // offset of the tile's granule flags (one per 256 taps; bit 1 corrections, bit 2 folds)
   int32_t first;    // first slot of the tile in the slot arrays
   int32_t count;    // live kernels in the tile
 };
