@@ -138,9 +138,10 @@ rf_status rf_kernels_taps_fp64(const rf_kernels* k, int32_t idx, double* host_ou
  * those that carry the two correction products: a step takes the hi*hi
  * product alone when no kernel of its tile has a tap with |w| s_k >= 1/2 (s_k
  * the kernel's FP16 scale; such taps are below 2^-14 of the kernel's largest)
- * in the 1024-tap block, counted from the tile's first tap, that holds the
- * step.  Either pointer may be NULL.  Synchronises (reads the tiles' granule
- * flags). */
+ * in the 512-tap block, counted from the tile's first tap, that holds the
+ * step.  Neither count depends on `chunk` (the correction pass uses 512-tap
+ * chunks whatever the first pass uses); it is checked for validity only.
+ * Either pointer may be NULL.  Synchronises (reads the tiles' granule flags). */
 rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* corr_steps, int64_t* all_steps);
 rf_status rf_kernels_free(rf_kernels* k);
 

@@ -394,15 +394,13 @@ rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* co
   int64_t corr = 0, all = 0;
   for (const rf::TileDev& T : k->tiles) {
     const int64_t ntaps = T.ksteps * 16;
-    for (int64_t t0 = 0; t0 < ntaps; t0 += chunk) {
-      const int64_t ch = std::min<int64_t>(chunk, ntaps - t0);
-      // the 1024-tap blocks the chunk lies in decide, as in the kernels
-      const int64_t a = t0 / 1024 * 1024;
-      const int64_t b = std::min<int64_t>((t0 + chunk + 1023) / 1024 * 1024, ntaps);
+    all += T.ksteps;
+    // the corrections run over chunks of kCorrChunk taps, whatever `chunk` is
+    for (int64_t t0 = 0; t0 < ntaps; t0 += rf::kCorrChunk) {
+      const int64_t b = std::min<int64_t>(t0 + rf::kCorrChunk, ntaps);
       uint32_t need = 0;
-      for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= flags[size_t(T.gflag_off + g)];
-      all += ch / 16;
-      if (need & 1) corr += ch / 16;   // bit 1: the correction products
+      for (int64_t g = t0 / 256; g < (b + 255) / 256; ++g) need |= flags[size_t(T.gflag_off + g)];
+      if (need & 1) corr += (b - t0) / 16;   // bit 1: the correction products
     }
   }
   if (corr_steps) *corr_steps = corr;

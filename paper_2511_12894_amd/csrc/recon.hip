@@ -301,7 +301,6 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
                                       const float* __restrict__ colscale,
                                       const int32_t* __restrict__ slot_kernel, float zinv,
                                       float2* __restrict__ zout, const PeakOut& po) {
-  const int win_len = chunk + kTimes + 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
@@ -330,7 +329,6 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
       }
   };
   const int64_t ntaps = T.ksteps * 16;
-  const int nch = int((ntaps + chunk - 1) / chunk);
   const half8* B = reinterpret_cast<const half8*>(b16 + T.b16_off) + lane;
   const uint2* __restrict__ zq = reinterpret_cast<const uint2*>(zs);   // 4 halves per element
   const int64_t mask = n - 1;
@@ -340,7 +338,8 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // layout, so block k needs samples 4k .. 4k + 6, two aligned 4-sample loads
   // per plane.  Thread t handles block t and, for chunks above 736 taps, block
   // t + 256, both through the same staging registers (two rounds per chunk).
-  const int nblk = win_len / 4;
+  // The window of a chunk of cs taps holds cs + kTimes + 32 samples.
+  int nblk = 0;
   uint2 stage[4][2];
   auto load_blk = [&](int64_t t0, int k, uint2 (&v)[4][2]) {
     const int64_t g = ((gbase + t0 + 4 * k) & mask) >> 2;
@@ -374,31 +373,39 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   // fragment F(j): 8 samples at position p0 + 16 j of copy `sigma` (p0 is a
   // multiple of 4; in the interleaved layout 4 positions are 16 halves)
   const int p0 = (row - sigma) + 64 * wave + 8 * kh;
-  // Chunk c takes the correction products if its tile has a granule with bit 1
-  // (a scaled tap of at least 1/2) in the 1024-tap blocks (from the tile's first
-  // tap) that the chunk lies in, and the short folds if one has bit 2: the same
-  // steps get them whatever the chunk size (256, 512 or 1024), so every chunk
-  // size gives the same sums.
-  auto flagbits = [&](int c) {
-    const int64_t a = (int64_t(c) * chunk / 1024) * 1024;
-    const int64_t e = (int64_t(c + 1) * chunk + 1023) / 1024 * 1024;
+  // Granule flag bits of taps [a, b) of the tile (a a multiple of 256).
+  auto flagbits = [&](int64_t a, int64_t e) {
     const int64_t b = e < ntaps ? e : ntaps;
     uint32_t need = 0;
     for (int64_t g = a / 256; g < (b + 255) / 256; ++g) need |= gflag[T.gflag_off + g];
     return __builtin_amdgcn_readfirstlane(int(need));
   };
-  auto flagged = [&](int c) { return (flagbits(c) & 1) != 0; };
-  auto foldflag = [&](int c) { return (flagbits(c) & 2) != 0; };
+  // Pass-2 chunk c (kCorrChunk taps) takes the correction products if one of
+  // its granules has bit 1 (a scaled tap of at least 1/2).  Pass-1 chunk c
+  // (`chunk` taps) takes the short folds if a granule of the 1024-tap blocks
+  // (from the tile's first tap) that it lies in has bit 2: the same steps get
+  // them whatever the chunk size (256, 512 or 1024), so every chunk size gives
+  // the same sums.
+  auto flagged = [&](int c) {
+    return (flagbits(int64_t(c) * kCorrChunk, int64_t(c + 1) * kCorrChunk) & 1) != 0;
+  };
+  auto foldflag = [&](int c) {
+    return (flagbits((int64_t(c) * chunk / 1024) * 1024, (int64_t(c + 1) * chunk + 1023) / 1024 * 1024) & 2) != 0;
+  };
   // B ring (slot = step % 8, six steps ahead); it runs on across consecutive chunks
   half8 bh[8], bl[8];
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
-  // hi*hi product of every chunk into `acc`, folded into the FP64 total every
-  // kFoldF16 steps of the flagged chunks and at the pass's end; it reads the
-  // hi planes and the hi operand only.  Pass 2 (CORR true): the two correction
-  // products of the flagged chunks into `cor`.  Each pass restarts the window
-  // and the rings; only the FP64 total carries over from pass 1.
+  // hi*hi product of every chunk of `chunk` taps into `acc`, folded into the
+  // FP64 total every kFoldF16 steps of the chunks with bit 2 and at the pass's
+  // end; it reads the hi planes and the hi operand only.  Pass 2 (CORR true):
+  // the two correction products of the flagged chunks of kCorrChunk taps into
+  // `cor`.  Each pass restarts the window and the rings; only the FP64 total
+  // carries over from pass 1.
   auto pass = [&](auto corr_tag) {
     constexpr bool CORR = decltype(corr_tag)::value;
+    const int cs = CORR ? kCorrChunk : chunk;
+    const int nch = int((ntaps + cs - 1) / cs);
+    nblk = (cs + kTimes + 32) / 4;
     auto next_chunk = [&](int c) {
       ++c;
       if constexpr (CORR)
@@ -411,19 +418,19 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
     };
     int c = next_chunk(-1);
     if (c >= nch) return;
-    gather(int64_t(c) * chunk, threadIdx.x);
+    gather(int64_t(c) * cs, threadIdx.x);
     put(0, threadIdx.x);
-    gather(int64_t(c) * chunk, threadIdx.x + 256);
+    gather(int64_t(c) * cs, threadIdx.x + 256);
     put(0, threadIdx.x + 256);
     __syncthreads();
     int buf = 0;
     int prev = -2;                          // chunk the B ring last ran through
     while (c < nch) {
-      const int64_t t0 = int64_t(c) * chunk;
-      const int ch = int(ntaps - t0 < chunk ? ntaps - t0 : chunk);
+      const int64_t t0 = int64_t(c) * cs;
+      const int ch = int(ntaps - t0 < cs ? ntaps - t0 : cs);
       const int cn = next_chunk(c);
       const bool more = cn < nch;
-      const int64_t tn = int64_t(cn) * chunk;
+      const int64_t tn = int64_t(cn) * cs;
       if (more) gather(tn, threadIdx.x);
       const int64_t s0 = t0 / 16;
       if (prev != c - 1) {

@@ -36,7 +36,7 @@ def _expected_steps(info, taps, chunk):
     from a multiple of 4, rounded up to 128 taps; a 256-tap granule is marked
     where a kernel has |w| s_k >= 1/2 (s_k = 2^(14 - e), e the binary exponent
     of the largest |w| as an FP32 value); a step takes the corrections when
-    its 1024-tap block holds a marked granule."""
+    its 512-tap block holds a marked granule, whatever the window chunk."""
     nk = len(info["len"])
     order = sorted(range(nk), key=lambda k: info["m_lo"][k])
     corr = total = 0
@@ -54,13 +54,11 @@ def _expected_steps(info, taps, chunk):
             s = 2.0 ** (14 - int(e))
             pos = np.nonzero(np.abs(w * s) >= 0.5)[0] + (info["m_lo"][k] - m0)
             marked[np.unique(pos // 256)] = True
-        for t0 in range(0, ntaps, chunk):
-            ch = min(chunk, ntaps - t0)
-            a = t0 // 1024 * 1024
-            b = min(-(-(t0 + chunk) // 1024) * 1024, ntaps)
-            total += ch // 16
-            if marked[a // 256: -(-b // 256)].any():
-                corr += ch // 16
+        total += ntaps // 16
+        for t0 in range(0, ntaps, 512):
+            b = min(t0 + 512, ntaps)
+            if marked[t0 // 256: -(-b // 256)].any():
+                corr += (b - t0) // 16
     return corr, total
 
 

@@ -1,5 +1,5 @@
 """The split-FP16 reconstruction computes the two correction products (hi*lo,
-lo*hi) only in the 1024-tap blocks of a 32-kernel tile where some kernel has
+lo*hi) only in the 512-tap blocks of a 32-kernel tile where some kernel has
 a tap of at least half an FP16 unit after its power-of-two scale s_k (max |w|
 s_k in [2^13, 2^14)).  This pins, on the CPU and in FP64, what that rule drops:
 on a realistic-structure workload (64 s at 4096 Hz, ratio kernels of ~12k
@@ -33,7 +33,7 @@ def test_dropped_corrections_stay_below_1e6():
     lo = np.array([k["m_lo"] for k in ks])
     m0 = (lo.min() // 4) * 4                           # tile start (a multiple of 4)
     span = max(k["m_lo"] + len(k["taps"]) for k in ks) - m0
-    nblock = -(-span // 1024)
+    nblock = -(-span // 512)
     flagged = np.zeros(nblock, bool)
     scales = []
     for k in ks:
@@ -41,11 +41,11 @@ def test_dropped_corrections_stay_below_1e6():
         s = _pow2_scale(np.abs(t).max())
         scales.append(s)
         big = np.nonzero(np.abs(t * s) >= 0.5)[0] + (k["m_lo"] - m0)
-        flagged[np.unique(big // 1024)] = True
+        flagged[np.unique(big // 512)] = True
     assert 0 < flagged.sum() < nblock
     # share of the tile's 16-tap steps without corrections
     nst = -(-span // 128) * 8
-    drop_steps = sum(min(64, nst - 64 * b) for b in range(nblock) if not flagged[b])
+    drop_steps = sum(min(32, nst - 32 * b) for b in range(nblock) if not flagged[b])
     assert drop_steps / nst > 0.5
     # FP64 value of the dropped terms: sum over unflagged taps of z_lo w_hi + z_hi w_lo
     sz = _pow2_scale(max(np.abs(zr.real).max(), np.abs(zr.imag).max()))
@@ -61,7 +61,7 @@ def test_dropped_corrections_stay_below_1e6():
     worst = 0.0
     for k, kb in enumerate(ks):
         t = kb["taps"]
-        keep = flagged[(np.arange(len(t)) + kb["m_lo"] - m0) // 1024]
+        keep = flagged[(np.arange(len(t)) + kb["m_lo"] - m0) // 512]
         wh, wl = _split16(t * scales[k])
         dh, dl = np.where(keep, 0.0, wh), np.where(keep, 0.0, wl)
         off = kb["m_lo"] % n
