@@ -71,3 +71,66 @@ def test_dropped_corrections_stay_below_1e6():
         worst = max(worst, np.abs(er + 1j * ei).max() * nr / nk / (sz * scales[k]))
     print(f"dropped steps {drop_steps / nst:.3f}, largest dropped contribution {worst:.2e}")
     assert worst <= 1e-6, worst
+
+
+def test_short_folds_where_the_largest_taps_are():
+    """The first pass adds its hi*hi products into FP32 partial sums, one
+    rounding per 16-tap step (the matrix instruction sums its 16 products
+    before rounding into the accumulator), and folds them into an FP64 total
+    every 8 steps only in the 1024-tap blocks where some kernel of the tile has
+    a scaled tap of at least 256 (1/64..1/32 of its largest), and once at the
+    end.  Emulated on the CPU in that order, over the 1024 outputs around the
+    SNR-20 injection (where |z| peaks and roundings are largest) for 8 kernels
+    of the 64-s workload: the rule's roundings match those of folding in every
+    block with corrections and stay far below the 1e-5 budget; folding only at
+    the end is six times worse, so a dropped fold fails here."""
+    w = synth.workload_realistic(n_nbr=32, duration=64.0)
+    g = w["grid"]
+    n = g.n
+    zr, nr = omf.grid_snr_series(g, w["xf"], w["psd"], *w["ref"])
+    ks = [orat.build_kernel(g, w["ref"], nb) for nb in w["nbrs"]]
+    m0 = (min(k["m_lo"] for k in ks) // 4) * 4
+    span = max(k["m_lo"] + len(k["taps"]) for k in ks) - m0
+    ntaps = -(-span // 128) * 128
+    nst = ntaps // 16
+
+    def marked(th):
+        f = np.zeros(-(-ntaps // 1024), bool)
+        for k in ks:
+            t = k["taps"]
+            big = np.nonzero(np.abs(t * _pow2_scale(np.abs(t).max())) >= th)[0] + (k["m_lo"] - m0)
+            f[np.unique(big // 1024)] = True
+        return f
+    fold_blocks, corr_blocks = marked(256.0), marked(0.5)
+    assert 0 < fold_blocks.sum() < corr_blocks.sum()
+    M = 1024
+    ms = (int(np.argmax(np.abs(zr))) - M // 2 + np.arange(M)) % n
+    sz = _pow2_scale(np.abs(zr).max())
+    rules = {"rule": fold_blocks, "every_corr_block": corr_blocks, "end_only": np.zeros_like(fold_blocks)}
+    worst = dict.fromkeys(rules, 0.0)
+    for k in range(0, 32, 4):
+        kb = ks[k]
+        t = kb["taps"]
+        s = _pow2_scale(np.abs(t).max())
+        wt = np.zeros(ntaps)
+        off = kb["m_lo"] - m0
+        wt[off:off + len(t)] = t * s
+        nk = omf.norm(g.fs, g.n, g.f_low, g.f_high, w["psd"], omf.template_spectrum(g.fs, g.n, *w["nbrs"][k]))
+        to_snr = nr / nk / (s * sz)
+        Z = zr[(ms[:, None] + m0 + np.arange(ntaps)[None, :]) % n] * sz
+        P = (Z * wt[None, :]).reshape(M, nst, 16).sum(axis=2)      # exact 16-tap step sums
+        for name, blocks in rules.items():
+            for part in (P.real, P.imag):
+                acc = np.zeros(M, np.float32)
+                tot = np.zeros(M)
+                for st in range(nst):
+                    acc = (acc.astype(np.float64) + part[:, st]).astype(np.float32)
+                    if (st + 1) % 8 == 0 and blocks[st * 16 // 1024]:
+                        tot += acc
+                        acc[:] = 0
+                tot += acc
+                worst[name] = max(worst[name], np.abs(tot - part.sum(axis=1)).max() * to_snr)
+    print(f"largest rounding error: {worst}")
+    assert worst["rule"] <= 1.05 * worst["every_corr_block"]
+    assert worst["rule"] <= 4e-6
+    assert worst["end_only"] >= 3 * worst["rule"]
