@@ -107,6 +107,18 @@ const char* rf_last_error(const rf_ctx* ctx);
 rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
                      const rf_tmpl* tmpl, int32_t nt, void* z, double* sigma);
 
+/* Direct matched filtering with the read-out only (the comparator of section
+ * IV: every template filtered on its own, equation matched_filter): the same
+ * series as mf_ref_snr, bit for bit, but the last transform pass reads each
+ * one out (running peak of |z|, crossings |z| > out->thr) instead of storing it.
+ *   xf, psd, tmpl, nt   as mf_ref_snr
+ *   out->peaks   device rf_peak [nt]; out->trig device rf_trigger [out->cap]
+ *                (seg = 0, unspecified order); *out->ntrig host count (may
+ *                exceed cap).
+ * Synchronises; RF_E_OVERFLOW when the count exceeds cap. */
+rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
+                       const rf_tmpl* tmpl, int32_t nt, const rf_peak_args* out);
+
 /* Exact truncated ratio kernels of nk targets against one reference
  * (sections II.B-II.D):
  *   R~_j = W(f_j) (B_k/B_ref)(f_j) exp(-i (Psi_k - Psi_ref)(f_j)), j = 0..nb/2,

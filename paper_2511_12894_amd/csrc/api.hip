@@ -238,6 +238,55 @@ rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const dou
   });
 }
 
+rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
+                       const rf_tmpl* tmpl, int32_t nt, const rf_peak_args* out) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    validate_grid(grid);
+    RF_CHECK(xf && psd && tmpl && out, "mf_snr_peaks: null pointer");
+    RF_CHECK(nt >= 1, "mf_snr_peaks: nt must be >= 1");
+    RF_CHECK(out->peaks && out->ntrig && out->cap >= 0 && (out->cap == 0 || out->trig),
+             "mf_snr_peaks: bad read-out arguments");
+    RF_CHECK(std::isfinite(out->thr) && out->thr >= 0, "mf_snr_peaks: bad threshold");
+    const int64_t n = grid->n;
+    std::vector<Tf2Coef> coef(nt);
+    for (int i = 0; i < nt; ++i) {
+      validate_tmpl(tmpl[i]);
+      coef[i] = tf2_coef(tmpl[i]);
+    }
+    Tf2Coef* coef_dev = upload(ctx, WS_COEF, coef.data(), coef.size());
+    double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
+    band_moment(ctx, grid, psd, moment);
+    int64_t jlo, jhi;
+    band_limits(grid, &jlo, &jhi);
+    float2* q = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(jhi - jlo + 1)));
+    condition_data(ctx, grid, static_cast<const double2*>(xf), psd, q);
+    uint64_t* packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * (nt + 1)));
+    fill_u64(ctx, packed, 0ull, nt + 1);
+    PeakOut po{};
+    po.packed = packed;
+    po.count = reinterpret_cast<unsigned long long*>(packed + nt);
+    po.trig = out->trig;
+    po.cap = out->cap;
+    po.thr2 = out->thr * out->thr;
+    po.seg = 0;
+    po.nk = nt;
+    // templates in batches (two transform scratch buffers of up to 2 GiB each)
+    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    for (int t0 = 0; t0 < nt; t0 += per) {
+      const int cnt = std::min(per, nt - t0);
+      po.tmpl0 = t0;
+      fft_inverse_tmpl_peaks_f32(ctx, grid, q, coef_dev + t0, cnt, moment, cnt, po);
+    }
+    peaks_finalize(ctx, packed, nt, out->peaks);
+    unsigned long long c = 0;
+    RF_HIP(hipMemcpyAsync(&c, po.count, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    *out->ntrig = int64_t(c);
+    if (int64_t(c) > out->cap) throw Error{RF_E_OVERFLOW, "mf_snr_peaks: trigger buffer overflow"};
+  });
+}
+
 rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd, rf_tmpl ref,
                              const rf_tmpl* nbr, int32_t nk, double thr, rf_thr_unit unit,
                              int64_t n_build, rf_kernels** out) {

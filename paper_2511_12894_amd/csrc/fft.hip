@@ -15,7 +15,7 @@
 // weighted template spectrum (FP64 phase), so neither is ever stored.
 #include <type_traits>
 
-#include "rf_internal.h"
+#include "recon.h"
 
 namespace rf {
 namespace {
@@ -154,10 +154,13 @@ struct TmplIn {
 
 enum PassInput { kPlain = 0, kBand = 1, kTmpl = 2 };
 
-template <typename T, int P, int MODE>
+// RO (a pass after the first, FP32): the outputs are not stored but read out
+// (running peak and threshold crossings of series tmpl0 + blockIdx.y).
+template <typename T, int P, int MODE, bool RO = false>
 __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* __restrict__ in,
                                                        typename C2<T>::t* __restrict__ out,
-                                                       int64_t n, int64_t ns, BandIn bin, TmplIn tin) {
+                                                       int64_t n, int64_t ns, BandIn bin, TmplIn tin,
+                                                       PeakOut po) {
   using V = typename C2<T>::t;
   __shared__ V s[kCols][P + 1];
   __shared__ V tw[P];
@@ -226,6 +229,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   }
   __syncthreads();
   inner_dft<T, P, 1>(s, tw);
+  if constexpr (RO) {
+    static_assert(std::is_same<T, float>::value && MODE == kPlain, "read-out: FP32 passes after the first");
+    // output m = (j / ns) ns P + j mod ns + q ns, as in the store below
+    Best best{-1.f, INT32_MAX};
+    for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
+      const int c = e % kCols, q = e / kCols;
+      const int64_t j = j0 + c;
+      peak_visit(best, s[c][q].x, s[c][q].y, (j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns, po);
+    }
+    peak_commit(best, po);
+    return;
+  }
   if (ns == 1) {
     // out[j P + q]: the block's 16 columns are one contiguous run
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
@@ -251,16 +266,17 @@ std::vector<int> plan_passes(int lg) {
   return bits;
 }
 
-template <typename T, int MODE = kPlain>
+template <typename T, int MODE = kPlain, bool RO = false>
 void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}, TmplIn tin = TmplIn{}) {
+                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}, TmplIn tin = TmplIn{},
+                 PeakOut po = PeakOut{}) {
   const int64_t P = int64_t(1) << bits;
   dim3 grid(unsigned((n / P) / kCols), unsigned(batch));
   switch (bits) {
 #define RF_FFT_CASE(B)                                                                            \
   case B:                                                                                         \
-    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), MODE>), grid, dim3(kThreads), 0, st, in, out, n, ns, \
-                       bin, tin);                                                                 \
+    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), MODE, RO>), grid, dim3(kThreads), 0, st, in, out, n, \
+                       ns, bin, tin, po);                                                         \
     break;
     RF_FFT_CASE(4)
     RF_FFT_CASE(5)
@@ -277,7 +293,7 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
 template <typename T>
 void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
                  int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in, const BandIn* band = nullptr,
-                 const TmplIn* tmpl = nullptr) {
+                 const TmplIn* tmpl = nullptr, const PeakOut* ro = nullptr) {
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
@@ -307,6 +323,12 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
         continue;
       }
     }
+    if constexpr (std::is_same<T, float>::value) {
+      if (i == s - 1 && ro) {          // the last pass reads the outputs out instead
+        launch_pass<T, kPlain, true>(bits[i], src, nullptr, n, ns, batch, ctx->stream, BandIn{}, TmplIn{}, *ro);
+        break;
+      }
+    }
     launch_pass<T>(bits[i], src, dst, n, ns, batch, ctx->stream);
     ns <<= bits[i];
     src = dst;
@@ -334,6 +356,19 @@ void fft_inverse_tmpl_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const 
   t.nt = nt;
   RF_CHECK(t.jlo >= 1 && t.jhi < g->n, "fft: band outside the transform");
   fft_inverse<float>(ctx, nullptr, out, g->n, batch, wsa, wsb, nullptr, &t);
+}
+void fft_inverse_tmpl_peaks_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
+                                const double* moment, int batch, const PeakOut& po) {
+  RF_CHECK(nt >= 1 && batch % nt == 0, "fft: batch must be a multiple of the template count");
+  TmplIn t{};
+  t.q = q;
+  t.coef = coef;
+  t.moment = moment;
+  band_limits(g, &t.jlo, &t.jhi);
+  t.df = g->fs / double(g->n);
+  t.nt = nt;
+  RF_CHECK(t.jlo >= 1 && t.jhi < g->n, "fft: band outside the transform");
+  fft_inverse<float>(ctx, nullptr, nullptr, g->n, batch, nullptr, nullptr, nullptr, &t, &po);
 }
 void fft_inverse_band_f32(rf_ctx* ctx, const float2* Q, const float2* Ub, int64_t b0, int64_t nb, float inv_n,
                           float2* out, int64_t n, int batch) {

@@ -54,7 +54,54 @@ struct PeakOut {
   float thr2;
   int32_t seg;
   int32_t nk;
+  int32_t tmpl0;   // added to blockIdx.y for the template of a peak or trigger
 };
+
+// One sample of a read-out: running peak and threshold crossing (series
+// tmpl0 + blockIdx.y of the launch).
+__device__ inline void peak_visit(Best& best, float re, float im, int64_t m, const PeakOut& po) {
+  const float a2 = abs2_rn(re, im);
+  best = better(best, Best{a2, int32_t(m)});
+  if (a2 > po.thr2) {
+    const unsigned long long slot_t = atomicAdd(po.count, 1ull);
+    if (int64_t(slot_t) < po.cap) {
+      rf_trigger tr;
+      tr.tmpl = po.tmpl0 + int32_t(blockIdx.y);
+      tr.seg = po.seg;
+      tr.idx = int32_t(m);
+      tr.absz = sqrtf(a2);
+      tr.argz = atan2f(im, re);
+      po.trig[slot_t] = tr;
+    }
+  }
+}
+
+// A workgroup's running peaks (every thread's) merged into packed[seg * nk +
+// tmpl0 + blockIdx.y] (workgroups of at most 1024 threads).
+__device__ inline void peak_commit(Best best, const PeakOut& po) {
+  for (int o = 32; o > 0; o >>= 1) {
+    Best q{__shfl_xor(best.a2, o), __shfl_xor(best.idx, o)};
+    best = better(best, q);
+  }
+  __shared__ float sa[16];
+  __shared__ int32_t si[16];
+  const int wv = int(threadIdx.x >> 6), nw = int((blockDim.x + 63) >> 6);
+  if ((threadIdx.x & 63) == 0) {
+    sa[wv] = best.a2;
+    si[wv] = best.idx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < nw; ++i) best = better(best, Best{sa[i], si[i]});
+    if (best.idx != INT32_MAX) {
+      const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
+                           uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
+      atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 +
+                                                      blockIdx.y),
+                (unsigned long long)key);
+    }
+  }
+}
 
 // Batched form: a tile of some reference's kernel set (slot arrays global
 // over the batch) and one unit of work of the persistent launch.
@@ -85,5 +132,10 @@ void peaks_finalize(rf_ctx* ctx, const uint64_t* packed, int64_t count, rf_peak*
 // Trigger records written with the raw (re, im) in (absz, argz): replace them by
 // |z| and arg z as every read-out writes them (the first min(*count, cap)).
 void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count, int64_t cap);
+// Matched filter of `batch` templates (a multiple of nt, coefficients coef[b % nt])
+// against the conditioned data q, as fft_inverse_tmpl_f32, with the last
+// transform pass reading the series out into po instead of storing them.
+void fft_inverse_tmpl_peaks_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
+                                const double* moment, int batch, const PeakOut& po);
 
 }  // namespace rf

@@ -684,24 +684,6 @@ __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __r
   }
 }
 
-// One sample of the standalone read-out: running peak and threshold crossing.
-__device__ inline void peak_visit(Best& best, float re, float im, int64_t m, const PeakOut& po) {
-  const float a2 = abs2_rn(re, im);
-  best = better(best, Best{a2, int32_t(m)});
-  if (a2 > po.thr2) {
-    const unsigned long long slot_t = atomicAdd(po.count, 1ull);
-    if (int64_t(slot_t) < po.cap) {
-      rf_trigger tr;
-      tr.tmpl = int32_t(blockIdx.y);
-      tr.seg = po.seg;
-      tr.idx = int32_t(m);
-      tr.absz = sqrtf(a2);
-      tr.argz = atan2f(im, re);
-      po.trig[slot_t] = tr;
-    }
-  }
-}
-
 // Standalone read-out over nt series (blockIdx.y).  VEC: series 16-byte aligned,
 // read two samples per 16-byte load, four loads in flight per thread.
 template <bool VEC>
@@ -731,27 +713,7 @@ __global__ __launch_bounds__(256) void k_peaks(const float2* __restrict__ z, int
       peak_visit(best, v.x, v.y, m, po);
     }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    Best q{__shfl_xor(best.a2, o), __shfl_xor(best.idx, o)};
-    best = better(best, q);
-  }
-  __shared__ float sa[4];
-  __shared__ int32_t si[4];
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    sa[wv] = best.a2;
-    si[wv] = best.idx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < 4; ++i) best = better(best, Best{sa[i], si[i]});
-    if (best.idx != INT32_MAX) {
-      const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
-                           uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
-      atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + blockIdx.y),
-                (unsigned long long)key);
-    }
-  }
+  peak_commit(best, po);
 }
 
 __global__ void k_peaks_finalize(const uint64_t* __restrict__ packed, int64_t count, rf_peak* out) {

@@ -21,7 +21,7 @@ RF_THR_PER_SECOND, RF_THR_PER_TAP = 0, 1
 RF_PREC_FP32, RF_PREC_SPLIT_FP16 = 0, 1
 PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 
-EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "ratio_kernel_build",
+EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "mf_snr_peaks", "ratio_kernel_build",
             "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
             "rf_batch_autotune", "rf_batch_run", "rf_batch_free", "rf_surrogate_create",
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     lib.rf_last_error.restype = ctypes.c_char_p
     lib.mf_ref_snr.argtypes = [vp, ctypes.POINTER(RfGrid), vp, vp, ctypes.POINTER(RfTmpl), i32, vp,
                                ctypes.POINTER(dbl)]
+    lib.mf_snr_peaks.argtypes = [vp, ctypes.POINTER(RfGrid), vp, vp, ctypes.POINTER(RfTmpl), i32,
+                                 ctypes.POINTER(RfPeakArgs)]
     lib.ratio_kernel_build.argtypes = [vp, ctypes.POINTER(RfGrid), vp, RfTmpl, ctypes.POINTER(RfTmpl),
                                        i32, dbl, ctypes.c_int, i64, ctypes.POINTER(vp)]
     lib.rf_kernels_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
@@ -232,6 +234,26 @@ def mf_ref_snr(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, template
     ctx.check(ctx.lib.mf_ref_snr(ctx.h, ctypes.byref(g), _ptr(xf), _ptr(psd), _tmpl_array(templates),
                                  nt, _ptr(z), sig))
     return z, (list(sig) if want_sigma else None)
+
+
+def mf_snr_peaks(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, templates, thr: float,
+                 trig_cap: int = 4096):
+    """Direct matched filtering of each template with the read-out only (the
+    series are not stored): peaks tensor of RfPeak bytes, triggers, count."""
+    n = int(grid.n)
+    assert xf.dtype == torch.complex128 and xf.is_cuda and xf.numel() == n // 2 + 1 and xf.is_contiguous()
+    assert psd.dtype == torch.float64 and psd.is_cuda and psd.numel() == n // 2 + 1 and psd.is_contiguous()
+    nt = len(templates)
+    peaks = torch.empty((nt, 2), dtype=torch.int32, device=xf.device)
+    trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=xf.device)
+    cnt = ctypes.c_int64(0)
+    args = RfPeakArgs(float(thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap), ctypes.pointer(cnt))
+    g = to_grid(grid)
+    st = ctx.lib.mf_snr_peaks(ctx.h, ctypes.byref(g), _ptr(xf), _ptr(psd), _tmpl_array(templates), nt,
+                              ctypes.byref(args))
+    if st not in (RF_OK, RF_E_OVERFLOW):
+        ctx.check(st)
+    return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
 
 
 def ratio_kernel_build(ctx: Context, grid, psd: torch.Tensor, ref, nbrs, thr: float = 1e-3,

@@ -114,6 +114,30 @@ def test_direct_mf_of_neighbours(rf, ctx, small, small_gpu):
 
 # ------------------------------------------------------------ kernel build
 
+def _same_readout(rf, a, b):
+    v1, i1 = rf.decode_peaks(a["peaks"])
+    v2, i2 = rf.decode_peaks(b["peaks"])
+    np.testing.assert_array_equal(i1, i2)
+    np.testing.assert_array_equal(v1, v2)
+    assert a["ntrig"] == b["ntrig"] > 0
+    assert sorted(rf.decode_triggers(a["trig"], a["ntrig"])) == sorted(rf.decode_triggers(b["trig"], b["ntrig"]))
+
+
+def test_direct_mf_readout_equals_stored_series(rf, ctx, small, small_gpu):
+    """mf_snr_peaks reads the series out in its last transform pass: peaks and
+    trigger set equal snr_peaks on the series mf_ref_snr stores, exactly."""
+    w = small["w"]
+    tm = [w["ref"]] + list(w["nbrs"])
+    z, _ = rf.mf_ref_snr(ctx, w["grid"], small_gpu["xf"], small_gpu["psd"], tm, want_sigma=False)
+    ref = rf.snr_peaks(ctx, z, 6.0, trig_cap=1 << 16)
+    out = rf.mf_snr_peaks(ctx, w["grid"], small_gpu["xf"], small_gpu["psd"], tm, 6.0, trig_cap=1 << 16)
+    _say(f"direct read-out: {out['ntrig']} triggers over {len(tm)} templates")
+    _same_readout(rf, out, ref)
+    g = rf.to_grid(w["grid"])
+    assert ctx.lib.mf_snr_peaks(ctx.h, rf.ctypes.byref(g), rf._ptr(small_gpu["xf"]), rf._ptr(small_gpu["psd"]),
+                                rf._tmpl_array(tm), len(tm), None) == rf.RF_E_INVAL
+
+
 def test_kernel_build_matches_oracle(rf, ctx, small, small_gpu):
     K = small_gpu["K"]
     info = K.info()
@@ -307,6 +331,24 @@ def test_build_length_shorter_than_segment(rf, ctx, small, small_gpu):
 @pytest.fixture(scope="module")
 def realistic():
     return synth.workload_realistic()
+
+
+def test_direct_mf_readout_full_size(rf, ctx, realistic):
+    """The benchmark's comparator shape: 257 templates of 2^21 samples, three
+    transform batches (template offsets in the read-out), exactly as the stored
+    series read out on their own."""
+    w = realistic
+    g = w["grid"]
+    xf = _dev(w["xf"], torch.complex128)
+    psd = _dev(w["psd"], torch.float64)
+    tm = [w["ref"]] + list(w["nbrs"])
+    _say(f"full-size direct read-out: {len(tm)} templates, n = {g.n}")
+    z, _ = rf.mf_ref_snr(ctx, g, xf, psd, tm, want_sigma=False)
+    ref = rf.snr_peaks(ctx, z, 6.0, trig_cap=1 << 17)
+    del z
+    out = rf.mf_snr_peaks(ctx, g, xf, psd, tm, 6.0, trig_cap=1 << 17)
+    _say(f"full-size direct read-out: {out['ntrig']} triggers")
+    _same_readout(rf, out, ref)
 
 
 def test_realistic_full_size_sampled(rf, ctx, realistic):
