@@ -96,9 +96,12 @@ __device__ inline void peak_commit(Best best, const PeakOut& po) {
     if (best.idx != INT32_MAX) {
       const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
                            uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
-      atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 +
-                                                      blockIdx.y),
-                (unsigned long long)key);
+      unsigned long long* dst =
+          reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 + blockIdx.y);
+      // keys only grow: a value read at or above this key (even a stale one) makes
+      // the atomic a no-op, so most workgroups of a long series skip it
+      if (__hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < key)
+        atomicMax(dst, (unsigned long long)key);
     }
   }
 }
