@@ -88,14 +88,27 @@ def test_mf_ref_snr_matches_oracle(rf, ctx, small, small_gpu):
 
 
 def test_mf_ref_snr_many_templates_and_tiny_grid(rf, ctx):
-    """nt = 3 templates on the smallest grid (n = 2^8 ... 2^11) vs the brute-force DFT."""
+    """nt = 3 templates on the smallest grid (n = 2^8 ... 2^11) vs the brute-force DFT, and
+    the transform's own read-out against the read-out of the stored series."""
     for n, fs in ((256, 256.0), (2048, 256.0)):
         g = synth.make_grid(fs, n, 20.0)
         psd = synth.make_psd(g)
         xf = synth.noise(g, psd, seed=17 + n)
         tm = [(3.0, 2.5), (2.0, 1.5), (1.2, 1.1)]
         _say(f"tiny mf n={n}")
-        z, sig = rf.mf_ref_snr(ctx, g, _dev(xf, torch.complex128), _dev(psd, torch.float64), tm)
+        xf_d, psd_d = _dev(xf, torch.complex128), _dev(psd, torch.float64)
+        z, sig = rf.mf_ref_snr(ctx, g, xf_d, psd_d, tm)
+        # the read-out in the last transform pass (two 16- or 32-point passes here)
+        # equals the read-out of the stored series, with a threshold some samples cross
+        thr = float(0.5 * z.abs().max().item())
+        a = rf.mf_snr_peaks(ctx, g, xf_d, psd_d, tm, thr)
+        b = rf.snr_peaks(ctx, z, thr)
+        v1, i1 = rf.decode_peaks(a["peaks"])
+        v2, i2 = rf.decode_peaks(b["peaks"])
+        np.testing.assert_array_equal(i1, i2)
+        np.testing.assert_array_equal(v1, v2)
+        assert a["ntrig"] == b["ntrig"] > 0
+        assert sorted(rf.decode_triggers(a["trig"], a["ntrig"])) == sorted(rf.decode_triggers(b["trig"], b["ntrig"]))
         z = z.cpu().numpy()
         for i, t in enumerate(tm):
             zo, no = omf.snr_series_bruteforce(g.fs, g.n, g.f_low, g.f_high, xf, psd, *t)
