@@ -222,7 +222,10 @@ rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const dou
     band_limits(grid, &jlo, &jhi);
     float2* q = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(jhi - jlo + 1)));
     condition_data(ctx, grid, static_cast<const double2*>(xf), psd, q);
-    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    // at most 2^28 / n templates a batch, split evenly (no small last batch)
+    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    const int nbatch = (nt + cap - 1) / cap;
+    const int per = (nt + nbatch - 1) / nbatch;
     float2* zo = static_cast<float2*>(z);
     for (int t0 = 0; t0 < nt; t0 += per) {
       const int cnt = std::min(per, nt - t0);
@@ -272,7 +275,10 @@ rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const d
     po.seg = 0;
     po.nk = nt;
     // templates in batches (two transform scratch buffers of up to 2 GiB each)
-    const int per = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    // at most 2^28 / n templates a batch, split evenly (no small last batch)
+    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    const int nbatch = (nt + cap - 1) / cap;
+    const int per = (nt + nbatch - 1) / nbatch;
     for (int t0 = 0; t0 < nt; t0 += per) {
       const int cnt = std::min(per, nt - t0);
       po.tmpl0 = t0;
