@@ -87,9 +87,35 @@ def grad(theta, x, t):
 
 
 def adam_step(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (step counts from 1); returns new theta, m, v."""
+    """One Adam update (Kingma and Ba, arXiv 1412.6980, Algorithm 1; step counts
+    from 1): exponential moving averages of g and g^2, each divided by its bias
+    factor 1 - beta^step; returns new theta, m, v."""
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def cosine_lr(lr0, k, total):
+    """Learning rate of step k (0-based) of a cosine decay from lr0 to 0 over
+    `total` steps: lr0 (1 + cos(pi k / total)) / 2."""
+    return lr0 * 0.5 * (1.0 + math.cos(math.pi * k / total))
+
+
+def train(theta, x, t, order, lr0):
+    """Training as the surrogate does it: for step k = 0 .. steps-1 the rows
+    order[k] of (x, t) form the batch, the gradient of the mean squared error
+    is taken there, and Adam (moments starting at zero) moves theta with the
+    cosine-decayed rate of step k.  Returns the final theta and the loss of
+    every step (before its update)."""
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    hist = []
+    steps = len(order)
+    for k in range(steps):
+        rows = np.asarray(order[k])
+        L, g = grad(theta, x[rows], t[rows])
+        hist.append(L)
+        theta, m, v = adam_step(theta, g, m, v, k + 1, cosine_lr(lr0, k, steps))
+    return theta, np.array(hist)

@@ -394,6 +394,81 @@ def test_adam_first_step_moves_by_lr():
     np.testing.assert_allclose(new, th - 0.01 * np.sign(g), rtol=1e-4)
 
 
+def test_adam_constant_gradient_every_step():
+    """A constant gradient g makes both bias-corrected moments exact at every
+    step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2, geometric sums), so each
+    step moves theta by lr_t g / (|g| + eps), whatever the step count."""
+    from oracle import mlp
+    g = np.array([0.3, -4.0, 2e-3, -7e-2])
+    th = np.array([1.0, -2.0, 0.5, 0.25])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lrs = (0.01, 0.004, 0.02, 0.001, 0.015, 0.007)
+    for k, lr in enumerate(lrs):
+        th, m, v = mlp.adam_step(th, g, m, v, k + 1, lr)
+        np.testing.assert_allclose(m, (1 - 0.9 ** (k + 1)) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - 0.999 ** (k + 1)) * g * g, rtol=1e-12)
+    expect = np.array([1.0, -2.0, 0.5, 0.25]) - sum(lrs) * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(th, expect, rtol=1e-12, atol=1e-15)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """g_t = (-1)^(t+1) g: the first moment is a geometric sum with ratio -b1,
+    m_t = (-1)^(t+1) (1 - b1)(1 - (-b1)^t) / (1 + b1) g, while v_t = (1 - b2^t) g^2;
+    the step t update is lr m_t / (1 - b1^t) / (|g| + eps)."""
+    from oracle import mlp
+    b1 = 0.9
+    g = np.array([0.5, -1.5])
+    th0 = np.array([0.1, 0.2])
+    th, m, v = th0.copy(), np.zeros(2), np.zeros(2)
+    lr = 0.01
+    for t in range(1, 8):
+        prev = th
+        th, m, v = mlp.adam_step(th, (-1.0) ** (t + 1) * g, m, v, t, lr)
+        mt = (-1.0) ** (t + 1) * (1 - b1) * (1 - (-b1) ** t) / (1 + b1) * g
+        np.testing.assert_allclose(m, mt, rtol=1e-12)
+        np.testing.assert_allclose(prev - th, lr * mt / (1 - b1 ** t) / (np.abs(g) + 1e-8), rtol=1e-10)
+
+
+def test_cosine_schedule_values():
+    """lr0 at the start, lr0 / 2 half way, 0 at the end, falling in between,
+    symmetric about the midpoint: lr(k) + lr(total - k) = lr0."""
+    from oracle import mlp
+    T = 40
+    assert mlp.cosine_lr(3e-3, 0, T) == 3e-3
+    assert mlp.cosine_lr(3e-3, T // 2, T) == pytest.approx(1.5e-3, rel=1e-15)
+    assert mlp.cosine_lr(3e-3, T, T) == pytest.approx(0.0, abs=1e-19)
+    lr = np.array([mlp.cosine_lr(1.0, k, T) for k in range(T + 1)])
+    assert np.all(np.diff(lr) < 0)
+    np.testing.assert_allclose(lr + lr[::-1], 1.0, rtol=1e-14)
+
+
+def test_training_loop_steps():
+    """The training loop: zero rate leaves theta unchanged; the loss history is
+    the loss of each batch before its update; one step equals one Adam step at
+    lr0 on the first batch's gradient."""
+    from oracle import mlp
+    rng = np.random.default_rng(31)
+    theta = rng.standard_normal(mlp.n_params()) * 0.05
+    x = rng.standard_normal((20, 4))
+    t = rng.standard_normal((20, 128)) * 0.2
+    order = rng.integers(0, 20, (3, 6))
+    th0, h0 = mlp.train(theta, x, t, order, 0.0)
+    np.testing.assert_array_equal(th0, theta)
+    assert h0[0] == mlp.loss(theta, x[order[0]], t[order[0]])
+    th1, _ = mlp.train(theta, x, t, order[:1], 1e-3)
+    _, g = mlp.grad(theta, x[order[0]], t[order[0]])
+    np.testing.assert_allclose(th1, theta - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-10, atol=1e-18)
+    # two steps of a two-step schedule: the second runs at lr0 (1 + cos(pi / 2)) / 2 = lr0 / 2
+    th2, h2 = mlp.train(theta, x, t, order[:2], 1e-3)
+    _, g1 = mlp.grad(th1, x[order[1]], t[order[1]])
+    assert h2[1] == mlp.loss(th1, x[order[1]], t[order[1]])
+    m = 0.9 * 0.1 * g + 0.1 * g1
+    v = 0.999 * 0.001 * g * g + 0.001 * g1 * g1
+    step2 = 0.5e-3 * (m / (1 - 0.9 ** 2)) / (np.sqrt(v / (1 - 0.999 ** 2)) + 1e-8)
+    np.testing.assert_allclose(th2, th1 - step2, rtol=1e-9, atol=1e-17)
+
+
 # ---- projection of a kernel set (factored form, not in the paper) ----
 
 def _random_set(rng, k, lo=-30, hi=30, nmin=5, nmax=40):
