@@ -193,9 +193,12 @@ rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr
  * series (as mf_ref_snr) and the reconstructed series of every kernel of group
  * r (as snr_reconstruct with RF_PREC_SPLIT_FP16), reading them out only
  * through the fused peak/threshold read-out -- the series are not stored.  The
- * device work is one captured hipGraph (re-captured when a pointer, cap or thr
- * changes) whose reconstruction is a single persistent launch over all
- * (segment, tile, time block) work items, longest tiles first.  Kernel k of
+ * device work is one captured hipGraph whose reconstruction is a single
+ * persistent launch over all (segment, tile, time block) work items, longest
+ * tiles first.  The graph reads and writes only buffers of the batch: each run
+ * copies the caller's data in before the replay and the read-out out after it,
+ * so new pointers do not re-capture it; a new cap or thr, or new chunk sizes,
+ * do.  Kernel k of
  * group r has global index kbase[r] + k.  The batch borrows psd and the kernel
  * sets' contents are copied (the sets may be freed afterwards); it owns its
  * device buffers (about 24 bytes per sample per (segment, reference)). */
@@ -223,6 +226,9 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
  * RF_E_OVERFLOW when the crossings exceed cap. */
 rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr, rf_peak* peaks,
                        rf_trigger* trig, int64_t cap, int64_t* ntrig);
+/* Host copies (either may be NULL): number of graph captures and of replays
+ * since the batch was created. */
+rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays);
 rf_status rf_batch_free(rf_batch* b);
 
 /* ---- learned kernels: an MLP predicting ratio kernels in an SVD basis ----
@@ -255,6 +261,10 @@ rf_status rf_surrogate_info(const rf_surrogate* s, int32_t* window, int32_t* ran
  * W3 [256][256], b3, W4 [128][256], b4.  set_params also resets Adam state. */
 rf_status rf_surrogate_set_params(rf_ctx* ctx, rf_surrogate* s, const float* theta);
 rf_status rf_surrogate_get_params(rf_ctx* ctx, const rf_surrogate* s, float* theta);
+/* Training rows the surrogate was built with: x device float [npair][4]
+ * (standardised features), t device float [npair][128] (targets); either may
+ * be NULL.  Synchronises. */
+rf_status rf_surrogate_dataset(rf_ctx* ctx, const rf_surrogate* s, float* x, float* t);
 /* Loss (mean squared error over rows x 128 outputs) and its gradient for inputs
  * x (device float [rows][4], standardised) and targets t (device [rows][128]);
  * grad_out: device float [165760].  Synchronises. */

@@ -4,9 +4,12 @@
 // split of every reference series, one persistent split-FP16 reconstruction
 // launch over all (segment, tile, time block) work items with the fused
 // peak/threshold read-out, peak finalisation -- captured once in a hipGraph
-// and replayed.  Work items are ordered longest tile first so the queue ends
-// on short items; the chunk size of each item comes from an autotuner that
-// times the candidate chunk sizes per kernel-length bucket on the device.
+// and replayed.  The graph reads and writes only buffers the batch owns (the
+// caller's data are copied in before a replay, the read-out copied out after
+// it), so a replay does not depend on the caller's pointers.  Work items are
+// ordered longest tile first so the queue ends on short items; the chunk size
+// of each item comes from an autotuner that times the candidate chunk sizes
+// per kernel-length bucket on the device.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -51,13 +54,16 @@ struct rf_batch {
   int nblocks = 0;
   // chunk size per kernel-length bucket (taps)
   int chunk_for_bucket[3] = {512, 512, 512};
-  // captured graph and the arguments it was captured with
+  // buffers the captured graph reads and writes (never the caller's)
+  double2* xf_own = nullptr;           // [nseg][n/2+1]: copy of the caller's data
+  rf_peak* peaks_own = nullptr;        // [nseg][ktotal]
+  rf_trigger* trig_own = nullptr;      // [trig_cap]
+  int64_t trig_cap = 0;
+  // captured graph and the read-out settings it was captured with
   hipGraphExec_t exec = nullptr;
-  const void* g_xf = nullptr;
-  const void* g_trig = nullptr;
-  const void* g_peaks = nullptr;
   int64_t g_cap = -1;
   float g_thr = -1.f;
+  int64_t captures = 0, replays = 0;
 };
 
 namespace rf {
@@ -71,7 +77,7 @@ void free_batch(rf_batch* b) {
   for (void* p : {(void*)b->coef, (void*)b->moment, (void*)b->tiles, (void*)b->items, (void*)b->b16,
                   (void*)b->colscale, (void*)b->slot_kernel, (void*)b->q, (void*)b->zref, (void*)b->zs,
                   (void*)b->maxbits, (void*)b->zinv, (void*)b->packed, (void*)b->counter, (void*)b->gflag,
-                  (void*)b->fa, (void*)b->fb})
+                  (void*)b->fa, (void*)b->fb, (void*)b->xf_own, (void*)b->peaks_own, (void*)b->trig_own})
     if (p) (void)hipFree(p);
   delete b;
 }
@@ -243,6 +249,8 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     // FFT scratch owned by the batch: the captured graph references it
     b->fa = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
     b->fb = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
+    b->xf_own = dev_alloc<double2>(size_t(nseg) * size_t(b->n / 2 + 1), "batch: device allocation failed");
+    b->peaks_own = dev_alloc<rf_peak>(size_t(nseg) * size_t(b->ktotal), "batch: device allocation failed");
     RF_HIP(hipStreamSynchronize(ctx->stream));
     *out = b;
     st = RF_OK;
@@ -375,16 +383,23 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
     RF_CHECK(cap >= 0 && (cap == 0 || trig), "rf_batch_run: bad trigger buffer");
     RF_CHECK(std::isfinite(thr) && thr >= 0, "rf_batch_run: bad threshold");
     RF_CHECK(ctx->stream != nullptr, "rf_batch_run: needs a non-null stream (graph capture)");
-    if (!b->exec || b->g_xf != xf_segs || b->g_trig != trig || b->g_peaks != peaks || b->g_cap != cap ||
-        b->g_thr != thr) {
+    if (!b->exec || b->g_cap != cap || b->g_thr != thr) {
       if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
       }
+      if (cap > b->trig_cap) {
+        RF_HIP(hipStreamSynchronize(ctx->stream));
+        if (b->trig_own) (void)hipFree(b->trig_own);
+        b->trig_own = nullptr;
+        b->trig_cap = 0;
+        b->trig_own = dev_alloc<rf_trigger>(size_t(cap), "batch: device allocation failed");
+        b->trig_cap = cap;
+      }
       hipGraph_t graph = nullptr;
       RF_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
       try {
-        enqueue_run(ctx, b, xf_segs, thr, peaks, trig, cap);
+        enqueue_run(ctx, b, b->xf_own, thr, b->peaks_own, cap > 0 ? b->trig_own : nullptr, cap);
       } catch (...) {
         hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(ctx->stream, &g2);
@@ -395,16 +410,23 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
       hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
-      b->g_xf = xf_segs;
-      b->g_trig = trig;
-      b->g_peaks = peaks;
       b->g_cap = cap;
       b->g_thr = thr;
+      ++b->captures;
     }
-    RF_HIP(hipGraphLaunch(b->exec, ctx->stream));
-    unsigned long long cnt = 0;
     const int64_t np = int64_t(b->nseg) * b->ktotal;
+    RF_HIP(hipMemcpyAsync(b->xf_own, xf_segs, sizeof(double2) * size_t(b->nseg) * size_t(b->n / 2 + 1),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    RF_HIP(hipGraphLaunch(b->exec, ctx->stream));
+    ++b->replays;
+    unsigned long long cnt = 0;
     RF_HIP(hipMemcpyAsync(&cnt, b->packed + np, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+    RF_HIP(hipStreamSynchronize(ctx->stream));
+    RF_HIP(hipMemcpyAsync(peaks, b->peaks_own, sizeof(rf_peak) * size_t(np), hipMemcpyDeviceToDevice, ctx->stream));
+    const int64_t nrec = std::min<int64_t>(int64_t(cnt), cap);
+    if (nrec > 0)
+      RF_HIP(hipMemcpyAsync(trig, b->trig_own, sizeof(rf_trigger) * size_t(nrec), hipMemcpyDeviceToDevice,
+                            ctx->stream));
     RF_HIP(hipStreamSynchronize(ctx->stream));
     *ntrig = int64_t(cnt);
     if (int64_t(cnt) > cap) throw Error{RF_E_OVERFLOW, "rf_batch_run: trigger buffer overflow"};
@@ -415,6 +437,13 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
     ctx->last_error = "rf_batch_run: unexpected exception";
     return RF_E_HIP;
   }
+  return RF_OK;
+}
+
+rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays) {
+  if (!b) return RF_E_INVAL;
+  if (captures) *captures = b->captures;
+  if (replays) *replays = b->replays;
   return RF_OK;
 }
 

@@ -732,6 +732,19 @@ rf_status rf_surrogate_get_params(rf_ctx* ctx, const rf_surrogate* s, float* the
   });
 }
 
+rf_status rf_surrogate_dataset(rf_ctx* ctx, const rf_surrogate* s, float* x, float* t) {
+  if (!ctx || !s || (!x && !t)) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    if (x)
+      RF_HIP(hipMemcpyAsync(x, s->X, sizeof(float) * size_t(s->npair) * mlpdef::kIn, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+    if (t)
+      RF_HIP(hipMemcpyAsync(t, s->T, sizeof(float) * size_t(s->npair) * mlpdef::kOut, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+    RF_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 rf_status rf_surrogate_grad(rf_ctx* ctx, rf_surrogate* s, const float* x, const float* t, int32_t rows,
                             float* loss_host, float* grad_out) {
   if (!ctx || !s) return RF_E_INVAL;

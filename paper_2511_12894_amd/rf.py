@@ -24,9 +24,9 @@ PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "mf_snr_peaks", "ratio_kernel_build",
             "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
-            "rf_batch_autotune", "rf_batch_run", "rf_batch_free", "rf_surrogate_create",
+            "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
-            "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
+            "rf_surrogate_dataset", "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
             "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
             "rf_factored_free", "rf_ols_build", "rf_ols_info", "snr_reconstruct_ols", "rf_ols_free",
             "rf_template_durations", "rf_bank_organise", "rf_surrogate_free")
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.rf_batch_set_chunks.argtypes = [vp, ctypes.POINTER(i32)]
     lib.rf_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p]
     lib.rf_batch_run.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
+    lib.rf_batch_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rf_batch_free.argtypes = [vp]
     lib.rf_surrogate_create.argtypes = [vp, ctypes.POINTER(RfGrid), ctypes.POINTER(RfTmpl), ctypes.POINTER(RfTmpl),
                                         i32, i32, i32, vp, i32, ctypes.POINTER(vp)]
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.rf_surrogate_set_params.argtypes = [vp, vp, vp]
     lib.rf_surrogate_get_params.argtypes = [vp, vp, vp]
+    lib.rf_surrogate_dataset.argtypes = [vp, vp, vp, vp]
     lib.rf_surrogate_grad.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
     lib.rf_surrogate_train.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
     lib.rf_surrogate_predict.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, vp]
@@ -147,6 +149,24 @@ def _tmpl_array(ts):
 
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _require(cond, msg):
+    """Argument check that survives python -O (unlike assert)."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _dev_tensor(t, dtype, numel=None, shape=None, what="tensor"):
+    """A contiguous CUDA tensor of the given dtype and size, else ValueError."""
+    _require(isinstance(t, torch.Tensor), f"{what}: expected a torch tensor")
+    _require(t.dtype == dtype, f"{what}: expected dtype {dtype}, got {t.dtype}")
+    _require(t.is_cuda, f"{what}: must be on a CUDA device")
+    _require(t.is_contiguous(), f"{what}: must be contiguous")
+    if numel is not None:
+        _require(t.numel() == numel, f"{what}: expected {numel} elements, got {t.numel()}")
+    if shape is not None:
+        _require(tuple(t.shape) == tuple(shape), f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
 class Context:
@@ -223,12 +243,13 @@ def mf_ref_snr(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, template
                want_sigma: bool = True):
     """Complex SNR series of each template: z complex64 [nt, n] (device), sigma list."""
     n = int(grid.n)
-    assert xf.dtype == torch.complex128 and xf.is_cuda and xf.numel() == n // 2 + 1 and xf.is_contiguous()
-    assert psd.dtype == torch.float64 and psd.is_cuda and psd.numel() == n // 2 + 1 and psd.is_contiguous()
+    _dev_tensor(xf, torch.complex128, n // 2 + 1, what="xf")
+    _dev_tensor(psd, torch.float64, n // 2 + 1, what="psd")
     nt = len(templates)
     if z is None:
         z = torch.empty((nt, n), dtype=torch.complex64, device=xf.device)
-    assert z.dtype == torch.complex64 and z.is_contiguous() and z.numel() >= nt * n
+    _dev_tensor(z, torch.complex64, what="z")
+    _require(z.numel() >= nt * n, "z: needs room for nt * n samples")
     g = to_grid(grid)
     sig = (ctypes.c_double * nt)() if want_sigma else None
     ctx.check(ctx.lib.mf_ref_snr(ctx.h, ctypes.byref(g), _ptr(xf), _ptr(psd), _tmpl_array(templates),
@@ -241,8 +262,8 @@ def mf_snr_peaks(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, templa
     """Direct matched filtering of each template with the read-out only (the
     series are not stored): peaks tensor of RfPeak bytes, triggers, count."""
     n = int(grid.n)
-    assert xf.dtype == torch.complex128 and xf.is_cuda and xf.numel() == n // 2 + 1 and xf.is_contiguous()
-    assert psd.dtype == torch.float64 and psd.is_cuda and psd.numel() == n // 2 + 1 and psd.is_contiguous()
+    _dev_tensor(xf, torch.complex128, n // 2 + 1, what="xf")
+    _dev_tensor(psd, torch.float64, n // 2 + 1, what="psd")
     nt = len(templates)
     peaks = torch.empty((nt, 2), dtype=torch.int32, device=xf.device)
     trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=xf.device)
@@ -258,6 +279,7 @@ def mf_snr_peaks(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, templa
 
 def ratio_kernel_build(ctx: Context, grid, psd: torch.Tensor, ref, nbrs, thr: float = 1e-3,
                        unit: int = RF_THR_PER_SECOND, n_build: int = 0) -> Kernels:
+    _dev_tensor(psd, torch.float64, int(grid.n) // 2 + 1, what="psd")
     g = to_grid(grid)
     h = ctypes.c_void_p()
     ctx.check(ctx.lib.ratio_kernel_build(ctx.h, ctypes.byref(g), _ptr(psd), RfTmpl(*map(float, ref)),
@@ -271,10 +293,12 @@ def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: s
                     trig_cap: int = 4096):
     """Reconstructed series [nk, n] (if store) and, with fused_thr, the fused
     read-out (peaks tensor of RfPeak bytes, triggers, count)."""
+    _dev_tensor(z_ref, torch.complex64, what="z_ref")
     n = z_ref.numel()
-    assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
     if store and z_out is None:
         z_out = torch.empty((kernels.nk, n), dtype=torch.complex64, device=z_ref.device)
+    if store:
+        _dev_tensor(z_out, torch.complex64, shape=(kernels.nk, n), what="z_out")
     fused = None
     peaks = trig = None
     cnt = ctypes.c_int64(0)
@@ -296,7 +320,8 @@ def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: s
 
 def snr_peaks(ctx: Context, z: torch.Tensor, thr: float, trig_cap: int = 4096):
     """Peaks and threshold crossings of series z [nt, n] (complex64, device)."""
-    assert z.dtype == torch.complex64 and z.is_cuda and z.is_contiguous() and z.dim() == 2
+    _dev_tensor(z, torch.complex64, what="z")
+    _require(z.dim() == 2, "z: expected [nt, n]")
     nt, n = z.shape
     peaks = torch.empty((nt, 2), dtype=torch.int32, device=z.device)
     trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z.device)
@@ -357,8 +382,7 @@ class Batch:
             raise RfError(st, "rf_batch_set_chunks failed")
 
     def _inputs_ready(self, xf_segs):
-        assert xf_segs.dtype == torch.complex128 and xf_segs.is_cuda and xf_segs.is_contiguous()
-        assert xf_segs.shape == (self.nseg, self.n // 2 + 1)
+        _dev_tensor(xf_segs, torch.complex128, shape=(self.nseg, self.n // 2 + 1), what="xf_segs")
         self.ctx.stream.wait_stream(torch.cuda.current_stream(xf_segs.device))
 
     def autotune(self, xf_segs: torch.Tensor, cache_path: str | None = None):
@@ -374,12 +398,21 @@ class Batch:
             peaks = torch.empty((self.nseg, self.ktotal, 2), dtype=torch.int32, device=dev)
         if trig is None:
             trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=dev)
+        _dev_tensor(peaks, torch.int32, numel=self.nseg * self.ktotal * 2, what="peaks")
+        _dev_tensor(trig, torch.int32, what="trig")
+        _require(trig.numel() >= 5 * trig_cap, "trig: needs room for trig_cap records")
         cnt = ctypes.c_int64(0)
         st = self.ctx.lib.rf_batch_run(self.ctx.h, self.h, _ptr(xf_segs), ctypes.c_float(thr), _ptr(peaks),
                                        _ptr(trig), int(trig_cap), ctypes.byref(cnt))
         if st not in (RF_OK, RF_E_OVERFLOW):
             self.ctx.check(st)
         return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+
+    def graph_stats(self):
+        """(captures, replays) of the batch's graph since creation."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.rf_batch_graph_stats(self.h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     def free(self):
         if getattr(self, "h", None):
@@ -404,8 +437,9 @@ class Surrogate:
     def __init__(self, ctx: Context, grid, refs, nbrs, window: int, omega: torch.Tensor, rank: int = 64):
         self.ctx = ctx
         self.grid = grid
-        assert omega.dtype == torch.float64 and omega.is_cuda and omega.is_contiguous()
-        assert omega.shape[0] == len(refs) == len(nbrs)
+        _dev_tensor(omega, torch.float64, what="omega")
+        _require(omega.dim() == 2 and omega.shape[0] == len(refs) == len(nbrs),
+                 "omega: expected [npair, nomega] with one row per training pair")
         g = to_grid(grid)
         h = ctypes.c_void_p()
         torch.cuda.synchronize()
@@ -414,6 +448,7 @@ class Surrogate:
                                               ctypes.byref(h)))
         self.h = h
         self.rank = rank
+        self.npair = len(refs)
 
     def info(self):
         w, r, kr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -426,7 +461,7 @@ class Surrogate:
                     out_scale=sc.value, steps=st.value)
 
     def set_params(self, theta: torch.Tensor):
-        assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == N_MLP_PARAMS
+        _dev_tensor(theta, torch.float32, N_MLP_PARAMS, what="theta")
         torch.cuda.synchronize()
         self.ctx.check(self.ctx.lib.rf_surrogate_set_params(self.ctx.h, self.h, _ptr(theta)))
 
@@ -436,8 +471,20 @@ class Surrogate:
         self.ctx.check(self.ctx.lib.rf_surrogate_get_params(self.ctx.h, self.h, _ptr(out)))
         return out
 
+    def dataset(self):
+        """(x [npair, 4], t [npair, 128]) float32 device copies of the training rows."""
+        dev = f"cuda:{self.ctx.device}"
+        x = torch.empty((self.npair, 4), dtype=torch.float32, device=dev)
+        t = torch.empty((self.npair, 2 * self.rank), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_dataset(self.ctx.h, self.h, _ptr(x), _ptr(t)))
+        return x, t
+
     def grad(self, x: torch.Tensor, t: torch.Tensor):
+        _dev_tensor(x, torch.float32, what="x")
+        _require(x.dim() == 2 and x.shape[1] == 4, "x: expected [rows, 4]")
         rows = x.shape[0]
+        _dev_tensor(t, torch.float32, shape=(rows, 2 * self.rank), what="t")
         g = torch.empty(N_MLP_PARAMS, dtype=torch.float32, device=x.device)
         loss = ctypes.c_float()
         torch.cuda.synchronize()
@@ -446,7 +493,12 @@ class Surrogate:
         return loss.value, g
 
     def train(self, order: torch.Tensor, lr: float):
+        _dev_tensor(order, torch.int32, what="order")
+        _require(order.dim() == 2, "order: expected [steps, batch]")
         steps, batch = order.shape
+        _require(steps >= 1 and batch >= 1, "order: empty")
+        lo, hi = int(order.min().item()), int(order.max().item())
+        _require(0 <= lo and hi < self.npair, f"order: rows must lie in [0, {self.npair})")
         hist = (ctypes.c_float * steps)()
         torch.cuda.synchronize()
         self.ctx.check(self.ctx.lib.rf_surrogate_train(self.ctx.h, self.h, _ptr(order), steps, batch, float(lr), hist))
@@ -468,6 +520,13 @@ class Surrogate:
         """Kernel set from the surrogate (network coefficients unless `coeffs`);
         check = (grid, xf, psd) of a check segment."""
         nk = len(nbrs)
+        _dev_tensor(psd, torch.float64, int(grid.n) // 2 + 1, what="psd")
+        if coeffs is not None:
+            _dev_tensor(coeffs, torch.complex128, shape=(nk, self.rank), what="coeffs")
+        if check:
+            nc = int(check[0].n)
+            _dev_tensor(check[1], torch.complex128, nc // 2 + 1, what="check xf")
+            _dev_tensor(check[2], torch.float64, nc // 2 + 1, what="check psd")
         g = to_grid(grid)
         fb = (ctypes.c_int32 * nk)()
         err = (ctypes.c_float * nk)()
@@ -516,10 +575,12 @@ class Factored:
 
     def reconstruct(self, z_ref: torch.Tensor, z_out=None, store: bool = True, fused_thr: float | None = None,
                     trig_cap: int = 4096, prec: str = "split16"):
+        _dev_tensor(z_ref, torch.complex64, what="z_ref")
         n = z_ref.numel()
-        assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
         if store and z_out is None:
             z_out = torch.empty((self.nk, n), dtype=torch.complex64, device=z_ref.device)
+        if store:
+            _dev_tensor(z_out, torch.complex64, shape=(self.nk, n), what="z_out")
         fused = None
         peaks = trig = None
         cnt = ctypes.c_int64(0)
@@ -573,10 +634,12 @@ class Ols:
 
     def reconstruct(self, z_ref: torch.Tensor, z_out=None, store: bool = True, fused_thr: float | None = None,
                     trig_cap: int = 4096):
+        _dev_tensor(z_ref, torch.complex64, what="z_ref")
         n = z_ref.numel()
-        assert z_ref.dtype == torch.complex64 and z_ref.is_cuda and z_ref.is_contiguous()
         if store and z_out is None:
             z_out = torch.empty((self.nk, n), dtype=torch.complex64, device=z_ref.device)
+        if store:
+            _dev_tensor(z_out, torch.complex64, shape=(self.nk, n), what="z_out")
         fused = None
         peaks = trig = None
         cnt = ctypes.c_int64(0)

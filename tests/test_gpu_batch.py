@@ -108,12 +108,21 @@ def test_batch_matches_per_call_exactly(rf, work, setup, chunk):
 
 
 def test_batch_graph_replay_and_recapture(rf, work, setup):
+    """New output and input buffers replay the captured graph (it holds only
+    the batch's own buffers); a new threshold re-captures it."""
     b = setup["batch"]
     a = _decode(rf, b.run(setup["xf"], 6.0), 2, b.ktotal)
-    c = _decode(rf, b.run(setup["xf"], 6.0), 2, b.ktotal)       # replay
-    np.testing.assert_array_equal(a[0], c[0])
-    assert a[1] == c[1]
+    cap0, rep0 = b.graph_stats()
+    xf2 = setup["xf"].clone()                                      # another input pointer
+    outs = [b.run(xf2 if i % 2 else setup["xf"], 6.0) for i in range(3)]   # fresh outputs each time
+    cap1, rep1 = b.graph_stats()
+    assert cap1 == cap0 and rep1 == rep0 + 3
+    for o in outs:
+        c = _decode(rf, o, 2, b.ktotal)
+        np.testing.assert_array_equal(a[0], c[0])
+        assert a[1] == c[1]
     d = _decode(rf, b.run(setup["xf"], 7.5), 2, b.ktotal)       # new threshold: re-capture
+    assert b.graph_stats()[0] == cap1 + 1
     np.testing.assert_array_equal(a[0], d[0])
     assert d[1] == set(t for t in a[1] if t[3] > 7.5)
 

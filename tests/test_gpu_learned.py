@@ -88,6 +88,46 @@ def test_gradient_matches_oracle(rf, st, rows):
             k += size
 
 
+def test_training_steps_match_oracle(rf, st):
+    """Six GPU training steps (batch gather, forward, backward, Adam with bias
+    correction and the cosine rate, replayed from one captured graph) against
+    the FP64 oracle's training loop from the same parameters, training rows and
+    batch order.  A component whose oracle gradient is below 1e-3 of the step's
+    rms gradient at some step may take its Adam step with the other sign in
+    FP32 (the update is about lr sign(g)); it is held only to the bound of two
+    full steps, every other component to 0.5 % of one step."""
+    S = st["S"]
+    steps, batch, lr = 6, 64, 1e-3
+    order = np.random.default_rng(6200).integers(0, NPAIR, (steps, batch)).astype(np.int32)
+    with torch.cuda.stream(st["stream"]):
+        S.set_params(torch.from_numpy(st["theta0"]).cuda())
+        x_d, t_d = S.dataset()
+        hist = np.array(S.train(torch.from_numpy(order).cuda(), lr))
+        th_gpu = S.get_params().cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    x = x_d.cpu().numpy().astype(np.float64)
+    t = t_d.cpu().numpy().astype(np.float64)
+    th0 = st["theta0"].astype(np.float64)
+    th_ref, h_ref = omlp.train(th0, x, t, order, lr)
+    # the oracle's gradients along its own path, to find sign-ambiguous components
+    th, m, v = th0.copy(), np.zeros_like(th0), np.zeros_like(th0)
+    amb = np.zeros(th0.size, dtype=bool)
+    for k in range(steps):
+        _, g = omlp.grad(th, x[order[k]], t[order[k]])
+        amb |= np.abs(g) < 1e-3 * np.sqrt(np.mean(g * g))
+        th, m, v = omlp.adam_step(th, g, m, v, k + 1, omlp.cosine_lr(lr, k, steps))
+    np.testing.assert_array_equal(th, th_ref)
+    d = np.abs(th_gpu - th_ref)
+    _say(f"training steps: loss {hist[0]:.5e} -> {hist[-1]:.5e} (oracle {h_ref[0]:.5e} -> {h_ref[-1]:.5e}); "
+         f"max |dtheta| / lr = {d[~amb].max() / lr:.2e} ({(~amb).sum()} components), "
+         f"{amb.sum()} sign-ambiguous with max {d[amb].max() / lr if amb.any() else 0:.2e}")
+    np.testing.assert_allclose(hist, h_ref, rtol=2e-5)
+    assert amb.mean() <= 0.02
+    assert d[~amb].max() <= 5e-3 * lr
+    assert d.max() <= 2 * lr * steps
+    assert np.abs(th_ref - th0).max() >= 0.5 * lr        # the steps moved the parameters
+
+
 def test_basis_spectrum(rf, st):
     inf = st["S"].info()
     sv = np.array(inf["svals"])
