@@ -30,10 +30,12 @@
 // v_mfma_f32_32x32x16_f16, FP32 accumulation).  In the split form the second
 // time block's Hankel fragment at step s is the first block's fragment at step
 // s + 2, so one LDS fragment load per plane and step serves both blocks.  The
-// split form takes the two correction products only in the 1024-tap blocks of
+// split form takes the two correction products only in the 512-tap blocks of
 // a tile where some kernel has a tap of at least half an FP16 unit after its
 // scale (the kernels are a narrow peak with a long low tail; elsewhere hi*hi
-// alone is within 1e-6), in a second pass over those blocks.
+// alone is within 1e-6), in a second pass over those blocks; its FP32 partial
+// sums are folded into FP64 every 8 steps only in the 1024-tap blocks that
+// hold a kernel's largest taps, and every 32 steps elsewhere.
 //
 // Optional fused read-out: instead of (or besides) storing the series, the
 // epilogue folds every output into the per-kernel peak (|z|^2 compared in FP32,

@@ -1,7 +1,11 @@
 // Host-only eigen-decomposition of a real symmetric matrix (FP64): Householder
 // reduction to tridiagonal form followed by the implicit-shift QL iteration
 // (Golub & Van Loan, Matrix Computations, secs. 8.3.1 and 8.3.3), with the
-// orthogonal transforms accumulated.  Used for the Gram matrix of a kernel set
+// orthogonal transforms accumulated.  The QL loop takes its steps in the order
+// of the published EISPACK routine imtql2 (Bowdler, Martin, Reinsch and
+// Wilkinson, Numer. Math. 12, 1968; also "tqli" in Numerical Recipes): the
+// shift from the leading 2x2 block, the chase of rotations from the bottom of
+// the unreduced block upwards, and the deflation when a rotation radius is 0.  Used for the Gram matrix of a kernel set
 // (a few hundred rows), where O(n^3) host work is negligible next to the GPU
 // build of the kernels.
 #pragma once
