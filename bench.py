@@ -1,17 +1,24 @@
 """Benchmark of the ratio-filter hot path on one MI355X.
 
-Workload: single reference, realistic -- 512 s at 4096 Hz (n = 2^21),
-f_low = 20 Hz, reference 1.6+1.2 Msun with 256 lattice neighbours, coloured
-Gaussian noise plus four injections (synthetic, seeded).
+Headline workload: batched uneven -- 8 data segments of 256 s at 4096 Hz
+(2^20 samples each), f_low = 25 Hz, 64 references with m1, m2 ~ U[1, 3] Msun,
+each with floor(exp U[ln 32, ln 512]) lattice neighbours (10,136 kernels in
+all), coloured Gaussian noise plus one injection per segment (synthetic,
+seeded).  The largest configuration that fits one GPU.
 
-One step = the method's per-segment work for one reference group:
-  reference matched filter (FP64 TaylorF2 spectrum + FP32 FFT) and the
-  reconstruction of all 256 neighbour series (split-FP16 MFMA) with the fused
-  peak / threshold read-out, series stored to HBM.
-value = produced template-SNR samples per second, (1 + 256) * n / step time.
-Kernel build is timed separately (it is done once and stored), and so are
-the plain FP32 reconstruction and direct FFT matched filtering of the same
-257 templates (the comparator).
+One step = the method's whole per-batch work: the reference matched filter of
+every (segment, reference) (FP64 TaylorF2 spectrum + FP32 FFT), and the
+split-FP16 reconstruction of every neighbour series of every segment in one
+persistent launch with the fused peak / threshold read-out (|z| > 6), captured
+in hipGraphs and replayed.  value = produced template-SNR samples per second,
+(kernels + references) * n * segments / step time.  Kernel build is timed
+separately (it is done once and stored).
+
+Beside it (under "extra"): the single-reference realistic workload (512 s,
+256 neighbours) with the plain FP32 path, direct FFT matched filtering of the
+same templates, the factored and overlap-save forms, bank organisation, the
+reduced batched launch against its call loop, the learned kernels, and the
+next-generation-detector shape (2048 s, 4 x 1024 templates).
 """
 from __future__ import annotations
 
@@ -32,7 +39,8 @@ from paper_2511_12894_amd import rf, synth  # noqa: E402
 
 METRIC = "reconstructed template-SNR samples/s vs direct FFT MF at ≤2e-4 err; %roofline"
 PEAK_FP16_TFLOPS = 2500.0
-PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_TFLOPS = 157.3          # FP32 matrix cores (v_mfma_f32_32x32x2_f32)
+PEAK_FP32_VECTOR_TFLOPS = 78.6    # FP32 vector ALU without packed-FP32 instructions (the build disables them)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -56,18 +64,103 @@ def timed(fn, steps, warmup, stream):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
-def counter_traffic():
-    """Calibrated HBM bytes per launch of the split-FP16 kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source changed since."""
+def counter_traffic(name):
+    """Calibrated HBM bytes per launch of a kernel from the committed rocprofv3
+    counter summary profiles/<name>_counters.json, or None when any source the
+    kernel is built from (the files listed there, headers included) changed
+    since the counters were taken."""
     import hashlib
     try:
-        d = json.load(open(os.path.join(ROOT, "profiles", "k_recon_f16_counters.json")))
-        src = open(os.path.join(ROOT, d["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
-        return None
-    if hashlib.sha256(src).hexdigest() != d.get("source_sha256"):
+        d = json.load(open(os.path.join(ROOT, "profiles", f"{name}_counters.json")))
+        for rel, digest in d["sources_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != digest:
+                return None
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
     return float(d["traffic_bytes_per_dispatch"])
+
+
+def host_cpu():
+    """(model name, usable cores) of the host this runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def _oracle_group(args):
+    """Oracle work of one reference group on one segment: the reference's
+    matched filter and the FFT-based reconstruction of the given neighbours
+    (kernels built beforehand, untimed).  Returns the seconds it took."""
+    from oracle import mf as omf
+    from oracle import ratio as orat
+    g, xf, psd, ref, kern = args
+    t0 = time.perf_counter()
+    zr, nr = omf.grid_snr_series(g, xf, psd, *ref)
+    for m_lo, taps, scale in kern:
+        orat.reconstruct(zr, m_lo, taps, nr * scale)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_batched(wb, n_groups_1=2, per_group=6, seed=77):
+    """The FP64 oracle on the host on a seeded subset of the batched workload:
+    reference groups of segment 0 (reference matched filter + FFT-based
+    reconstruction of `per_group` seeded neighbours each, full 2^20-sample
+    series).  Single core: n_groups_1 groups in this process; all cores: one
+    group per usable core in a process pool.  Rates are extrapolated to the
+    whole workload as template-samples per second (kernel builds untimed)."""
+    import multiprocessing as mp
+    from oracle import mf as omf
+    from oracle import ratio as orat
+    g = wb["grid"]
+    psd = wb["psd"]
+    xf = wb["segments"][0]
+    model, cores = host_cpu()
+    ncores = max(1, min(cores, 16))
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(wb["refs"]), size=max(n_groups_1, ncores), replace=ncores > len(wb["refs"]))
+    tasks = []
+    for r in pick:
+        ref = wb["refs"][int(r)]
+        grp = wb["groups"][int(r)]
+        sel = rng.choice(len(grp), size=min(per_group, len(grp)), replace=False)
+        kern = []
+        for i in sel:
+            nb = grp[int(i)]
+            kb = orat.build_kernel(g, ref, nb)
+            nk = omf.norm(g.fs, g.n, g.f_low, g.f_high, psd, omf.template_spectrum(g.fs, g.n, *nb))
+            kern.append((kb["m_lo"], kb["taps"], 1.0 / nk))
+        tasks.append((g, xf, psd, ref, kern))
+    t0 = time.perf_counter()
+    for t in tasks[:n_groups_1]:
+        _oracle_group(t)
+    t1 = time.perf_counter() - t0
+    tmpl1 = sum(1 + len(t[4]) for t in tasks[:n_groups_1])
+    single = tmpl1 * g.n / t1
+    with mp.get_context("fork").Pool(ncores) as pool:
+        pool.map(_oracle_group, tasks[:1])                 # start the workers
+        t0 = time.perf_counter()
+        pool.map(_oracle_group, tasks[:ncores], chunksize=1)
+        tn = time.perf_counter() - t0
+    tmpln = sum(1 + len(t[4]) for t in tasks[:ncores])
+    allc = tmpln * g.n / tn
+    return dict(value=allc, unit="template-samples/s", cores=ncores, kind="oracle",
+                sample=f"segment 0 of the batched workload: {ncores} seeded reference groups, each the reference "
+                       f"matched filter + FFT reconstruction of {per_group} seeded neighbours (full 2^20-sample "
+                       f"series), numpy FP64, one group per core in a process pool ({tn:.2f} s); "
+                       f"extrapolated to the workload as samples/s",
+                extrapolated=True, cpu_model=model, cores_usable=cores,
+                single_core=dict(value=single, templates=tmpl1, seconds=t1), all_core_templates=tmpln,
+                all_core_seconds=tn)
 
 
 def cpu_baseline(w, n_nbr_sample, n_cmp=12):
@@ -112,45 +205,110 @@ def cpu_baseline(w, n_nbr_sample, n_cmp=12):
                                           "kernel, reference filter shared by the 257-template group"))
 
 
-def batched_leg(dev, full=False):
-    """Batched uneven workload, one persistent split-FP16 launch in a captured
-    graph, against the per-(segment, reference) call loop on the same data.
-    Reduced (default): 4 segments of 32 s at 1024 Hz, 8 references with 8..96
-    lattice neighbours (log-uniform), autotuned chunks.  Full: 8 segments of
-    256 s at 4096 Hz, 64 references with 32..512 neighbours, chunks of 512 /
-    1024 / 1024 taps per length bucket (the autotuner's trial launches would
-    take minutes at this size)."""
-    if full:
-        wb = synth.workload_batched()
-    else:
-        wb = synth.workload_batched(n_seg=4, n_ref=8, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
-                                    nbr_range=(8, 96))
+def headline_leg(dev, steps, warmup, cache_path=None):
+    """The headline step at the batched workload's full shape (8 x 256 s at
+    4096 Hz, 64 references, 10,136 kernels): one rf_batch_run per step, timed
+    over exactly `steps` runs after `warmup`, with the reconstruction graph's
+    duration (persistent launch + read-out) from the library's HIP events on
+    the batch's stream, every step."""
+    log("bench: generating the batched workload (8 x 256 s, 64 references)")
+    wb = synth.workload_batched()
     g = wb["grid"]
+    nseg = len(wb["segments"])
     stream = torch.cuda.Stream(dev)
     ctx = rf.Context(0, stream)
     psd = torch.from_numpy(wb["psd"]).to(dev)
     xf = torch.from_numpy(np.stack(wb["segments"])).to(dev)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
-        ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
-        batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=len(wb["segments"]))
-        if full:
-            batch.set_chunks([512, 1024, 1024])
-            chunks = batch.info()["chunks"]
-        else:
-            chunks = batch.autotune(xf)
-        sum_l = sum(sum(k.info()["len"]) for k in ksets)
-        batch.run(xf, 6.0, trig_cap=1 << 20)
-        stream.synchronize()
         t0 = time.perf_counter()
-        reps = 1 if full else 3
+        ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
+        stream.synchronize()
+        t_build = time.perf_counter() - t0
+        batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=nseg)
+        t0 = time.perf_counter()
+        chunks = batch.autotune(xf, cache_path)
+        t_tune = time.perf_counter() - t0
+        lens = np.concatenate([k.info()["len"] for k in ksets])
+        sum_l = int(lens.sum())
+        corr = [k.split_steps(1024) for k in ksets]
+        corr_steps, all_steps = sum(c for c, _ in corr), sum(a for _, a in corr)
+        ktot = batch.ktotal
+        peaks = torch.empty((nseg, ktot, 2), dtype=torch.int32, device=dev)
+        trig = torch.empty((1 << 20, 5), dtype=torch.int32, device=dev)
+        rec = []
+
+        def step():
+            out = batch.run(xf, 6.0, trig_cap=1 << 20, peaks=peaks, trig=trig)
+            rec.append(batch.last_recon_ms())
+            return out
+
+        log(f"bench: headline: {ktot} kernels ({lens.min()}..{lens.max()} taps), chunks {chunks}; "
+            f"{warmup} warm-up + {steps} timed steps")
+        for _ in range(warmup):
+            step()
+        cap0, rep0 = batch.graph_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            last = step()
+            log(f"bench: headline step {i + 1}/{steps}: reconstruction {rec[-1]:.1f} ms")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        cap1, rep1 = batch.graph_stats()
+    vals, idx = rf.decode_peaks(peaks.view(nseg * ktot, 2))
+    trig_list = rf.decode_triggers(trig, last["ntrig"])
+    # each segment's injection recovered by its template's series at the injection time
+    found = 0
+    for (s_, m1, m2, snr, t0_, phi) in wb["injections"]:
+        found += any(t[1] == s_ and abs(t[2] - int(round(t0_ * g.fs))) <= 8 for t in trig_list)
+    res = dict(wb=wb, grid=g, nseg=nseg, ktot=ktot, nref=len(wb["refs"]), lens=lens, sum_l=sum_l,
+               corr_frac=corr_steps / max(all_steps, 1), exec_taps=all_steps * 16 * 32, chunks=chunks,
+               wall_ms=wall, recon_ms=rec[-steps:], build_s=t_build, tune_s=t_tune,
+               captures_in_timed=cap1 - cap0, replays_in_timed=rep1 - rep0, ntrig=last["ntrig"],
+               peak_max=float(vals.max()), injections_found=found)
+    batch.free()
+    for k in ksets:
+        k.free()
+    ctx.close()
+    del peaks, trig, xf
+    return res
+
+
+def batched_leg(dev):
+    """Reduced batched uneven workload (4 segments of 32 s at 1024 Hz, 8
+    references with 8..96 lattice neighbours, autotuned chunks): one persistent
+    split-FP16 launch in captured graphs, replays only, against the
+    per-(segment, reference) call loop on the same data."""
+    wb = synth.workload_batched(n_seg=4, n_ref=8, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
+                                nbr_range=(8, 96))
+    g = wb["grid"]
+    stream = torch.cuda.Stream(dev)
+    ctx = rf.Context(0, stream)
+    psd = torch.from_numpy(wb["psd"]).to(dev)
+    xf = torch.from_numpy(np.stack(wb["segments"])).to(dev)
+    nseg = len(wb["segments"])
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
+        batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=nseg)
+        chunks = batch.autotune(xf)
+        sum_l = sum(sum(k.info()["len"]) for k in ksets)
+        peaks = torch.empty((nseg, batch.ktotal, 2), dtype=torch.int32, device=dev)
+        trig = torch.empty((1 << 20, 5), dtype=torch.int32, device=dev)
+        batch.run(xf, 6.0, trig_cap=1 << 20, peaks=peaks, trig=trig)          # capture
+        stream.synchronize()
+        cap0, _ = batch.graph_stats()
+        reps = 5
+        t0 = time.perf_counter()
         for _ in range(reps):
-            out = batch.run(xf, 6.0, trig_cap=1 << 20)
+            out = batch.run(xf, 6.0, trig_cap=1 << 20, peaks=peaks, trig=trig)
         t_batch = (time.perf_counter() - t0) / reps
+        cap1, _ = batch.graph_stats()
         z = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
 
         def loop():
-            for s_ in range(len(wb["segments"])):
+            for s_ in range(nseg):
                 for r, K in enumerate(ksets):
                     rf.mf_ref_snr(ctx, g, xf[s_].contiguous(), psd, [wb["refs"][r]], z=z, want_sigma=False)
                     rf.snr_reconstruct(ctx, K, z[0], prec="split16", store=False, fused_thr=6.0)
@@ -160,13 +318,13 @@ def batched_leg(dev, full=False):
         loop()
         stream.synchronize()
         t_loop = time.perf_counter() - t0
-    nseg = len(wb["segments"])
     ktot = batch.ktotal
     flops = 4.0 * g.n * sum_l * nseg
     samples = (ktot + len(wb["refs"])) * g.n * nseg
-    res = dict(workload=wb["name"] + ("" if full else "-reduced"), segments=nseg, references=len(wb["refs"]),
+    res = dict(workload=wb["name"] + "-reduced", segments=nseg, references=len(wb["refs"]),
                kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks, sum_taps=sum_l,
                batch_ms=t_batch * 1e3, loop_ms=t_loop * 1e3, speedup=t_loop / t_batch,
+               graph_captures_while_timed=cap1 - cap0,
                value=samples / t_batch, unit="template-samples/s",
                frac_fp16_peak=flops / t_batch / 1e12 / PEAK_FP16_TFLOPS, ntrig=out["ntrig"])
     batch.free()
@@ -267,7 +425,9 @@ def ols_leg(dev, ctx, w, psd, xf, K, steps):
                spectra_bytes=info["spectra_bytes"], build_s=t_build, step_ms=ms, recon_ms=rms,
                value=(1 + len(nbrs)) * n / (ms * 1e-3), unit="template-samples/s", err_vs_direct_mf=err,
                ntrig=last["ntrig"], fft_mac_flops=flops,
-               vector_fp32_frac=flops / (rms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS)
+               # against the FP32 vector peak without packed-FP32 instructions (switched off in the build)
+               vector_fp32_frac=flops / (rms * 1e-3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+               vector_fp32_peak_tflops=PEAK_FP32_VECTOR_TFLOPS)
     O.free()
     return res
 
@@ -576,36 +736,11 @@ def _learned(dev, ctx, stream, w, psd, xf, K_exact, build_s, steps):
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-nbrs", type=int, default=24)
-    ap.add_argument("--only", default="",
-                    help="comma list of legs to run: step,fp32,direct,factored,ols,bank,batched,learned "
-                         "(default: all of them), sweep, stress and batched_full (only when named)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run one 256 MiB device copy first (calibrates HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
-        sys.exit(2)
-    legs = set(args.only.split(",")) if args.only else {"step", "fp32", "direct", "factored", "ols", "bank",
-                                                        "batched", "learned"}
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
+def c2_legs(dev, args, legs):
+    """The single-reference realistic workload (512 s at 4096 Hz, n = 2^21,
+    reference 1.6+1.2 with 256 lattice neighbours) and the legs that use it."""
     stream = torch.cuda.current_stream(dev)
-
-    if args.copy_probe:
-        a = torch.ones(1 << 26, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    log("bench: generating the synthetic workload")
+    log("bench: generating the realistic workload (512 s, 256 neighbours)")
     w = synth.workload_realistic()
     g = w["grid"]
     n = g.n
@@ -615,7 +750,6 @@ def main():
     ctx = rf.Context(0, stream)
 
     # ---- kernel build (timed separately; stored once in the method)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     K = rf.ratio_kernel_build(ctx, g, psd, w["ref"], nbrs)
     torch.cuda.synchronize()
@@ -693,92 +827,146 @@ def main():
     if "bank" in legs:
         log("bench: bank organisation and storage")
         res["bank"] = bank_leg(dev, ctx, w, psd)
-    if "stress" in legs:
-        log("bench: next-generation-detector shape (4 x 1024 templates, 2^23 samples)")
-        res["stress"] = stress_leg(dev, ctx)
-    if "sweep" in legs:
-        log("bench: SNR loss against kernel length")
-        res["sweep"] = sweep_leg(dev, ctx)
-    if "batched" in legs:
-        log("bench: batched uneven workload")
-        res["batched"] = batched_leg(dev)
-    if "batched_full" in legs:
-        log("bench: batched uneven workload at full size")
-        res["batched_full"] = batched_leg(dev, full=True)
     if "learned" in legs:
         log("bench: learned kernels (training, inference, check and fallback)")
         res["learned"] = learned_leg(dev, w, psd, xf, K, build_s, args.steps)
     torch.cuda.synchronize()
 
-    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
-           "data": "synthetic"}
     samples = (1 + len(nbrs)) * n
+    out = {"workload": w["name"], "n": n, "fs": g.fs, "f_low": g.f_low, "f_high": g.f_high,
+           "neighbours": len(nbrs), "threshold_per_s": 1e-3, "kernel_taps_min": int(lens.min()),
+           "kernel_taps_max": int(lens.max()), "kernel_taps_sum": sum_l, "kernel_build_s": build_s}
     if "step" in res:
         ms = res["step"]["wall_ms"] / args.steps
-        out["value"] = samples / (ms * 1e-3)
-        out["unit"] = "template-samples/s"
-        out["ms_per_step"] = ms
-        alg_flops = 4.0 * n * sum_l                    # complex x real MAC per kept tap and sample
         t_rec = res["step"]["recon_ms"] * 1e-3
-        ach = alg_flops / t_rec / 1e12
-        out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / PEAK_FP16_TFLOPS, "traffic": counter_traffic(),
-                           "kernel": "k_recon_f16 (split-FP16 reconstruction)",
-                           "executed_over_useful_taps": exec_taps / sum_l,
-                           "correction_step_frac": corr_frac,
-                           "executed_frac_of_peak": (1 + 2 * corr_frac) * 4.0 * n * exec_taps / t_rec / 1e12
-                           / PEAK_FP16_TFLOPS}
-    out["config"] = {"workload": w["name"], "n": n, "fs": g.fs, "f_low": g.f_low, "f_high": g.f_high,
-                     "neighbours": len(nbrs), "threshold_per_s": 1e-3, "kernel_taps_min": int(lens.min()),
-                     "kernel_taps_max": int(lens.max()), "kernel_taps_sum": sum_l,
-                     "precision": "split fp16 hi/lo, 3 products, fp32 accumulation"}
-    extra = {"kernel_build_s": build_s}
-    if "step" in res:
-        extra["recon_split16_ms"] = res["step"]["recon_ms"]
-        extra["ntrig"] = res.get("ntrig")
-        extra["peak_max_absz"] = res.get("peak_max")
+        ach = 4.0 * n * sum_l / t_rec / 1e12
+        out.update(step_ms=ms, value=samples / (ms * 1e-3), unit="template-samples/s",
+                   recon_split16_ms=res["step"]["recon_ms"], ntrig=res.get("ntrig"), peak_max_absz=res.get("peak_max"),
+                   roofline={"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+                             "frac": ach / PEAK_FP16_TFLOPS, "traffic": counter_traffic("k_recon_f16"),
+                             "kernel": "k_recon_f16 (split-FP16 reconstruction)",
+                             "executed_over_useful_taps": exec_taps / sum_l, "correction_step_frac": corr_frac,
+                             "executed_frac_of_peak": (1 + 2 * corr_frac) * 4.0 * n * exec_taps / t_rec / 1e12
+                             / PEAK_FP16_TFLOPS})
     if "fp32" in res:
         t32 = res["fp32"]["recon_ms"] * 1e-3
-        extra["recon_fp32_ms"] = res["fp32"]["recon_ms"]
-        extra["fp32_path_value"] = samples / (res["fp32"]["wall_ms"] / max(2, args.steps // 2) * 1e-3)
-        extra["fp32_roofline_frac"] = 4.0 * n * sum_l / t32 / 1e12 / PEAK_FP32_TFLOPS
+        out["recon_fp32_ms"] = res["fp32"]["recon_ms"]
+        out["fp32_path_value"] = samples / (res["fp32"]["wall_ms"] / max(2, args.steps // 2) * 1e-3)
+        out["fp32_roofline_frac"] = 4.0 * n * sum_l / t32 / 1e12 / PEAK_FP32_TFLOPS
     if "direct" in res:
         dms = res["direct"]["wall_ms"] / max(2, args.steps // 2)
-        extra["direct_fft_mf_ms"] = dms
-        extra["direct_fft_mf_value"] = samples / (dms * 1e-3)
+        out["direct_fft_mf_ms"] = dms
+        out["direct_fft_mf_value"] = samples / (dms * 1e-3)
         # the same filtering with the series stored and read out by a separate kernel
-        extra["direct_fft_mf_stored_ms"] = res["direct"]["stored_wall_ms"] / max(2, args.steps // 2)
+        out["direct_fft_mf_stored_ms"] = res["direct"]["stored_wall_ms"] / max(2, args.steps // 2)
         # HBM roofline on the algorithmic 16 B per template-sample: the template spectrum is
         # formed on chip and the series read out on chip, but a transform of 2^21 points does
         # not fit on chip, so its intermediate is written and read once (8 B each)
-        extra["direct_fft_mf_roofline"] = {"bound": "hbm", "bytes_per_template_sample": 16,
-                                           "achieved": 16 * samples / (dms * 1e-3) / 1e9,
-                                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                           "frac": 16 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS}
-        extra["err_vs_direct_mf"] = res["err_vs_direct"]
-    if "factored" in res:
-        extra["factored"] = res["factored"]
-    if "ols" in res:
-        extra["ols"] = res["ols"]
-    if "bank" in res:
-        extra["bank"] = res["bank"]
-    if "sweep" in res:
-        extra["sweep"] = res["sweep"]
-    if "stress" in res:
-        extra["stress"] = res["stress"]
-    if "batched" in res:
-        extra["batched"] = res["batched"]
-    if "batched_full" in res:
-        extra["batched_full"] = res["batched_full"]
-    if "learned" in res:
-        extra["learned"] = res["learned"]
-    out["extra"] = extra
-    if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_nbrs)
+        out["direct_fft_mf_roofline"] = {"bound": "hbm", "bytes_per_template_sample": 16,
+                                         "achieved": 16 * samples / (dms * 1e-3) / 1e9,
+                                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "frac": 16 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        out["err_vs_direct_mf"] = res["err_vs_direct"]
+    for key in ("factored", "ols", "bank", "learned"):
+        if key in res:
+            out[key] = res[key]
+    if "cpu" in legs:
+        log("bench: CPU oracle on the realistic workload (one core) and the host cost comparison")
+        out["cpu_oracle_one_core"] = cpu_baseline(w, args.cpu_nbrs)
     K.free()
     ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--cpu-nbrs", type=int, default=24)
+    ap.add_argument("--only", default="",
+                    help="comma list of legs: headline (the batched workload at full shape), and on the "
+                         "realistic workload step,fp32,direct,factored,ols,bank,learned, then batched (reduced), "
+                         "stress (default: all of these); sweep only when named")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.only.split(",")) if args.only else {"headline", "step", "fp32", "direct", "factored", "ols",
+                                                        "bank", "batched", "learned", "stress"}
+    if not args.no_cpu:
+        legs.add("cpu")
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+           "data": "synthetic"}
+    extra = {}
+    h = None
+    if "headline" in legs:
+        h = headline_leg(dev, args.steps, args.warmup)
+        g = h["grid"]
+        samples = (h["ktot"] + h["nref"]) * g.n * h["nseg"]
+        ms = h["wall_ms"] / args.steps
+        t_rec = float(np.mean(h["recon_ms"])) * 1e-3
+        alg = 4.0 * g.n * h["sum_l"] * h["nseg"]          # complex x real MAC per kept tap and output sample
+        ach = alg / t_rec / 1e12
+        out.update(value=samples / (ms * 1e-3), unit="template-samples/s", ms_per_step=ms)
+        out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / PEAK_FP16_TFLOPS, "traffic": counter_traffic("k_recon_f16_queue"),
+                           "kernel": "k_recon_f16_queue (persistent split-FP16 reconstruction, fused read-out)",
+                           "kernel_ms": t_rec * 1e3, "flops_per_launch": alg,
+                           "timed": "reconstruction graph per step (persistent launch + peak finalisation), "
+                                    "HIP events on the batch's stream",
+                           "executed_over_useful_taps": h["exec_taps"] / h["sum_l"],
+                           "correction_step_frac": h["corr_frac"],
+                           "executed_frac_of_peak": (1 + 2 * h["corr_frac"]) * 4.0 * g.n * h["exec_taps"] * h["nseg"]
+                           / t_rec / 1e12 / PEAK_FP16_TFLOPS}
+        out["config"] = {"workload": f"batched-{h['nseg']}seg-256s-4096Hz-{h['nref']}ref-{h['ktot']}kernels",
+                         "segments": h["nseg"], "n": g.n, "fs": g.fs, "f_low": g.f_low, "f_high": g.f_high,
+                         "references": h["nref"], "kernels": h["ktot"], "threshold_per_s": 1e-3,
+                         "kernel_taps_min": int(h["lens"].min()), "kernel_taps_max": int(h["lens"].max()),
+                         "kernel_taps_sum": h["sum_l"], "chunks": h["chunks"],
+                         "precision": "split fp16 hi/lo, hi*lo + lo*hi where large taps, fp32 accumulation"}
+        extra["headline"] = {"kernel_build_s": h["build_s"], "autotune_s": h["tune_s"],
+                             "recon_ms_per_step": h["recon_ms"], "graph_captures_while_timed": h["captures_in_timed"],
+                             "graph_replays_while_timed": h["replays_in_timed"], "ntrig": h["ntrig"],
+                             "peak_max_absz": h["peak_max"], "injections_with_trigger": h["injections_found"]}
+    c2 = {"step", "fp32", "direct", "factored", "ols", "bank", "learned"} & legs
+    if c2:
+        extra["realistic"] = c2_legs(dev, args, legs)
+        if h is None and "value" in extra["realistic"]:
+            r = extra["realistic"]
+            out.update(value=r["value"], unit=r["unit"], ms_per_step=r["step_ms"], roofline=r["roofline"])
+            out["config"] = {"workload": r["workload"], "n": r["n"], "neighbours": r["neighbours"]}
+    if "batched" in legs:
+        log("bench: batched uneven workload (reduced)")
+        extra["batched_reduced"] = batched_leg(dev)
+    if "stress" in legs:
+        log("bench: next-generation-detector shape (4 x 1024 templates, 2^23 samples)")
+        ctx = rf.Context(0, torch.cuda.current_stream(dev))
+        extra["stress"] = stress_leg(dev, ctx)
+        ctx.close()
+    if "sweep" in legs:
+        log("bench: SNR loss against kernel length")
+        ctx = rf.Context(0, torch.cuda.current_stream(dev))
+        extra["sweep"] = sweep_leg(dev, ctx)
+        ctx.close()
+    torch.cuda.synchronize()
+    out["extra"] = extra
+    if "cpu" in legs and h is not None:
+        log("bench: CPU oracle baseline (seeded subset of the batched workload)")
+        out["cpu_baseline"] = cpu_baseline_batched(h["wb"])
     print(json.dumps(out), flush=True)
 
 

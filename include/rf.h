@@ -195,10 +195,11 @@ rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr
  * through the fused peak/threshold read-out -- the series are not stored.  The
  * device work is one captured hipGraph whose reconstruction is a single
  * persistent launch over all (segment, tile, time block) work items, longest
- * tiles first.  The graph reads and writes only buffers of the batch: each run
- * copies the caller's data in before the replay and the read-out out after it,
- * so new pointers do not re-capture it; a new cap or thr, or new chunk sizes,
- * do.  Kernel k of
+ * tiles first (captured as two graphs, the reference series and the
+ * reconstruction with its read-out, replayed back to back).  The graphs read
+ * and write only buffers of the batch: each run copies the caller's data in
+ * before the replay and the read-out out after it, so new pointers do not
+ * re-capture them; a new cap or thr, or new chunk sizes, do.  Kernel k of
  * group r has global index kbase[r] + k.  The batch borrows psd and the kernel
  * sets' contents are copied (the sets may be freed afterwards); it owns its
  * device buffers (about 24 bytes per sample per (segment, reference)). */
@@ -226,9 +227,11 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
  * RF_E_OVERFLOW when the crossings exceed cap. */
 rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr, rf_peak* peaks,
                        rf_trigger* trig, int64_t cap, int64_t* ntrig);
-/* Host copies (either may be NULL): number of graph captures and of replays
- * since the batch was created. */
-rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays);
+/* Host copies (any may be NULL): number of graph captures and of replays
+ * since the batch was created, and the duration in ms of the last run's
+ * reconstruction graph (the persistent launch with its read-out), from HIP
+ * events recorded around it on the context's stream. */
+rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays, float* recon_ms);
 rf_status rf_batch_free(rf_batch* b);
 
 /* ---- learned kernels: an MLP predicting ratio kernels in an SVD basis ----

@@ -59,11 +59,16 @@ struct rf_batch {
   rf_peak* peaks_own = nullptr;        // [nseg][ktotal]
   rf_trigger* trig_own = nullptr;      // [trig_cap]
   int64_t trig_cap = 0;
-  // captured graph and the read-out settings it was captured with
+  // captured graphs (reference series; reconstruction and read-out) and the
+  // read-out settings they were captured with
   hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec_ref = nullptr;
   int64_t g_cap = -1;
   float g_thr = -1.f;
   int64_t captures = 0, replays = 0;
+  // events around the reconstruction graph of each run (on the context's stream)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_recon_ms = 0.f;
 };
 
 namespace rf {
@@ -71,9 +76,18 @@ namespace {
 
 int bucket_of(int64_t ksteps) { return ksteps <= 64 ? 0 : (ksteps <= 512 ? 1 : 2); }
 
+void drop_graphs(rf_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec_ref) (void)hipGraphExecDestroy(b->exec_ref);
+  b->exec = nullptr;
+  b->exec_ref = nullptr;
+}
+
 void free_batch(rf_batch* b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  drop_graphs(b);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
   for (void* p : {(void*)b->coef, (void*)b->moment, (void*)b->tiles, (void*)b->items, (void*)b->b16,
                   (void*)b->colscale, (void*)b->slot_kernel, (void*)b->q, (void*)b->zref, (void*)b->zs,
                   (void*)b->maxbits, (void*)b->zinv, (void*)b->packed, (void*)b->counter, (void*)b->gflag,
@@ -85,10 +99,7 @@ void free_batch(rf_batch* b) {
 void upload_items(rf_batch* b) {
   for (auto& it : b->hitems) it.chunk = b->chunk_for_bucket[bucket_of(b->htiles[it.tile].t.ksteps)];
   RF_HIP(hipMemcpy(b->items, b->hitems.data(), sizeof(WorkItem) * b->hitems.size(), hipMemcpyHostToDevice));
-  if (b->exec) {
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
+  drop_graphs(b);
 }
 
 // reference series of every (segment, reference) and their FP16 split
@@ -99,11 +110,10 @@ void enqueue_reference(rf_ctx* ctx, rf_batch* b, const void* xf) {
   split_launch(ctx, b->zref, b->n, b->maxbits, b->zs, b->zinv, b->nseg * b->nref);
 }
 
-void enqueue_run(rf_ctx* ctx, rf_batch* b, const void* xf, float thr, rf_peak* peaks, rf_trigger* trig,
-                 int64_t cap) {
+// the persistent reconstruction over every work item with the fused read-out
+void enqueue_recon(rf_ctx* ctx, rf_batch* b, float thr, rf_peak* peaks, rf_trigger* trig, int64_t cap) {
   const int64_t np = int64_t(b->nseg) * b->ktotal;
   fill_u64(ctx, b->packed, 0ull, np + 1);
-  enqueue_reference(ctx, b, xf);
   PeakOut po{};
   po.packed = b->packed;
   po.count = reinterpret_cast<unsigned long long*>(b->packed + np);
@@ -115,6 +125,26 @@ void enqueue_run(rf_ctx* ctx, rf_batch* b, const void* xf, float thr, rf_peak* p
   queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, b->items, int(b->hitems.size()),
                b->counter, b->b16, b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
   peaks_finalize(ctx, b->packed, np, peaks);
+}
+
+template <typename F>
+hipGraphExec_t capture(rf_ctx* ctx, F&& enqueue) {
+  hipGraph_t graph = nullptr;
+  RF_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue();
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(ctx->stream, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  RF_HIP(hipStreamEndCapture(ctx->stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+  return exec;
 }
 
 std::string signature(const rf_batch* b) {
@@ -251,6 +281,8 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     b->fb = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
     b->xf_own = dev_alloc<double2>(size_t(nseg) * size_t(b->n / 2 + 1), "batch: device allocation failed");
     b->peaks_own = dev_alloc<rf_peak>(size_t(nseg) * size_t(b->ktotal), "batch: device allocation failed");
+    RF_HIP(hipEventCreate(&b->ev0));
+    RF_HIP(hipEventCreate(&b->ev1));
     RF_HIP(hipStreamSynchronize(ctx->stream));
     *out = b;
     st = RF_OK;
@@ -383,11 +415,8 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
     RF_CHECK(cap >= 0 && (cap == 0 || trig), "rf_batch_run: bad trigger buffer");
     RF_CHECK(std::isfinite(thr) && thr >= 0, "rf_batch_run: bad threshold");
     RF_CHECK(ctx->stream != nullptr, "rf_batch_run: needs a non-null stream (graph capture)");
-    if (!b->exec || b->g_cap != cap || b->g_thr != thr) {
-      if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-      }
+    if (!b->exec || !b->exec_ref || b->g_cap != cap || b->g_thr != thr) {
+      drop_graphs(b);
       if (cap > b->trig_cap) {
         RF_HIP(hipStreamSynchronize(ctx->stream));
         if (b->trig_own) (void)hipFree(b->trig_own);
@@ -396,20 +425,8 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
         b->trig_own = dev_alloc<rf_trigger>(size_t(cap), "batch: device allocation failed");
         b->trig_cap = cap;
       }
-      hipGraph_t graph = nullptr;
-      RF_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      try {
-        enqueue_run(ctx, b, b->xf_own, thr, b->peaks_own, cap > 0 ? b->trig_own : nullptr, cap);
-      } catch (...) {
-        hipGraph_t g2 = nullptr;
-        (void)hipStreamEndCapture(ctx->stream, &g2);
-        if (g2) (void)hipGraphDestroy(g2);
-        throw;
-      }
-      RF_HIP(hipStreamEndCapture(ctx->stream, &graph));
-      hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) throw Error{RF_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      b->exec_ref = capture(ctx, [&] { enqueue_reference(ctx, b, b->xf_own); });
+      b->exec = capture(ctx, [&] { enqueue_recon(ctx, b, thr, b->peaks_own, cap > 0 ? b->trig_own : nullptr, cap); });
       b->g_cap = cap;
       b->g_thr = thr;
       ++b->captures;
@@ -417,7 +434,10 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
     const int64_t np = int64_t(b->nseg) * b->ktotal;
     RF_HIP(hipMemcpyAsync(b->xf_own, xf_segs, sizeof(double2) * size_t(b->nseg) * size_t(b->n / 2 + 1),
                           hipMemcpyDeviceToDevice, ctx->stream));
+    RF_HIP(hipGraphLaunch(b->exec_ref, ctx->stream));
+    RF_HIP(hipEventRecord(b->ev0, ctx->stream));
     RF_HIP(hipGraphLaunch(b->exec, ctx->stream));
+    RF_HIP(hipEventRecord(b->ev1, ctx->stream));
     ++b->replays;
     unsigned long long cnt = 0;
     RF_HIP(hipMemcpyAsync(&cnt, b->packed + np, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
@@ -428,6 +448,7 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
       RF_HIP(hipMemcpyAsync(trig, b->trig_own, sizeof(rf_trigger) * size_t(nrec), hipMemcpyDeviceToDevice,
                             ctx->stream));
     RF_HIP(hipStreamSynchronize(ctx->stream));
+    RF_HIP(hipEventElapsedTime(&b->last_recon_ms, b->ev0, b->ev1));
     *ntrig = int64_t(cnt);
     if (int64_t(cnt) > cap) throw Error{RF_E_OVERFLOW, "rf_batch_run: trigger buffer overflow"};
   } catch (const Error& e) {
@@ -440,10 +461,11 @@ rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr,
   return RF_OK;
 }
 
-rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays) {
+rf_status rf_batch_graph_stats(const rf_batch* b, int64_t* captures, int64_t* replays, float* recon_ms) {
   if (!b) return RF_E_INVAL;
   if (captures) *captures = b->captures;
   if (replays) *replays = b->replays;
+  if (recon_ms) *recon_ms = b->last_recon_ms;
   return RF_OK;
 }
 

@@ -98,7 +98,7 @@ def load(path: str = LIB_PATH):
     lib.rf_batch_set_chunks.argtypes = [vp, ctypes.POINTER(i32)]
     lib.rf_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p]
     lib.rf_batch_run.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
-    lib.rf_batch_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.rf_batch_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
     lib.rf_batch_free.argtypes = [vp]
     lib.rf_surrogate_create.argtypes = [vp, ctypes.POINTER(RfGrid), ctypes.POINTER(RfTmpl), ctypes.POINTER(RfTmpl),
                                         i32, i32, i32, vp, i32, ctypes.POINTER(vp)]
@@ -307,8 +307,7 @@ def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: s
         trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
         fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
                            ctypes.pointer(cnt))
-    st = ctx.lib.snr_reconstruct(ctx.h, kernels.h, _ptr(z_ref), n, PREC[prec],
-                                 _ptr(z_out) if store else None,
+    st = ctx.lib.snr_reconstruct(ctx.h, kernels.h, _ptr(z_ref), n, PREC[prec], _ptr(z_out) if store else None,
                                  ctypes.byref(fused) if fused is not None else None)
     if st not in (RF_OK, RF_E_OVERFLOW):
         ctx.check(st)
@@ -409,10 +408,16 @@ class Batch:
         return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
 
     def graph_stats(self):
-        """(captures, replays) of the batch's graph since creation."""
+        """(captures, replays) of the batch's graphs since creation."""
         c, r = ctypes.c_int64(), ctypes.c_int64()
-        self.ctx.check(self.ctx.lib.rf_batch_graph_stats(self.h, ctypes.byref(c), ctypes.byref(r)))
+        self.ctx.check(self.ctx.lib.rf_batch_graph_stats(self.h, ctypes.byref(c), ctypes.byref(r), None))
         return c.value, r.value
+
+    def last_recon_ms(self):
+        """Duration of the last run's reconstruction graph (HIP events on the batch's stream)."""
+        ms = ctypes.c_float()
+        self.ctx.check(self.ctx.lib.rf_batch_graph_stats(self.h, None, None, ctypes.byref(ms)))
+        return ms.value
 
     def free(self):
         if getattr(self, "h", None):
