@@ -175,6 +175,18 @@ rf_status rf_kernels_free(rf_kernels* k);
 rf_status snr_reconstruct(rf_ctx* ctx, const rf_kernels* k, const void* z_ref, int64_t n,
                           rf_prec prec, void* z_out, const rf_peak_args* fused);
 
+/* snr_reconstruct without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, bit for bit, with the work
+ * buffers (FP16 split planes of z_ref, the read-out's peak keys) in a static
+ * device array of the library, 16 MiB + 33 KiB per device, held until the
+ * process ends.  Limits: n <= 2^21 and at most 4096 kernels (RF_E_INVAL
+ * beyond).  Every call on one device shares that array, so calls that overlap
+ * on a device (other streams or threads) race; calls in one stream are
+ * ordered.  Arguments otherwise as snr_reconstruct. */
+rf_status snr_reconstruct_noalloc(rf_ctx* ctx, const rf_kernels* k, const void* z_ref, int64_t n,
+                                  rf_prec prec, void* z_out, const rf_peak_args* fused);
+
 /* Peak and threshold read-out of nt series of n samples (section IV reads
  * the peak SNR of each series):
  *   z      device complex64 [nt][n]

@@ -3,10 +3,25 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 
 #include "recon.h"
+
+// Scratch of snr_reconstruct_noalloc, for callers that cannot allocate: the
+// FP16 split planes of the reference series (4 x n halves) with the split's
+// maximum bits and inverse scale, then the peak keys and trigger count of the
+// fused read-out.  One copy per device, held until the process ends; every
+// call on a device shares it (calls that overlap on one device race).
+namespace rf {
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 21;
+constexpr int32_t kNoAllocMaxKernels = 4096;
+constexpr size_t kNoAllocSplitBytes = sizeof(__half) * 4 * size_t(kNoAllocMaxN) + 256;
+constexpr size_t kNoAllocBytes = kNoAllocSplitBytes + sizeof(uint64_t) * (size_t(kNoAllocMaxKernels) + 1);
+constexpr int kMaxDevices = 64;
+}  // namespace rf
+static __device__ __align__(256) unsigned char scratch[rf::kNoAllocBytes];
 
 namespace rf {
 
@@ -58,6 +73,32 @@ T* upload(rf_ctx* ctx, int slot, const T* host, size_t count) {
 }
 
 void sync(rf_ctx* ctx) { RF_HIP(hipStreamSynchronize(ctx->stream)); }
+
+// Device address of `scratch` on each device (the host-side name is not one):
+// looked up once per device, with that device current, by rf_ctx_create.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_lookup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[device] = p;
+  return e;
+}
+
+char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return static_cast<char*>(g_scratch_ptr[device]);
+}
+
+// Work buffers of one reconstruction: split planes (+ max bits, inverse scale)
+// and the fused read-out's peak keys (+ trigger count).
+struct ReconScratch {
+  char* split;
+  uint64_t* packed;
+};
 
 double pow2_scale_for(double maxabs) {
   if (!(maxabs > 0)) return 1.0;
@@ -181,7 +222,7 @@ rf_status rf_ctx_create(int device, void* hip_stream, rf_ctx** out) {
   if (!c) return RF_E_NOMEM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipSetDevice(device) != hipSuccess) {
+  if (device >= kMaxDevices || hipSetDevice(device) != hipSuccess || scratch_lookup(device) != hipSuccess) {
     delete c;
     return RF_E_HIP;
   }
@@ -481,56 +522,94 @@ rf_status rf_kernels_free(rf_kernels* k) {
   return RF_OK;
 }
 
+}  // extern "C"
+
+namespace rf {
+namespace {
+
+void check_reconstruct_args(const rf_kernels* K, const void* z_ref, int64_t n, rf_prec prec, const void* z_out,
+                            const rf_peak_args* fused, const char* who) {
+  // messages are built only on failure (the no-allocation entry point shares this)
+  RF_CHECK(K && z_ref, std::string(who) + ": null pointer");
+  RF_CHECK(z_out || fused, std::string(who) + ": need z_out or fused read-out");
+  RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, std::string(who) + ": bad precision");
+  RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24),
+           std::string(who) + ": n must be a power of two in [2^8, 2^24]");
+  for (const TileDev& T : K->tiles)
+    RF_CHECK(T.ksteps * 16 <= n, std::string(who) + ": kernel support longer than the segment");
+  if (fused) {
+    RF_CHECK(fused->peaks && fused->ntrig && fused->cap >= 0 && (fused->cap == 0 || fused->trig),
+             std::string(who) + ": bad fused read-out arguments");
+    RF_CHECK(std::isfinite(fused->thr) && fused->thr >= 0, std::string(who) + ": bad threshold");
+  }
+}
+
+// snr_reconstruct on the given work buffers (split: 4 n halves + 256 bytes,
+// packed: nk + 1 keys); arguments already checked.
+void reconstruct_on(rf_ctx* ctx, const rf_kernels* K, const void* z_ref, int64_t n, rf_prec prec, void* z_out,
+                    const rf_peak_args* fused, const ReconScratch& ws, const char* who) {
+  PeakOut po{};
+  if (fused) {
+    fill_u64(ctx, ws.packed, 0ull, K->nk + 1);
+    po.packed = ws.packed;
+    po.count = reinterpret_cast<unsigned long long*>(ws.packed + K->nk);
+    po.trig = fused->trig;
+    po.cap = fused->cap;
+    po.thr2 = fused->thr * fused->thr;
+    po.seg = 0;
+    po.nk = K->nk;
+  }
+  const void* src = z_ref;
+  const float* zinv = nullptr;
+  if (prec == RF_PREC_SPLIT_FP16) {
+    uint32_t* mx = reinterpret_cast<uint32_t*>(ws.split + sizeof(__half) * 4 * size_t(n));
+    float* inv = reinterpret_cast<float*>(mx + 16);
+    split_launch(ctx, static_cast<const float2*>(z_ref), n, mx, reinterpret_cast<__half*>(ws.split), inv);
+    src = ws.split;
+    zinv = inv;
+  }
+  if (!K->tiles.empty())
+    recon_launch(ctx, prec, src, n, K->tiles_dev, int(K->tiles.size()), K, zinv, static_cast<float2*>(z_out), po,
+                 fused != nullptr);
+  if (fused) {
+    peaks_finalize(ctx, ws.packed, K->nk, fused->peaks);
+    unsigned long long cnt = 0;
+    RF_HIP(hipMemcpyAsync(&cnt, po.count, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    *fused->ntrig = int64_t(cnt);
+    if (int64_t(cnt) > fused->cap) throw Error{RF_E_OVERFLOW, std::string(who) + ": trigger buffer overflow"};
+  }
+}
+
+}  // namespace
+}  // namespace rf
+
+extern "C" {
+
 rf_status snr_reconstruct(rf_ctx* ctx, const rf_kernels* K, const void* z_ref, int64_t n,
                           rf_prec prec, void* z_out, const rf_peak_args* fused) {
   if (!ctx) return RF_E_INVAL;
   return guarded(ctx, [&] {
-    RF_CHECK(K && z_ref, "snr_reconstruct: null pointer");
-    RF_CHECK(z_out || fused, "snr_reconstruct: need z_out or fused read-out");
-    RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct: bad precision");
-    RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24),
-             "snr_reconstruct: n must be a power of two in [2^8, 2^24]");
-    for (const TileDev& T : K->tiles)
-      RF_CHECK(T.ksteps * 16 <= n, "snr_reconstruct: kernel support longer than the segment");
-    if (fused) {
-      RF_CHECK(fused->peaks && fused->ntrig && fused->cap >= 0 && (fused->cap == 0 || fused->trig),
-               "snr_reconstruct: bad fused read-out arguments");
-      RF_CHECK(std::isfinite(fused->thr) && fused->thr >= 0, "snr_reconstruct: bad threshold");
-    }
-    PeakOut po{};
-    uint64_t* packed = nullptr;
-    if (fused) {
-      packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * (K->nk + 1)));
-      fill_u64(ctx, packed, 0ull, K->nk + 1);
-      po.packed = packed;
-      po.count = reinterpret_cast<unsigned long long*>(packed + K->nk);
-      po.trig = fused->trig;
-      po.cap = fused->cap;
-      po.thr2 = fused->thr * fused->thr;
-      po.seg = 0;
-      po.nk = K->nk;
-    }
-    const void* src = z_ref;
-    const float* zinv = nullptr;
-    if (prec == RF_PREC_SPLIT_FP16) {
-      char* sp = static_cast<char*>(ctx->ws[WS_SPLIT].ensure(sizeof(__half) * 4 * size_t(n) + 256));
-      uint32_t* mx = reinterpret_cast<uint32_t*>(sp + sizeof(__half) * 4 * size_t(n));
-      float* inv = reinterpret_cast<float*>(mx + 16);
-      split_launch(ctx, static_cast<const float2*>(z_ref), n, mx, reinterpret_cast<__half*>(sp), inv);
-      src = sp;
-      zinv = inv;
-    }
-    if (!K->tiles.empty())
-      recon_launch(ctx, prec, src, n, K->tiles_dev, int(K->tiles.size()), K, zinv,
-                   static_cast<float2*>(z_out), po, fused != nullptr);
-    if (fused) {
-      peaks_finalize(ctx, packed, K->nk, fused->peaks);
-      unsigned long long cnt = 0;
-      RF_HIP(hipMemcpyAsync(&cnt, po.count, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
-      sync(ctx);
-      *fused->ntrig = int64_t(cnt);
-      if (int64_t(cnt) > fused->cap) throw Error{RF_E_OVERFLOW, "snr_reconstruct: trigger buffer overflow"};
-    }
+    check_reconstruct_args(K, z_ref, n, prec, z_out, fused, "snr_reconstruct");
+    ReconScratch ws{nullptr, nullptr};
+    if (fused) ws.packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * (K->nk + 1)));
+    if (prec == RF_PREC_SPLIT_FP16)
+      ws.split = static_cast<char*>(ctx->ws[WS_SPLIT].ensure(sizeof(__half) * 4 * size_t(n) + 256));
+    reconstruct_on(ctx, K, z_ref, n, prec, z_out, fused, ws, "snr_reconstruct");
+  });
+}
+
+rf_status snr_reconstruct_noalloc(rf_ctx* ctx, const rf_kernels* K, const void* z_ref, int64_t n,
+                                  rf_prec prec, void* z_out, const rf_peak_args* fused) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    check_reconstruct_args(K, z_ref, n, prec, z_out, fused, "snr_reconstruct_noalloc");
+    RF_CHECK(n <= kNoAllocMaxN, "snr_reconstruct_noalloc: n above the scratch limit of 2^21 samples");
+    RF_CHECK(K->nk <= kNoAllocMaxKernels, "snr_reconstruct_noalloc: more than 4096 kernels");
+    char* base = scratch_of(ctx->device);
+    RF_CHECK(base != nullptr, "snr_reconstruct_noalloc: no scratch address for this device");
+    ReconScratch ws{base, reinterpret_cast<uint64_t*>(base + kNoAllocSplitBytes)};
+    reconstruct_on(ctx, K, z_ref, n, prec, z_out, fused, ws, "snr_reconstruct_noalloc");
   });
 }
 

@@ -22,7 +22,7 @@ RF_PREC_FP32, RF_PREC_SPLIT_FP16 = 0, 1
 PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "mf_snr_peaks", "ratio_kernel_build",
-            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct",
+            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct", "snr_reconstruct_noalloc",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
             "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
     lib.rf_kernels_split_steps.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rf_kernels_free.argtypes = [vp]
     lib.snr_reconstruct.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.snr_reconstruct_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
     lib.snr_peaks.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
     lib.rf_batch_create.argtypes = [vp, ctypes.POINTER(RfGrid), vp, i32, ctypes.POINTER(RfTmpl),
                                     ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
@@ -290,9 +291,11 @@ def ratio_kernel_build(ctx: Context, grid, psd: torch.Tensor, ref, nbrs, thr: fl
 
 def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: str = "split16",
                     z_out=None, store: bool = True, fused_thr: float | None = None,
-                    trig_cap: int = 4096):
+                    trig_cap: int = 4096, noalloc: bool = False):
     """Reconstructed series [nk, n] (if store) and, with fused_thr, the fused
-    read-out (peaks tensor of RfPeak bytes, triggers, count)."""
+    read-out (peaks tensor of RfPeak bytes, triggers, count).  noalloc selects
+    snr_reconstruct_noalloc (the library allocates nothing; the outputs are
+    still the caller's)."""
     _dev_tensor(z_ref, torch.complex64, what="z_ref")
     n = z_ref.numel()
     if store and z_out is None:
@@ -307,8 +310,9 @@ def snr_reconstruct(ctx: Context, kernels: Kernels, z_ref: torch.Tensor, prec: s
         trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=z_ref.device)
         fused = RfPeakArgs(float(fused_thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap),
                            ctypes.pointer(cnt))
-    st = ctx.lib.snr_reconstruct(ctx.h, kernels.h, _ptr(z_ref), n, PREC[prec], _ptr(z_out) if store else None,
-                                 ctypes.byref(fused) if fused is not None else None)
+    fn = ctx.lib.snr_reconstruct_noalloc if noalloc else ctx.lib.snr_reconstruct
+    st = fn(ctx.h, kernels.h, _ptr(z_ref), n, PREC[prec], _ptr(z_out) if store else None,
+            ctypes.byref(fused) if fused is not None else None)
     if st not in (RF_OK, RF_E_OVERFLOW):
         ctx.check(st)
     out = dict(z=z_out if store else None)
