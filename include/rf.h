@@ -299,6 +299,22 @@ rf_status rf_surrogate_predict(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const 
  * the training grid): device complex128 [nk][rank].  Synchronises. */
 rf_status rf_surrogate_project(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
                                void* coeffs);
+/* Learned predictive coding of the coefficients (not in the paper): the exact
+ * coefficients c = U^H h of the pairs (ref, nbr[k]) are stored as residual
+ * codes against the network's prediction p (use_network = 1) or as plain
+ * codes (use_network = 0, p = 0):
+ *   r = c - p,  scale_k = max_j max(|Re r_j|, |Im r_j|) / qmax  (FP32),
+ *   code = round(r / scale_k) in [-qmax, qmax],  qmax = 2^(bits-1) - 1,
+ * bits 8 or 16; codes device int8 / int16 [nk][2 rank] (real parts, then
+ * imaginary parts), scales device float [nk].  Decoding gives c~ = p + code
+ * scale_k (device complex128 [nk][rank]) for rf_surrogate_kernels, so a kernel
+ * costs 2 rank codes + one scale instead of its taps; the network shrinks the
+ * range the codes must span.  Both synchronise. */
+rf_status rf_surrogate_encode(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                              int32_t bits, int32_t use_network, void* codes, float* scales);
+rf_status rf_surrogate_decode(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                              int32_t bits, int32_t use_network, const void* codes, const float* scales,
+                              void* coeffs);
 /* Kernel set of the targets nbr[k] of ref from the surrogate: w = Re(U c) on
  * the window, truncated as ratio_kernel_build truncates, with c the network's
  * prediction, or coeffs (device complex128 [nk][rank]) when not NULL.  A kernel

@@ -317,6 +317,64 @@ __global__ void k_from_outputs(const float* __restrict__ o, int n, int rank, dou
                                             double(o[int64_t(p) * 2 * rank + rank + j]) * scale);
 }
 
+// Residual codes of one kernel's coefficients (one block per kernel):
+// r = c - p (p the network's prediction, or zero), scale = max |Re r|, |Im r|
+// over the kernel's 2 rank reals / qmax (as float), code = round(r / scale)
+// clamped to [-qmax, qmax]; real parts first, then imaginary parts.
+template <typename Q>
+__global__ __launch_bounds__(128) void k_encode(const double2* __restrict__ c, const double2* __restrict__ p,
+                                                int rank, int qmax, Q* __restrict__ codes,
+                                                float* __restrict__ scales) {
+  __shared__ double sh[128];
+  const int k = blockIdx.x;
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < rank; j += blockDim.x) {
+    double2 r = c[int64_t(k) * rank + j];
+    if (p) {
+      r.x -= p[int64_t(k) * rank + j].x;
+      r.y -= p[int64_t(k) * rank + j].y;
+    }
+    mx = fmax(mx, fmax(fabs(r.x), fabs(r.y)));
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 64; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const float sc = float(sh[0] / double(qmax));
+  if (threadIdx.x == 0) scales[k] = sc;
+  const double inv = sc > 0.f ? 1.0 / double(sc) : 0.0;
+  for (int j = threadIdx.x; j < rank; j += blockDim.x) {
+    double2 r = c[int64_t(k) * rank + j];
+    if (p) {
+      r.x -= p[int64_t(k) * rank + j].x;
+      r.y -= p[int64_t(k) * rank + j].y;
+    }
+    const double qa = fmin(fmax(rint(r.x * inv), -double(qmax)), double(qmax));
+    const double qb = fmin(fmax(rint(r.y * inv), -double(qmax)), double(qmax));
+    codes[int64_t(k) * 2 * rank + j] = Q(qa);
+    codes[int64_t(k) * 2 * rank + rank + j] = Q(qb);
+  }
+}
+
+// c = p + code * scale (p the prediction, or zero)
+template <typename Q>
+__global__ void k_decode(const Q* __restrict__ codes, const float* __restrict__ scales,
+                         const double2* __restrict__ p, int rank, double2* __restrict__ c) {
+  const int k = blockIdx.x;
+  const double sc = double(scales[k]);
+  for (int j = threadIdx.x; j < rank; j += blockDim.x) {
+    double2 v = make_double2(double(codes[int64_t(k) * 2 * rank + j]) * sc,
+                             double(codes[int64_t(k) * 2 * rank + rank + j]) * sc);
+    if (p) {
+      v.x += p[int64_t(k) * rank + j].x;
+      v.y += p[int64_t(k) * rank + j].y;
+    }
+    c[int64_t(k) * rank + j] = v;
+  }
+}
+
 // max_m |a[k][m] - b[k][m]| per row (complex64), one block per row
 __global__ __launch_bounds__(256) void k_rowmaxdiff(const float2* __restrict__ a, const float2* __restrict__ b,
                                                     int64_t n, float* __restrict__ out) {
@@ -852,6 +910,61 @@ rf_status rf_surrogate_project(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const 
     RF_HIP(hipStreamSynchronize(ctx->stream));
   });
   if (H) (void)hipFree(H);
+  return st;
+}
+
+rf_status rf_surrogate_encode(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                              int32_t bits, int32_t use_network, void* codes, float* scales) {
+  if (!ctx || !s) return RF_E_INVAL;
+  double2* H = nullptr;
+  double2* c = nullptr;
+  rf_status st = guarded(ctx, [&] {
+    RF_CHECK(nbr && codes && scales && nk >= 1, "rf_surrogate_encode: bad arguments");
+    RF_CHECK(bits == 8 || bits == 16, "rf_surrogate_encode: bits must be 8 or 16");
+    const int L = s->window;
+    std::vector<rf_tmpl> refs(size_t(nk), ref);
+    H = dev_alloc<double2>(size_t(nk) * L, "surrogate: device allocation failed");
+    c = dev_alloc<double2>(size_t(nk) * s->rank * 2, "surrogate: device allocation failed");
+    double2* p = use_network ? c + size_t(nk) * s->rank : nullptr;
+    window_kernels(ctx, &s->grid, refs.data(), nbr, nk, L, H);
+    zgemm(ctx, H, L, 0, 0, s->U, s->rank, 0, 1, c, s->rank, nk, s->rank, L);   // exact U^H h
+    if (p) predict_into(ctx, s, ref, nbr, nk, p);
+    if (bits == 8)
+      hipLaunchKernelGGL(k_encode<int8_t>, dim3(unsigned(nk)), dim3(128), 0, ctx->stream, c, p, s->rank, 127,
+                         static_cast<int8_t*>(codes), scales);
+    else
+      hipLaunchKernelGGL(k_encode<int16_t>, dim3(unsigned(nk)), dim3(128), 0, ctx->stream, c, p, s->rank, 32767,
+                         static_cast<int16_t*>(codes), scales);
+    RF_HIP(hipGetLastError());
+    RF_HIP(hipStreamSynchronize(ctx->stream));
+  });
+  if (H) (void)hipFree(H);
+  if (c) (void)hipFree(c);
+  return st;
+}
+
+rf_status rf_surrogate_decode(rf_ctx* ctx, rf_surrogate* s, rf_tmpl ref, const rf_tmpl* nbr, int32_t nk,
+                              int32_t bits, int32_t use_network, const void* codes, const float* scales,
+                              void* coeffs) {
+  if (!ctx || !s) return RF_E_INVAL;
+  double2* p = nullptr;
+  rf_status st = guarded(ctx, [&] {
+    RF_CHECK(nbr && codes && scales && coeffs && nk >= 1, "rf_surrogate_decode: bad arguments");
+    RF_CHECK(bits == 8 || bits == 16, "rf_surrogate_decode: bits must be 8 or 16");
+    if (use_network) {
+      p = dev_alloc<double2>(size_t(nk) * s->rank, "surrogate: device allocation failed");
+      predict_into(ctx, s, ref, nbr, nk, p);
+    }
+    if (bits == 8)
+      hipLaunchKernelGGL(k_decode<int8_t>, dim3(unsigned(nk)), dim3(64), 0, ctx->stream,
+                         static_cast<const int8_t*>(codes), scales, p, s->rank, static_cast<double2*>(coeffs));
+    else
+      hipLaunchKernelGGL(k_decode<int16_t>, dim3(unsigned(nk)), dim3(64), 0, ctx->stream,
+                         static_cast<const int16_t*>(codes), scales, p, s->rank, static_cast<double2*>(coeffs));
+    RF_HIP(hipGetLastError());
+    RF_HIP(hipStreamSynchronize(ctx->stream));
+  });
+  if (p) (void)hipFree(p);
   return st;
 }
 

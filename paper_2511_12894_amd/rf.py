@@ -27,6 +27,7 @@ EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "m
             "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
             "rf_surrogate_dataset", "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
+            "rf_surrogate_encode", "rf_surrogate_decode",
             "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
             "rf_factored_free", "rf_ols_build", "rf_ols_info", "snr_reconstruct_ols", "rf_ols_free",
             "rf_template_durations", "rf_bank_organise", "rf_surrogate_free")
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
     lib.rf_surrogate_train.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]
     lib.rf_surrogate_predict.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, vp]
     lib.rf_surrogate_project.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, vp]
+    lib.rf_surrogate_encode.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, i32, i32, vp, vp]
+    lib.rf_surrogate_decode.argtypes = [vp, vp, RfTmpl, ctypes.POINTER(RfTmpl), i32, i32, i32, vp, vp, vp]
     lib.rf_surrogate_kernels.argtypes = [vp, vp, ctypes.POINTER(RfGrid), vp, RfTmpl, ctypes.POINTER(RfTmpl), i32,
                                          vp, dbl, ctypes.c_int, ctypes.POINTER(RfGrid), vp, vp, dbl,
                                          ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
@@ -523,6 +526,32 @@ class Surrogate:
         c = torch.empty((len(nbrs), self.rank), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
         self.ctx.check(self.ctx.lib.rf_surrogate_project(self.ctx.h, self.h, RfTmpl(*map(float, ref)),
                                                          _tmpl_array(nbrs), len(nbrs), _ptr(c)))
+        return c
+
+    def encode(self, ref, nbrs, bits: int = 16, network: bool = True):
+        """Residual codes of the exact coefficients against the network's
+        prediction (network=False: plain codes): (codes int8/int16 [nk, 2 rank],
+        scales float32 [nk]) on the device."""
+        _require(bits in (8, 16), "bits must be 8 or 16")
+        dev = f"cuda:{self.ctx.device}"
+        codes = torch.empty((len(nbrs), 2 * self.rank), dtype=torch.int8 if bits == 8 else torch.int16, device=dev)
+        scales = torch.empty(len(nbrs), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_encode(self.ctx.h, self.h, RfTmpl(*map(float, ref)), _tmpl_array(nbrs),
+                                                        len(nbrs), int(bits), int(bool(network)), _ptr(codes),
+                                                        _ptr(scales)))
+        return codes, scales
+
+    def decode(self, ref, nbrs, codes: torch.Tensor, scales: torch.Tensor, network: bool = True):
+        """Coefficients (complex128 [nk, rank], device) from residual codes."""
+        bits = 8 if codes.dtype == torch.int8 else 16
+        _dev_tensor(codes, torch.int8 if bits == 8 else torch.int16, shape=(len(nbrs), 2 * self.rank), what="codes")
+        _dev_tensor(scales, torch.float32, len(nbrs), what="scales")
+        c = torch.empty((len(nbrs), self.rank), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        torch.cuda.synchronize()
+        self.ctx.check(self.ctx.lib.rf_surrogate_decode(self.ctx.h, self.h, RfTmpl(*map(float, ref)), _tmpl_array(nbrs),
+                                                        len(nbrs), bits, int(bool(network)), _ptr(codes), _ptr(scales),
+                                                        _ptr(c)))
         return c
 
     def kernels(self, grid, psd, ref, nbrs, coeffs=None, thr=1e-3, unit=RF_THR_PER_SECOND, check=None, tol=2e-4):

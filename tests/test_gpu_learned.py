@@ -224,6 +224,55 @@ def test_network_kernels_with_check_fallback(rf, st):
     K.free()
 
 
+def test_residual_codes_roundtrip_and_range(rf, st):
+    """Decoding the codes gives the exact coefficients within half a code step
+    per component, and the network's prediction shrinks the range the codes
+    span (smaller scales) compared with coding the coefficients alone."""
+    S = st["S"]
+    _train(rf, st, 1500, 3e-3)
+    with torch.cuda.stream(st["stream"]):
+        c = S.project(st["ref"], st["nb"])
+        out = {}
+        for net in (True, False):
+            codes, scales = S.encode(st["ref"], st["nb"], bits=16, network=net)
+            out[net] = (codes, scales, S.decode(st["ref"], st["nb"], codes, scales, network=net))
+    torch.cuda.synchronize()
+    for net, (codes, scales, cd) in out.items():
+        d = (cd - c)
+        bound = 0.5 * scales.double()[:, None] * (1 + 1e-12)
+        assert (d.real.abs() <= bound).all() and (d.imag.abs() <= bound).all()
+        assert codes.abs().max().item() == 32767        # the largest residual sets the scale
+    ratio = (out[False][1] / out[True][1]).cpu().numpy()
+    _say(f"code scale without / with the network: median {np.median(ratio):.1f}, min {ratio.min():.1f}")
+    assert np.median(ratio) >= 3.0
+
+
+def test_network_residual_kernels_pass_the_check(rf, st):
+    """The learned form that gains: network prediction + 16-bit residual codes
+    (2 rank codes and one scale per kernel).  Fewer than all kernels fall back,
+    every accepted kernel is within 2e-4 on the check segment, and the final
+    set's series match the oracle's direct matched filtering within 2e-4."""
+    S, ctx = st["S"], st["ctx"]
+    _train(rf, st, 1500, 3e-3)
+    gs = st["gs"]
+    chk = (gs, st["xf_d"], st["psd_d"])
+    with torch.cuda.stream(st["stream"]):
+        codes, scales = S.encode(st["ref"], st["nb"], bits=16, network=True)
+        cd = S.decode(st["ref"], st["nb"], codes, scales, network=True)
+        K, fb, err = S.kernels(gs, st["psd_d"], st["ref"], st["nb"], coeffs=cd, check=chk, tol=2e-4)
+        zr, _ = rf.mf_ref_snr(ctx, gs, st["xf_d"], st["psd_d"], [st["ref"]])
+        z = rf.snr_reconstruct(ctx, K, zr[0].contiguous(), prec="split16")["z"].cpu().numpy()
+    torch.cuda.synchronize()
+    _say(f"network + 16-bit residual codes: fallback {sum(fb)}/{len(fb)}, check errors max {max(err):.2e}")
+    assert sum(fb) < len(fb)
+    for k in range(len(fb)):
+        assert fb[k] == 1 or err[k] <= 2e-4
+    for k in (0, 9, 17, 23):
+        zd, _ = omf.grid_snr_series(gs, st["xf"], st["psd"], *st["nb"][k])
+        assert np.abs(z[k] - zd).max() <= 2e-4
+    K.free()
+
+
 def test_forced_fallback_equals_exact_build(rf, st):
     """tol = 0: every kernel is replaced; the set is the exact build, bit for bit."""
     S, ctx = st["S"], st["ctx"]
