@@ -67,9 +67,3 @@ def organise(bank, tau, max_spread: float = 10.0, max_size: int = 500):
         cands = [p for p in range(len(g)) if cost[p] <= best * (1 + 1e-12)]
         refs.append(g[min(cands, key=lambda p: (tg[p], p))])
     return groups, refs
-
-
-def storage_ratio(template_durations, kernel_durations) -> float:
-    """Storage of the full templates over storage of their ratio kernels (the
-    paper compares durations, sec. IV)."""
-    return float(np.sum(template_durations) / np.sum(kernel_durations))
