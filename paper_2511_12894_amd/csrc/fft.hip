@@ -24,7 +24,31 @@ template <typename T> struct C2;
 template <> struct C2<float> { using t = float2; };
 template <> struct C2<double> { using t = double2; };
 
-__device__ inline void sc_pi(float x, float* s, float* c) { sincospif(x, s, c); }
+// sin(pi x) and cos(pi x) in FP32 for |x| <= 2^22: the nearest quarter turn
+// q = rint(2x), the remainder f = x - q/2 in [-1/4, 1/4] (exact), theta = pi f
+// with pi split into two floats, then an odd degree-7 and an even degree-8
+// polynomial on [-pi/4, pi/4] (coefficients fitted here by weighted least
+// squares: relative error 3.6e-9 for sin, absolute 5.4e-11 for cos, in exact
+// arithmetic; about 0.6 ulp of 1 in FP32 with fused multiply-adds), rotated by
+// the quarter turn.
+__device__ inline void sincospi_f32(float x, float* s, float* c) {
+  const float q = rintf(2.f * x);
+  const float f = fmaf(-0.5f, q, x);
+  const float th = fmaf(f, 3.14159274101257324f, f * -8.74227766e-08f);
+  const float u = th * th;
+  float ps = fmaf(-1.9517e-04f, u, 8.33218e-03f);
+  ps = fmaf(ps, u, -0.16666655f);
+  const float sn = fmaf(th * u, ps, th);
+  float pc = fmaf(2.43904474e-05f, u, -1.38867638e-03f);
+  pc = fmaf(pc, u, 4.16666233e-02f);
+  pc = fmaf(pc, u, -0.499999997f);
+  const float cs = fmaf(u, pc, 1.f);
+  const int qi = int(q) & 3;
+  const float s0 = (qi & 1) ? cs : sn, c0 = (qi & 1) ? sn : cs;
+  *s = (qi & 2) ? -s0 : s0;
+  *c = ((qi + 1) & 2) ? -c0 : c0;
+}
+__device__ inline void sc_pi(float x, float* s, float* c) { sincospi_f32(x, s, c); }
 __device__ inline void sc_pi(double x, double* s, double* c) { sincospi(x, s, c); }
 
 template <typename V> __device__ inline V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
@@ -82,9 +106,23 @@ template <typename V> struct Dft<V, 8> {
 constexpr int kThreads = 256;
 constexpr int kCols = 16;
 
+// LDS layout of a block's columns: element x of a column at x + x / 32 (one
+// pad slot every 32 elements), columns lds_stride apart.  With 64 banks of 4
+// bytes this spreads the column-strided loads and the radix-8 stage writes
+// over the banks (a column stride of P + 1 put up to 4 lanes on a bank).
+__device__ constexpr int sw(int x) { return x + (x >> 5); }
+template <typename T, int P> struct Lds;
+template <int P> struct Lds<float, P> {
+  static constexpr int stride = P == 16 ? 18 : P == 32 ? 37 : P == 64 ? 70 : P == 128 ? 138 : 266;
+};
+template <int P> struct Lds<double, P> {
+  static constexpr int stride = P == 16 ? 17 : P == 32 ? 35 : P == 64 ? 67 : P == 128 ? 131 : 263;
+};
+template <typename T, int P> using LdsRow = typename C2<T>::t[Lds<T, P>::stride];
+
 // One in-LDS Stockham stage of radix R on every column (sub-length NS done).
 template <typename T, int P, int NS, int R>
-__device__ inline void inner_stage(typename C2<T>::t (*s)[P + 1], const typename C2<T>::t* tw) {
+__device__ inline void inner_stage(LdsRow<T, P>* s, const typename C2<T>::t* tw) {
   using V = typename C2<T>::t;
   constexpr int NBF = kCols * P / R;                 // butterflies in the block
   constexpr int PER = (NBF + kThreads - 1) / kThreads;
@@ -99,7 +137,7 @@ __device__ inline void inner_stage(typename C2<T>::t (*s)[P + 1], const typename
     if (NBF % kThreads == 0 || b < NBF) {
       const int kk = jj[i] % NS;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = s[cc[i]][jj[i] + q * Q];
+      for (int q = 0; q < R; ++q) v[i][q] = s[cc[i]][sw(jj[i] + q * Q)];
       if (NS > 1) {
 #pragma unroll
         for (int q = 1; q < R; ++q) v[i][q] = cmul(v[i][q], tw[q * kk * (P / (NS * R))]);
@@ -115,14 +153,14 @@ __device__ inline void inner_stage(typename C2<T>::t (*s)[P + 1], const typename
       const int kk = jj[i] % NS;
       const int d = (jj[i] / NS) * NS * R + kk;
 #pragma unroll
-      for (int q = 0; q < R; ++q) s[cc[i]][d + q * NS] = v[i][q];
+      for (int q = 0; q < R; ++q) s[cc[i]][sw(d + q * NS)] = v[i][q];
     }
   }
   __syncthreads();
 }
 
 template <typename T, int P, int NS>
-__device__ inline void inner_dft(typename C2<T>::t (*s)[P + 1], const typename C2<T>::t* tw) {
+__device__ inline void inner_dft(LdsRow<T, P>* s, const typename C2<T>::t* tw) {
   if constexpr (NS < P) {
     constexpr int REM = P / NS;
     constexpr int R = REM >= 8 ? 8 : REM;
@@ -152,7 +190,7 @@ struct TmplIn {
   int nt;
 };
 
-enum PassInput { kPlain = 0, kBand = 1, kTmpl = 2 };
+enum PassInput { kPlain = 0, kBand = 1 };
 
 // RO (a pass after the first, FP32): the outputs are not stored but read out
 // (running peak and threshold crossings of series tmpl0 + blockIdx.y).
@@ -162,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
                                                        int64_t n, int64_t ns, BandIn bin, TmplIn tin,
                                                        PeakOut po) {
   using V = typename C2<T>::t;
-  __shared__ V s[kCols][P + 1];
+  __shared__ V s[kCols][Lds<T, P>::stride];
   __shared__ V tw[P];
   const int64_t ncols = n / P;
   const int64_t j0 = int64_t(blockIdx.x) * kCols;
@@ -174,40 +212,15 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
     sc_pi(T(2 * m) / T(P), &sn, &cs);
     tw[m] = V{cs, sn};
   }
-  Tf2Coef tc{};
-  double tg = 0.0;
-  if constexpr (MODE == kTmpl) {
-    tc = tin.coef[blockIdx.y % tin.nt];
-    tg = sqrt(4.0 * tin.df / *tin.moment);
-  }
-  // load 16 columns, apply the inter-pass twiddle exp(+2 pi i r k / (ns P))
+  // load 16 columns, apply the inter-pass twiddle exp(+2 pi i r k / (ns P)); r k < ns P <= 2^24
+  // is exact in 32 bits and as a float, 2 / (ns P) a power of two
   const int64_t L = ns * P;
+  const T two_over_L = T(2) / T(L);
   for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
     const int c = e % kCols, r = e / kCols;
     const int64_t j = j0 + c;
     V v;
-    if constexpr (MODE == kTmpl) {
-      const int64_t fj = j + int64_t(r) * ncols;
-      v = V{0, 0};
-      if (fj >= tin.jlo && fj <= tin.jhi) {
-        const double f = double(fj) * tin.df;
-        // f^(1/3): the FP32 root refined by one Newton step (about 46 bits)
-        double cf = double(cbrtf(float(f)));
-        const float cf32 = float(cf);
-        cf -= double(float(cf * cf * cf - f) / (3.0f * cf32 * cf32));
-        // the phase in FP64 (it reaches ~1e5 rad), reduced to [-pi, pi] in FP64; the
-        // exponential of the reduced angle and the amplitude need only FP32
-        const double psi = tf2_phase(tc, tc.cbrt_piM * cf);
-        const double k = rint(psi * 0.15915494309189533577);
-        const float ang = float(fma(-k, 6.28318530717958647693, psi));
-        float sn, cs;
-        sincosf(ang, &sn, &cs);
-        // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
-        const float a = float(tg) / (float(f) * sqrtf(float(cf)));
-        const float2 q = tin.q[int64_t(blockIdx.y / tin.nt) * (tin.jhi - tin.jlo + 1) + (fj - tin.jlo)];
-        v = V{a * (q.x * cs - q.y * sn), a * (q.x * sn + q.y * cs)};
-      }
-    } else if constexpr (MODE == kBand) {
+    if constexpr (MODE == kBand) {
       const int64_t i = j + int64_t(r) * ncols - bin.b0;
       v = V{0, 0};
       if (i >= 0 && i < bin.nb) {
@@ -220,12 +233,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
       v = in[j + int64_t(r) * ncols];
     }
     if (ns > 1) {
-      const int64_t k = j & (ns - 1);
+      const uint32_t k = uint32_t(j) & uint32_t(ns - 1);
       T sn, cs;
-      sc_pi(T(2 * ((int64_t(r) * k) & (L - 1))) / T(L), &sn, &cs);
+      sc_pi(T(uint32_t(r) * k) * two_over_L, &sn, &cs);
       v = cmul(v, V{cs, sn});
     }
-    s[c][r] = v;
+    s[c][sw(r)] = v;
   }
   __syncthreads();
   inner_dft<T, P, 1>(s, tw);
@@ -236,7 +249,8 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
       const int c = e % kCols, q = e / kCols;
       const int64_t j = j0 + c;
-      peak_visit(best, s[c][q].x, s[c][q].y, (j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns, po);
+      const V z = s[c][sw(q)];
+      peak_visit(best, z.x, z.y, (j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns, po);
     }
     peak_commit(best, po);
     return;
@@ -245,14 +259,104 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
     // out[j P + q]: the block's 16 columns are one contiguous run
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
       const int q = e % P, c = e / P;
-      out[(j0 + c) * P + q] = s[c][q];
+      out[(j0 + c) * P + q] = s[c][sw(q)];
     }
   } else {
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
       const int c = e % kCols, q = e / kCols;
       const int64_t j = j0 + c;
-      out[(j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns] = s[c][q];
+      out[(j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns] = s[c][sw(q)];
     }
+  }
+}
+
+// First pass of the matched filters of TPW templates sharing one workgroup (the
+// kTmpl input of k_fft_pass): the parts of every bin's phase and amplitude that
+// do not depend on the template -- f^(1/3), ln f, f^(-1/3) in FP64 and
+// f^(-7/6) -- are computed once per bin and kept in registers; each template
+// then takes its phase series from them (v = (pi M)^(1/3) f^(1/3),
+// ln v = ln (pi M)^(1/3) + ln(f) / 3, 1 / v = f^(-1/3) / (pi M)^(1/3)), forms its
+// weighted spectrum, transforms its 16 columns in LDS and stores them.
+template <int P, int TPW>
+__global__ __launch_bounds__(kThreads) void k_fft_tmpl_pass(float2* __restrict__ out, int64_t n, int batch,
+                                                            TmplIn tin) {
+  using V = float2;
+  constexpr int PER = (kCols * P + kThreads - 1) / kThreads;
+  __shared__ V s[kCols][Lds<float, P>::stride];
+  __shared__ V tw[P];
+  const int64_t ncols = n / P;
+  const int64_t j0 = int64_t(blockIdx.x) * kCols;
+  for (int m = threadIdx.x; m < P; m += kThreads) {
+    float sn, cs;
+    sincospi_f32(float(2 * m) / float(P), &sn, &cs);
+    tw[m] = V{cs, sn};
+  }
+  const double tg = sqrt(4.0 * tin.df / *tin.moment);
+  // per-bin parts (in band: cf > 0)
+  double cf[PER], lf[PER], icf[PER];
+  float a0[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    cf[i] = 0.0;
+    lf[i] = 0.0;
+    icf[i] = 0.0;
+    a0[i] = 0.f;
+    if (kCols * P % kThreads == 0 || e < kCols * P) {
+      const int c = e % kCols, r = e / kCols;
+      const int64_t fj = j0 + c + int64_t(r) * ncols;
+      if (fj >= tin.jlo && fj <= tin.jhi) {
+        const double f = double(fj) * tin.df;
+        // f^(1/3): the FP32 root refined by one Newton step (about 46 bits)
+        double x = double(cbrtf(float(f)));
+        const float x32 = float(x);
+        x -= double(float(x * x * x - f) / (3.0f * x32 * x32));
+        cf[i] = x;
+        lf[i] = log(f);
+        icf[i] = 1.0 / x;
+        // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
+        a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
+      }
+    }
+  }
+  const int y0 = int(blockIdx.y) * TPW;
+  for (int t = 0; t < TPW && y0 + t < batch; ++t) {
+    const int y = y0 + t;
+    const Tf2Coef tc = tin.coef[y % tin.nt];
+    const float2* qs = tin.q + int64_t(y / tin.nt) * (tin.jhi - tin.jlo + 1);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (kCols * P % kThreads == 0 || e < kCols * P) {
+        const int c = e % kCols, r = e / kCols;
+        V v{0.f, 0.f};
+        if (cf[i] > 0.0) {
+          const int64_t fj = j0 + c + int64_t(r) * ncols;
+          const double vv = tc.cbrt_piM * cf[i];
+          const double lv = tc.ln_cbrt_piM + lf[i] * (1.0 / 3.0);
+          const double iv = icf[i] * tc.inv_cbrt_piM;
+          // the phase in FP64 (it reaches ~1e5 rad), reduced in FP64 to psi / pi - 2k in
+          // [-1, 1]; the exponential of the reduced angle and the amplitude need only FP32
+          const double psi = tf2_phase_v(tc, vv, lv, iv);
+          const double k = rint(psi * 0.15915494309189533577);
+          const float x = float(fma(psi, 0.31830988618379067154, -2.0 * k));
+          float sn, cs;
+          sincospi_f32(x, &sn, &cs);
+          const float2 q = qs[fj - tin.jlo];
+          v = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
+        }
+        s[c][sw(r)] = v;
+      }
+    }
+    __syncthreads();
+    inner_dft<float, P, 1>(s, tw);
+    // out[j P + q]: the block's 16 columns are one contiguous run
+    float2* o = out + int64_t(y) * n;
+    for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
+      const int q = e % P, c = e / P;
+      o[(j0 + c) * P + q] = s[c][sw(q)];
+    }
+    __syncthreads();
   }
 }
 
@@ -290,6 +394,30 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
   RF_HIP(hipGetLastError());
 }
 
+// first pass of matched filters: templates per workgroup
+constexpr int kTmplPerBlock = 4;
+
+void launch_tmpl_pass(int bits, float2* out, int64_t n, int batch, hipStream_t st, const TmplIn& tin) {
+  const int64_t P = int64_t(1) << bits;
+  dim3 grid(unsigned((n / P) / kCols), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
+  switch (bits) {
+#define RF_TMPL_CASE(B)                                                                                 \
+  case B:                                                                                               \
+    hipLaunchKernelGGL((k_fft_tmpl_pass<(1 << B), kTmplPerBlock>), grid, dim3(kThreads), 0, st, out, n, \
+                       batch, tin);                                                                     \
+    break;
+    RF_TMPL_CASE(4)
+    RF_TMPL_CASE(5)
+    RF_TMPL_CASE(6)
+    RF_TMPL_CASE(7)
+    RF_TMPL_CASE(8)
+#undef RF_TMPL_CASE
+    default:
+      throw Error{RF_E_UNSUPPORTED, "fft: unsupported pass size"};
+  }
+  RF_HIP(hipGetLastError());
+}
+
 template <typename T>
 void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
                  int batch, typename C2<T>::t* wsa_in, typename C2<T>::t* wsb_in, const BandIn* band = nullptr,
@@ -317,7 +445,7 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
         if (band)
           launch_pass<T, kBand>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
         else
-          launch_pass<T, kTmpl>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, BandIn{}, *tmpl);
+          launch_tmpl_pass(bits[i], dst, n, batch, ctx->stream, *tmpl);
         ns <<= bits[i];
         src = dst;
         continue;

@@ -115,20 +115,21 @@ struct Tf2Coef {
   double a2, a3, a4, a5c, a5l, a6c, a6l, a7;
   double amp;      // Mc^(5/6)
   double cbrt_piM; // (pi M)^(1/3)
+  double ln_cbrt_piM, inv_cbrt_piM;   // ln and reciprocal of (pi M)^(1/3)
 };
 Tf2Coef tf2_coef(const rf_tmpl& t);
 
-// Psi at v = (pi M f)^(1/3), FP64 (the phase reaches ~1e5 rad in band).
-__device__ inline double tf2_phase(const Tf2Coef& c, double v) {
-  const double lv = log(v);
+// Psi at v = (pi M f)^(1/3) with lv = ln v and iv = 1 / v supplied, FP64 (the
+// phase reaches ~1e5 rad in band).
+__device__ inline double tf2_phase_v(const Tf2Coef& c, double v, double lv, double iv) {
   const double v2 = v * v;
-  const double iv = 1.0 / v;
   const double iv5 = iv * iv * iv * iv * iv;
   const double poly =
       1.0 + v2 * (c.a2 + v * (c.a3 + v * (c.a4 + v * ((c.a5c + c.a5l * lv) +
                                                        v * ((c.a6c + c.a6l * lv) + v * c.a7)))));
   return -0.25 * 3.14159265358979323846 + c.pref * poly * iv5;
 }
+__device__ inline double tf2_phase(const Tf2Coef& c, double v) { return tf2_phase_v(c, v, log(v), 1.0 / v); }
 double tf2_dtdf(const Tf2Coef& c, double f);   // t'(f) = Psi''(f) / (2 pi)
 double tf2_t(const Tf2Coef& c, double f);      // t(f)  = Psi'(f) / (2 pi)
 

@@ -44,6 +44,8 @@ Tf2Coef tf2_coef(const rf_tmpl& t) {
   c.a7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * e2);
   c.amp = std::pow(mc, 5.0 / 6.0);
   c.cbrt_piM = std::cbrt(c.piM);
+  c.ln_cbrt_piM = std::log(c.cbrt_piM);
+  c.inv_cbrt_piM = 1.0 / c.cbrt_piM;
   return c;
 }
 
