@@ -105,6 +105,7 @@ template <typename V> struct Dft<V, 8> {
 
 constexpr int kThreads = 256;
 constexpr int kCols = 16;
+static_assert(kThreads % kCols == 0, "a thread keeps one column through every loop of a pass");
 
 // LDS layout of a block's columns: element x of a column at x + x / 32 (one
 // pad slot every 32 elements), columns lds_stride apart.  With 64 banks of 4
@@ -244,13 +245,15 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   inner_dft<T, P, 1>(s, tw);
   if constexpr (RO) {
     static_assert(std::is_same<T, float>::value && MODE == kPlain, "read-out: FP32 passes after the first");
-    // output m = (j / ns) ns P + j mod ns + q ns, as in the store below
+    // output m = (j / ns) ns P + j mod ns + q ns, as in the store below (< n <= 2^24); a
+    // thread's column c is fixed and its q rises along the loop
     Best best{-1.f, INT32_MAX};
+    const int64_t jt = j0 + (threadIdx.x % kCols);
+    const int32_t base = int32_t((jt / ns) * ns * P + (jt & (ns - 1)));
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
       const int c = e % kCols, q = e / kCols;
-      const int64_t j = j0 + c;
       const V z = s[c][sw(q)];
-      peak_visit(best, z.x, z.y, (j / ns) * ns * P + (j & (ns - 1)) + int64_t(q) * ns, po);
+      peak_visit_rising(best, z.x, z.y, base + q * int32_t(ns), po);
     }
     peak_commit(best, po);
     return;

@@ -57,11 +57,8 @@ struct PeakOut {
   int32_t tmpl0;   // added to blockIdx.y for the template of a peak or trigger
 };
 
-// One sample of a read-out: running peak and threshold crossing (series
-// tmpl0 + blockIdx.y of the launch).
-__device__ inline void peak_visit(Best& best, float re, float im, int64_t m, const PeakOut& po) {
-  const float a2 = abs2_rn(re, im);
-  best = better(best, Best{a2, int32_t(m)});
+// Threshold crossing of one sample (series tmpl0 + blockIdx.y of the launch).
+__device__ inline void crossing(float a2, float re, float im, int64_t m, const PeakOut& po) {
   if (a2 > po.thr2) {
     const unsigned long long slot_t = atomicAdd(po.count, 1ull);
     if (int64_t(slot_t) < po.cap) {
@@ -74,6 +71,25 @@ __device__ inline void peak_visit(Best& best, float re, float im, int64_t m, con
       po.trig[slot_t] = tr;
     }
   }
+}
+
+// One sample of a read-out: running peak and threshold crossing.
+__device__ inline void peak_visit(Best& best, float re, float im, int64_t m, const PeakOut& po) {
+  const float a2 = abs2_rn(re, im);
+  best = better(best, Best{a2, int32_t(m)});
+  crossing(a2, re, im, m, po);
+}
+
+// The same for samples one thread visits in rising index order: a strictly
+// larger |z|^2 replaces the running peak, so among equal values the first
+// (smallest) index stays, as better() keeps it.
+__device__ inline void peak_visit_rising(Best& best, float re, float im, int32_t m, const PeakOut& po) {
+  const float a2 = abs2_rn(re, im);
+  if (a2 > best.a2) {
+    best.a2 = a2;
+    best.idx = m;
+  }
+  crossing(a2, re, im, m, po);
 }
 
 // A workgroup's running peaks (every thread's) merged into packed[seg * nk +
