@@ -472,6 +472,71 @@ def bank_leg(dev, ctx, w, psd):
                 kernel_taps_total=dep_taps)
 
 
+def factored_batched_leg(dev, max_set=256, tol=2e-6):
+    """The factored form at the batched workload's full shape (8 x 256 s at
+    4096 Hz, 64 references, 10,136 kernels): each reference's neighbours in sets
+    of at most 256 consecutive lattice points, each set with its own basis
+    (kernel and basis builds timed apart); per segment and reference, the
+    reference matched filter and the factored reconstruction of every set with
+    the fused read-out (series not stored).  The peaks of every series are
+    compared with direct matched filtering of the same templates (read-out in
+    the transform), which is timed over the same segments."""
+    wb = synth.workload_batched()
+    g = wb["grid"]
+    nseg = len(wb["segments"])
+    stream = torch.cuda.current_stream(dev)
+    ctx = rf.Context(0, stream)
+    psd = torch.from_numpy(wb["psd"]).to(dev)
+    xf = torch.from_numpy(np.stack(wb["segments"])).to(dev)
+    zref = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
+    t_build = t_rec = t_direct = 0.0
+    jvals, resid, err = [], [], 0.0
+    nser = 0
+    for r, (ref, grp) in enumerate(zip(wb["refs"], wb["groups"])):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sets = []
+        for a in range(0, len(grp), max_set):
+            K = rf.ratio_kernel_build(ctx, g, psd, ref, list(grp[a:a + max_set]))
+            F = rf.Factored(ctx, K, g, tol=tol, jmax=128)
+            inf = F.info()
+            jvals.append(inf["J"])
+            resid.append(max(inf["resid"]))
+            sets.append((K, F))
+        torch.cuda.synchronize()
+        t_build += time.perf_counter() - t0
+        pk = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_ in range(nseg):
+            rf.mf_ref_snr(ctx, g, xf[s_], psd, [ref], z=zref, want_sigma=False)
+            for K, F in sets:
+                pk.append(F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)["peaks"])
+        torch.cuda.synchronize()
+        t_rec += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dpk = [rf.mf_snr_peaks(ctx, g, xf[s_], psd, list(grp), 6.0, trig_cap=1 << 18)["peaks"] for s_ in range(nseg)]
+        torch.cuda.synchronize()
+        t_direct += time.perf_counter() - t0
+        for s_ in range(nseg):
+            fv = np.concatenate([rf.decode_peaks(p)[0] for p in pk[s_ * len(sets):(s_ + 1) * len(sets)]])
+            dv = rf.decode_peaks(dpk[s_])[0]
+            err = max(err, float(np.abs(fv - dv).max()))
+            nser += len(grp)
+        for K, F in sets:
+            F.free()
+            K.free()
+    ktot = sum(len(x) for x in wb["groups"])
+    samples = (ktot + len(wb["refs"])) * g.n * nseg
+    ctx.close()
+    return dict(workload=f"batched-{nseg}seg-256s-4096Hz-{len(wb['refs'])}ref-{ktot}kernels", sets=len(jvals),
+                J_min=min(jvals), J_max=max(jvals), J_mean=float(np.mean(jvals)), resid_max=float(max(resid)),
+                build_s=t_build, recon_s=t_rec, value=samples / t_rec, unit="template-samples/s",
+                direct_s=t_direct, direct_value=samples / t_direct, series_checked=nser,
+                peak_err_vs_direct=err, within_2e_4=err <= 2e-4,
+                note="per-(segment, reference) calls: reference MF + factored reconstruction of each set")
+
+
 def stress_leg(dev, ctx):
     """Next-generation-detector shape: 2048 s at 4096 Hz (2^23 samples), f_low
     10 Hz, 4 references x 1024 lattice neighbours (kernels of 16k-28k taps).
@@ -928,7 +993,7 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma list of legs: headline (the batched workload at full shape), and on the "
                          "realistic workload step,fp32,direct,factored,ols,bank,learned, then batched (reduced), "
-                         "stress (default: all of these); sweep only when named")
+                         "factored_batched, stress (default: all of these); sweep only when named")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -937,7 +1002,7 @@ def main():
               "(the per-GPU workload is independent; see the sharding design).", file=sys.stderr)
         sys.exit(2)
     legs = set(args.only.split(",")) if args.only else {"headline", "step", "fp32", "direct", "factored", "ols",
-                                                        "bank", "batched", "learned", "stress"}
+                                                        "bank", "batched", "factored_batched", "learned", "stress"}
     if not args.no_cpu:
         legs.add("cpu")
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -992,6 +1057,9 @@ def main():
     if "batched" in legs:
         log("bench: batched uneven workload (reduced)")
         extra["batched_reduced"] = batched_leg(dev)
+    if "factored_batched" in legs:
+        log("bench: factored form at the batched workload's full shape")
+        extra["factored_batched"] = factored_batched_leg(dev)
     if "stress" in legs:
         log("bench: next-generation-detector shape (4 x 1024 templates, 2^23 samples)")
         ctx = rf.Context(0, torch.cuda.current_stream(dev))
