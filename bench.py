@@ -539,13 +539,14 @@ def factored_batched_leg(dev, max_set=256, tol=2e-6):
 
 def stress_leg(dev, ctx):
     """Next-generation-detector shape: 2048 s at 4096 Hz (2^23 samples), f_low
-    10 Hz, 4 references x 1024 lattice neighbours (kernels of 16k-28k taps).
+    10 Hz, 4 references x 1024 lattice neighbours (kernels of 10.8k-67k taps).
     Per reference: its matched filter + fused split-FP16 reconstruction of the
     1024 series (peaks and triggers, series not stored: 4096 x 2^23 complex64
     would be 275 GB), against direct FFT matched filtering of the same 4096
     templates with the same read-out, the blocked frequency-domain form and the
-    factored form (four 256-kernel sets per reference, peaks checked against
-    direct matched filtering); kernel builds timed apart.  The learned
+    factored form (one 1024-kernel set per reference, its basis up to 512
+    vectors, peaks checked against direct matched filtering); kernel builds
+    timed apart.  The learned
     kernels are not used here: a surrogate trained at f_low = 20 Hz does not
     transfer to this band (every kernel would take the exact fallback)."""
     w = synth.workload_stress()
@@ -596,38 +597,31 @@ def stress_leg(dev, ctx):
             rf.mf_ref_snr(ctx, g, xf, psd, part, z=zb, want_sigma=False)
             pk_direct.append(rf.decode_peaks(rf.snr_peaks(ctx, zb[:len(part)], 1e9)["peaks"])[0])
     pk_direct = np.concatenate(pk_direct)
-    # factored form: the library's basis covers up to 256 kernels, so each reference's 1024
-    # neighbours form four sets of 256 (consecutive lattice points), each with its own basis
-    t0 = time.perf_counter()
-    fsets = []
+    # factored form: each reference's 1024 neighbours form one set with its own basis (up to
+    # 512 vectors); sets are built, run and freed one reference at a time (the basis
+    # correlations of a set take J x 64 MiB)
+    t_fbuild = t_fact = 0.0
+    fpk, jinfo = [], []
     for r, grp in zip(w["refs"], w["groups"]):
-        sets = []
-        for a in range(0, len(grp), 256):
-            Kg = rf.ratio_kernel_build(ctx, g, psd, r, list(grp[a:a + 256]))
-            sets.append((Kg, rf.Factored(ctx, Kg, g, tol=2e-6)))
-        fsets.append(sets)
-    torch.cuda.synchronize()
-    t_fbuild = time.perf_counter() - t0
-    fpk = []
-
-    def factored(collect=False):
-        for r, sets in zip(w["refs"], fsets):
-            rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
-            for Kg, F in sets:
-                o = F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)
-                if collect:
-                    fpk.append(rf.decode_peaks(o["peaks"])[0])
-
-    factored(collect=True)
-    t_fact, _ = timed(factored, 1, 0, stream)
-    jinfo = [F.info() for sets in fsets for _, F in sets]
-    for sets in fsets:
-        for Kg, F in sets:
-            F.free()
-            Kg.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = rf.Factored(ctx, ksets[w["refs"].index(r)], g, tol=2e-6, jmax=512)
+        torch.cuda.synchronize()
+        t_fbuild += time.perf_counter() - t0
+        jinfo.append(F.info())
+        rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
+        o = F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rf.mf_ref_snr(ctx, g, xf, psd, [r], z=zref, want_sigma=False)
+        o = F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)
+        torch.cuda.synchronize()
+        t_fact += time.perf_counter() - t0
+        fpk.append(rf.decode_peaks(o["peaks"])[0])
+        F.free()
     fact = dict(sets=len(jinfo), J_min=min(i["J"] for i in jinfo), J_max=max(i["J"] for i in jinfo),
-                resid_max=float(max(max(i["resid"]) for i in jinfo)), build_s=t_fbuild, ms=t_fact,
-                value=(len(lens) + len(w["refs"])) * g.n / (t_fact * 1e-3),
+                resid_max=float(max(max(i["resid"]) for i in jinfo)), build_s=t_fbuild, ms=t_fact * 1e3,
+                value=(len(lens) + len(w["refs"])) * g.n / t_fact,
                 peak_err_vs_direct=float(np.abs(np.concatenate(fpk) - pk_direct).max()))
     fact["within_2e-4"] = fact["peak_err_vs_direct"] <= 2e-4
     ntpl = len(lens) + len(w["refs"])

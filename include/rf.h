@@ -345,8 +345,11 @@ typedef struct rf_factored rf_factored;
 /* Basis of the kernel set K for series of grid->n samples (a multiple of 256)
  * and grid's band.  J is the smallest basis size whose largest per-kernel
  * relative residual ||w_k - w~_k|| / ||w_k|| is at most tol, capped at jmax
- * (1..128) and at the number of kernels (1..256); tol <= 0 takes the cap.
- * Synchronises. */
+ * (1..512) and at the number of kernels (1..1024); tol <= 0 takes the cap.
+ * Sets of more than 256 kernels or 128 basis vectors mix in split FP16 only,
+ * by a tiled product (128 kernels x 128 times per workgroup); the basis
+ * correlations take J x n complex64 of device memory, the basis spectra
+ * J x (band bins).  Synchronises. */
 rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* grid, double tol, int32_t jmax,
                             rf_factored** out);
 /* Host copies (any may be NULL): basis size J, union support (first tap m0,
@@ -359,8 +362,9 @@ rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_
  * is); prec selects the mixing product: RF_PREC_FP32 (FP32 matrix cores) or
  * RF_PREC_SPLIT_FP16 (hi/lo FP16 parts of both operands after power-of-two
  * scales, three products, FP32 accumulation); the basis transforms are FP32
- * either way.  z_out device complex64 [nk][n] or NULL; fused read-out as in
- * snr_reconstruct.  Synchronises when fused. */
+ * either way (RF_E_UNSUPPORTED for RF_PREC_FP32 on a large set).  z_out
+ * device complex64 [nk][n] or NULL; fused read-out as in snr_reconstruct.
+ * Synchronises when fused. */
 rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec,
                                    void* z_out, const rf_peak_args* fused);
 rf_status rf_factored_free(rf_factored* F);

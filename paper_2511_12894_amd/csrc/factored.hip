@@ -39,6 +39,12 @@ struct rf_factored {
   // split-FP16 mixing: the coefficients as hi/lo FP16 B operand fragments
   // [JP/16][8 tiles][2 planes][64 lanes][8 basis indices] after the scale cscale
   _Float16* Cp = nullptr;
+  // large sets (more than 256 kernels or 128 basis vectors): the same hi/lo
+  // coefficients as [JP/16][KPL kernels][2 planes][16 basis indices], KPL a
+  // multiple of 128, for the tiled mixing
+  _Float16* CpL = nullptr;
+  int32_t KPL = 0;
+  bool large = false;
   uint32_t* zmax = nullptr;  // max(|re|, |im|) of the series being reconstructed (float bits)
   float l1max = 0.f;         // largest L1 norm of a basis vector
   float cscale = 1.f;        // power-of-two scale of the packed coefficients
@@ -138,7 +144,9 @@ __global__ void k_band_gather(const double2* __restrict__ in, int64_t n, int64_t
 // crossings are recorded with the raw (re, im) and finished by a pass over the
 // trigger list.  Persistent over time blocks.
 constexpr int kMixTimesMax = 256;                // n must be a multiple of this
-constexpr int kMixTiles = 8;                     // kernel tiles per set (up to 256 kernels)
+constexpr int kMixTiles = 8;                     // kernel tiles of the small-set mixings (up to 256 kernels)
+constexpr int kFactMaxKernels = 1024;             // kernels per set
+constexpr int kFactMaxBasis = 512;                // basis vectors per set
 // two waves per SIMD (one hides the other's loads) sweeping 2 tiles at a time
 // while the fragments fit in 256 registers, else one wave sweeping 4
 template <int JP>
@@ -475,6 +483,209 @@ __global__ __launch_bounds__(64 * mix16_waves<JP>(), 1) void k_mix16(const float
   }
 }
 
+// Split-FP16 mixing of large sets (more than 256 kernels or 128 basis
+// vectors), tiled as a matrix product: a workgroup owns 128 kernels and sweeps
+// its share of the time axis 128 times at a time; per 16 basis indices it
+// stages the coefficients (128 kernels x 16, hi and lo FP16 parts) and the
+// basis correlations (16 x 128 times, real and imaginary, split into hi and lo
+// after the scale s_y) in LDS, double-buffered, and each of its four waves
+// takes a 64-kernel x 64-time block as 2 x 2 products of 32 x 32 on
+// v_mfma_f32_32x32x16_f16 (rows kernels, columns times, three products per
+// term, real and imaginary parts apart).  The read-out keeps each kernel's
+// running peak key as LDS atomics over the workgroup's times, flushed to one
+// global atomic per kernel at the end; crossings as in the other mixings.
+constexpr int kLgTimes = 128;                     // times per tile (n must be a multiple)
+constexpr int kLgKern = 128;                      // kernels per workgroup
+constexpr int kLgCStride = 40;                    // halves per kernel row of a C stage (2 x 16 + pad)
+constexpr int kLgYStride = 24;                    // halves per time row of a Y plane (16 + pad)
+constexpr int kLgSlots = 8;                       // peak-key slots per kernel
+constexpr int kLgCStage = kLgKern * kLgCStride;   // halves
+constexpr int kLgYStage = 4 * kLgTimes * kLgYStride;
+
+template <bool STORE, bool FUSED>
+__global__ __launch_bounds__(256, 1) void k_mix16L(const float2* __restrict__ Y, int64_t n, int KS,
+                                                   const _Float16* __restrict__ CpL, int KPL, int nk,
+                                                   int tiles_per_block, const uint32_t* __restrict__ zmax,
+                                                   float l1max, float cscale, float2* __restrict__ zout,
+                                                   PeakOut po) {
+  __shared__ __attribute__((aligned(16))) _Float16 cst[2][kLgCStage];
+  __shared__ __attribute__((aligned(16))) _Float16 yst[2][kLgYStage];
+  __shared__ unsigned long long keys[FUSED ? kLgKern * kLgSlots : 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int kh = wave & 1, th = wave >> 1;            // this wave: kernels 64 kh.., times 64 th..
+  const int ktile = blockIdx.x;                        // kernels 128 ktile ..
+  const int64_t ntt = n / kLgTimes;
+  const int64_t tt0 = int64_t(blockIdx.y) * tiles_per_block;
+  const int64_t tt1 = tt0 + tiles_per_block < ntt ? tt0 + tiles_per_block : ntt;
+  if (FUSED)
+    for (int e = threadIdx.x; e < kLgKern * kLgSlots; e += 256) keys[e] = 0ull;
+  const float sy = y_scale(zmax, l1max);
+  const float inv = 1.f / (sy * cscale);
+  // staging roles: C rows (thread t: kernel t / 2, plane t % 2, 16 halves = 32 bytes);
+  // Y (thread t: time t % 128, basis indices 8 (t / 128) .. + 7)
+  const _Float16* csrc = CpL + (int64_t(ktile) * kLgKern + (threadIdx.x >> 1)) * 32 + (threadIdx.x & 1) * 16;
+  const int yt = threadIdx.x & (kLgTimes - 1), yg = threadIdx.x >> 7;
+  uint4 creg[2];
+  float2 yreg[8];
+  auto load = [&](int64_t tt, int ks) {
+    const uint4* cp = reinterpret_cast<const uint4*>(csrc + int64_t(ks) * KPL * 32);
+    creg[0] = cp[0];
+    creg[1] = cp[1];
+    const float2* yp = Y + int64_t(16 * ks + 8 * yg) * n + tt * kLgTimes + yt;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) yreg[q] = yp[int64_t(q) * n];
+  };
+  auto put = [&](int b) {
+    uint4* cd = reinterpret_cast<uint4*>(&cst[b][(threadIdx.x >> 1) * kLgCStride + (threadIdx.x & 1) * 16]);
+    cd[0] = creg[0];
+    cd[1] = creg[1];
+    half8 p[4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float re = yreg[q].x * sy, im = yreg[q].y * sy;
+      const _Float16 rh = _Float16(re), ih = _Float16(im);
+      p[0][q] = rh;
+      p[1][q] = _Float16(re - float(rh));
+      p[2][q] = ih;
+      p[3][q] = _Float16(im - float(ih));
+    }
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl)
+      *reinterpret_cast<half8*>(&yst[b][(pl * kLgTimes + yt) * kLgYStride + 8 * yg]) = p[pl];
+  };
+  const int kr = lane & 31, kq = 8 * (lane >> 5);
+  for (int64_t tt = tt0; tt < tt1; ++tt) {
+    floatx16 acc[2][2][2];                            // [kernel tile][time tile][re, im]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        acc[a][b][0] = floatx16{};
+        acc[a][b][1] = floatx16{};
+      }
+    load(tt, 0);
+    __syncthreads();                                  // the previous tile's readers are done
+    put(0);
+    __syncthreads();
+    for (int ks = 0; ks < KS; ++ks) {
+      const int buf = ks & 1;
+      if (ks + 1 < KS) load(tt, ks + 1);
+      half8 ch[2], cl[2], yv[2][4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const _Float16* row = &cst[buf][(64 * kh + 32 * a + kr) * kLgCStride + kq];
+        ch[a] = *reinterpret_cast<const half8*>(row);
+        cl[a] = *reinterpret_cast<const half8*>(row + 16);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+          yv[b][pl] = *reinterpret_cast<const half8*>(
+              &yst[buf][(pl * kLgTimes + 64 * th + 32 * b + kr) * kLgYStride + kq]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch[a], yv[b][0], acc[a][b][0], 0, 0, 0);
+          acc[a][b][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch[a], yv[b][2], acc[a][b][1], 0, 0, 0);
+          acc[a][b][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cl[a], yv[b][0], acc[a][b][0], 0, 0, 0);
+          acc[a][b][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cl[a], yv[b][2], acc[a][b][1], 0, 0, 0);
+          acc[a][b][0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch[a], yv[b][1], acc[a][b][0], 0, 0, 0);
+          acc[a][b][1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ch[a], yv[b][3], acc[a][b][1], 0, 0, 0);
+        }
+      if (ks + 1 < KS) {
+        put(buf ^ 1);
+        __syncthreads();
+      }
+    }
+    // epilogue: register i of lane l holds kernel 32 tile + acc_row(i, l), time 32 tile + l % 32
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int64_t m = tt * kLgTimes + 64 * th + 32 * b + kr;
+        const int kb = ktile * kLgKern + 64 * kh + 32 * a;       // + acc_row(i, lane)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          acc[a][b][0][i] *= inv;
+          acc[a][b][1][i] *= inv;
+        }
+        if (STORE) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int k = kb + acc_row(i, lane);
+            if (k < nk) zout[int64_t(k) * n + m] = make_float2(acc[a][b][0][i], acc[a][b][1][i]);
+          }
+        }
+        if (FUSED) {
+          uint32_t cross = 0;
+          const unsigned long long ikey = 0xFFFFFFFFu - uint32_t(m);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int kl = 64 * kh + 32 * a + acc_row(i, lane);
+            if (kb - 64 * kh - 32 * a + kl < nk) {
+              const float a2 = abs2_rn(acc[a][b][0][i], acc[a][b][1][i]);
+              atomicMax(&keys[kl * kLgSlots + (kr & (kLgSlots - 1))],
+                        (unsigned long long)(uint64_t(__float_as_uint(a2)) << 32) | ikey);
+              if (a2 > po.thr2) cross |= 1u << i;
+            }
+          }
+          if (cross) {
+#pragma unroll 1
+            for (int i = 0; i < 16; ++i)
+              if ((cross >> i) & 1u) {
+                const unsigned long long sl = atomicAdd(po.count, 1ull);
+                if (int64_t(sl) < po.cap) {
+                  rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
+                  tr.tmpl = kb + acc_row(i, lane);
+                  tr.seg = po.seg;
+                  tr.idx = int32_t(m);
+                  tr.absz = acc[a][b][0][i];
+                  tr.argz = acc[a][b][1][i];
+                  po.trig[sl] = tr;
+                }
+              }
+          }
+        }
+      }
+  }
+  if (FUSED) {
+    __syncthreads();
+    for (int kl = threadIdx.x; kl < kLgKern; kl += 256) {
+      const int k = ktile * kLgKern + kl;
+      if (k >= nk) continue;
+      unsigned long long b = 0ull;
+      for (int s2 = 0; s2 < kLgSlots; ++s2) b = max(b, keys[kl * kLgSlots + s2]);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
+    }
+  }
+}
+
+void mix16L_launch(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& po, bool fused) {
+  int dev = 0, cus = 0;
+  RF_HIP(hipGetDevice(&dev));
+  RF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int ktiles = F->KPL / kLgKern;
+  const int64_t ntt = F->n / kLgTimes;
+  // about two workgroups per CU over all kernel tiles, each over a contiguous run of time tiles
+  const int64_t ny = std::max<int64_t>(1, std::min<int64_t>(ntt, (2 * int64_t(cus) + ktiles - 1) / ktiles));
+  const int per = int((ntt + ny - 1) / ny);
+  const dim3 grid(unsigned(ktiles), unsigned((ntt + per - 1) / per));
+  const int KS = F->JP / 16;
+  const _Float16* Cp = F->CpL;
+  if (zout && fused)
+    hipLaunchKernelGGL((k_mix16L<true, true>), grid, dim3(256), 0, ctx->stream, F->Y, F->n, KS, Cp, F->KPL, F->nk,
+                       per, F->zmax, F->l1max, F->cscale, zout, po);
+  else if (zout)
+    hipLaunchKernelGGL((k_mix16L<true, false>), grid, dim3(256), 0, ctx->stream, F->Y, F->n, KS, Cp, F->KPL, F->nk,
+                       per, F->zmax, F->l1max, F->cscale, zout, po);
+  else
+    hipLaunchKernelGGL((k_mix16L<false, true>), grid, dim3(256), 0, ctx->stream, F->Y, F->n, KS, Cp, F->KPL, F->nk,
+                       per, F->zmax, F->l1max, F->cscale, zout, po);
+  RF_HIP(hipGetLastError());
+}
+
 template <int JP>
 void mix16_launch_jp(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& po, bool fused) {
   constexpr int KS = JP / 16;
@@ -559,7 +770,7 @@ void mix_launch(rf_ctx* ctx, const rf_factored* F, float2* zout, const PeakOut& 
 void free_factored(rf_factored* F) {
   if (!F) return;
   for (void* p : {(void*)F->Ub, (void*)F->C, (void*)F->Q, (void*)F->Qin, (void*)F->Y, (void*)F->Cp,
-                  (void*)F->zmax})
+                  (void*)F->CpL, (void*)F->zmax})
     if (p) (void)hipFree(p);
   delete F;
 }
@@ -587,8 +798,8 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     validate_grid(grid);
     RF_CHECK(K && out, "rf_factored_build: null pointer");
     *out = nullptr;
-    RF_CHECK(K->nk >= 1 && K->nk <= 32 * kMixTiles, "rf_factored_build: 1 to 256 kernels per set");
-    RF_CHECK(jmax >= 1 && jmax <= 128, "rf_factored_build: jmax must be in [1, 128]");
+    RF_CHECK(K->nk >= 1 && K->nk <= kFactMaxKernels, "rf_factored_build: 1 to 1024 kernels per set");
+    RF_CHECK(jmax >= 1 && jmax <= kFactMaxBasis, "rf_factored_build: jmax must be in [1, 512]");
     RF_CHECK(std::isfinite(tol), "rf_factored_build: bad tolerance");
     const int nk = K->nk;
     const int64_t n = grid->n;
@@ -662,7 +873,9 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
     }
     F->J = J;
     F->JP = ((J + 15) / 16) * 16;
-    F->KP = 32 * kMixTiles;
+    F->large = nk > 32 * kMixTiles || F->JP > 128;
+    F->KPL = ((nk + kLgKern - 1) / kLgKern) * kLgKern;
+    F->KP = F->large ? F->KPL : 32 * kMixTiles;
     F->lambda = lam;
     F->resid = res;
     // basis b_j = sum_k V[k][j] w_k: B [J][L] = V_J^T W
@@ -717,16 +930,34 @@ rf_status rf_factored_build(rf_ctx* ctx, const rf_kernels* K, const rf_grid* gri
         ch[size_t(j) * F->KP + k] = float(c);
         cmax = std::max(cmax, std::fabs(c));
       }
-    F->C = dev_alloc<float>(ch.size(), "factored: device allocation failed");
-    copy_sync(ctx, F->C, ch.data(), sizeof(float) * ch.size(), hipMemcpyHostToDevice);
+    if (!F->large) {
+      F->C = dev_alloc<float>(ch.size(), "factored: device allocation failed");
+      copy_sync(ctx, F->C, ch.data(), sizeof(float) * ch.size(), hipMemcpyHostToDevice);
+    }
     // the same, split into FP16 hi + lo after a power-of-two scale (largest
-    // scaled value in [2^13, 2^14)), in the B operand layout of the 32x32x16
-    // product: lane l of k-step ks, tile t holds C[16 ks + 8 (l / 32) + q][32 t + l % 32]
-    {
-      int e = 0;
-      std::frexp(cmax > 0 ? cmax : 1.0, &e);
-      const double cs = std::ldexp(1.0, 14 - e);
-      F->cscale = float(cs);
+    // scaled value in [2^13, 2^14)).  Small sets: in the operand layout of the
+    // 32x32x16 product, lane l of k-step ks, tile t holds
+    // C[16 ks + 8 (l / 32) + q][32 t + l % 32]; large sets: [ks][kernel][plane][16].
+    int e2 = 0;
+    std::frexp(cmax > 0 ? cmax : 1.0, &e2);
+    const double cs = std::ldexp(1.0, 14 - e2);
+    F->cscale = float(cs);
+    if (F->large) {
+      const int KS = F->JP / 16;
+      std::vector<_Float16> cp(size_t(KS) * F->KPL * 32);
+      for (int ks = 0; ks < KS; ++ks)
+        for (int k = 0; k < F->KPL; ++k)
+          for (int b = 0; b < 16; ++b) {
+            const double c = cd[size_t(16 * ks + b) * F->KP + k] * cs;
+            const _Float16 hi = _Float16(float(c));
+            const _Float16 lo = _Float16(float(c - double(float(hi))));
+            const size_t base = (size_t(ks) * F->KPL + k) * 32 + b;
+            cp[base] = hi;
+            cp[base + 16] = lo;
+          }
+      F->CpL = dev_alloc<_Float16>(cp.size(), "factored: device allocation failed");
+      copy_sync(ctx, F->CpL, cp.data(), sizeof(_Float16) * cp.size(), hipMemcpyHostToDevice);
+    } else {
       const int KS = F->JP / 16;
       std::vector<_Float16> cp(size_t(KS) * kMixTiles * 2 * 64 * 8);
       for (int ks = 0; ks < KS; ++ks)
@@ -777,6 +1008,9 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
     RF_CHECK(F && z_ref, "snr_reconstruct_factored: null pointer");
     RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct_factored: unknown precision");
     RF_CHECK(n == F->n, "snr_reconstruct_factored: series length differs from the build");
+    if (F->large && prec != RF_PREC_SPLIT_FP16)
+      throw Error{RF_E_UNSUPPORTED, "snr_reconstruct_factored: sets of more than 256 kernels or 128 basis "
+                                    "vectors mix in split FP16 only"};
     RF_CHECK(z_out || fused, "snr_reconstruct_factored: need z_out or fused read-out");
     if (fused) {
       RF_CHECK(fused->peaks && fused->ntrig && fused->cap >= 0 && (fused->cap == 0 || fused->trig),
@@ -801,9 +1035,15 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
                        n, F->Qin, F->zmax);
     RF_HIP(hipGetLastError());
     fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
-    // basis correlations: the band products formed inside the first transform pass
-    fft_inverse_band_f32(ctx, F->Q, F->Ub, F->b0, F->nb, float(1.0 / double(n)), F->Y, n, F->J);
-    if (prec == RF_PREC_SPLIT_FP16)
+    // basis correlations: the band products formed inside the first transform pass, in
+    // batches of at most 2^28 / n transforms (bounded transform scratch)
+    const int per = int(std::max<int64_t>(1, std::min<int64_t>(F->J, (int64_t(1) << 28) / n)));
+    for (int j0 = 0; j0 < F->J; j0 += per)
+      fft_inverse_band_f32(ctx, F->Q, F->Ub + int64_t(j0) * F->nb, F->b0, F->nb, float(1.0 / double(n)),
+                           F->Y + int64_t(j0) * n, n, std::min(per, F->J - j0));
+    if (F->large)
+      mix16L_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
+    else if (prec == RF_PREC_SPLIT_FP16)
       mix16_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
     else
       mix_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);

@@ -223,3 +223,62 @@ def test_argument_errors(rf, ctx, small):
                                           small["z"].data_ptr(), None)
     assert st == rf.RF_E_INVAL
     F.free()
+
+
+@pytest.fixture(scope="module")
+def large(rf, ctx):
+    """A set of 300 lattice neighbours (more than 256 kernels: the tiled mixing)."""
+    w = synth.workload_small()
+    g = w["grid"]
+    nbrs = synth.neighbour_lattice(*w["ref"], g.f_low, 300)
+    _say("factored large set: oracle kernels")
+    zr, nr, ks, norms = _oracle_setup(w, nbrs)
+    xf, psd, K, z = _gpu_inputs(rf, ctx, w, nbrs)
+    yield dict(w=w, nbrs=nbrs, zr=zr, nr=nr, ks=ks, norms=norms, xf=xf, psd=psd, K=K, z=z)
+    K.free()
+
+
+@pytest.mark.parametrize("tol,jmax", [(2e-6, 512), (0.0, 160)])
+def test_large_set_matches_the_oracle_projection(rf, ctx, large, tol, jmax):
+    """300 kernels (and, with jmax 160, more than 128 basis vectors): the tiled
+    split-FP16 mixing against the oracle's rank-J projection of the same kernels
+    (sampled outputs, 1e-5), against direct matched filtering (every sample,
+    2e-4), and its fused read-out against the read-out of the stored series."""
+    w = large["w"]
+    g = w["grid"]
+    F = rf.Factored(ctx, large["K"], g, tol=tol, jmax=jmax)
+    info = F.info()
+    J = info["J"]
+    _say(f"large set: J = {J}, max residual {max(info['resid']):.2e}")
+    m0, Wt, res = orat.project_kernel_set([(k["m_lo"], k["taps"]) for k in large["ks"]], J)
+    assert info["m0"] == m0 and info["len"] == Wt.shape[1]
+    # the library takes the residuals from the Gram matrix's eigenvalues, whose trailing
+    # part carries absolute errors of ~1e-16 of the largest: residuals near 1e-6 agree
+    # with the oracle's SVD to ~1e-7
+    np.testing.assert_allclose(info["resid"], res, rtol=1e-3, atol=1e-7)
+    out = F.reconstruct(large["z"], fused_thr=5.0, trig_cap=1 << 16)
+    zh = out["z"].cpu().numpy()
+    rng = np.random.default_rng(9)
+    idx = np.unique(np.concatenate([rng.integers(0, g.n, 300), 40 * 1024 + np.arange(-40, 40)]))
+    err = 0.0
+    for k in list(range(0, len(large["ks"]), 13)) + [len(large["ks"]) - 1]:
+        zo = orat.reconstruct_samples(large["zr"], m0, Wt[k], large["nr"] / large["norms"][k], idx)
+        err = max(err, np.abs(zh[k, idx] - zo).max())
+    _say(f"large set J={J} vs oracle projection (sampled): {err:.3e}")
+    assert err <= 1e-5
+    if tol > 0:
+        zd, _ = rf.mf_ref_snr(ctx, g, large["xf"], large["psd"], large["nbrs"])
+        ed = (out["z"] - zd).abs().max().item()
+        _say(f"large set vs direct MF: {ed:.3e}")
+        assert ed <= 2e-4
+    ref = rf.snr_peaks(ctx, out["z"], 5.0, trig_cap=1 << 16)
+    torch.cuda.synchronize()
+    assert torch.equal(out["peaks"], ref["peaks"])
+    assert set(rf.decode_triggers(out["trig"], out["ntrig"])) == set(rf.decode_triggers(ref["trig"], ref["ntrig"]))
+    assert out["ntrig"] > 0
+    fused = F.reconstruct(large["z"], store=False, fused_thr=5.0, trig_cap=1 << 16)
+    assert torch.equal(fused["peaks"], ref["peaks"])
+    with pytest.raises(rf.RfError) as e:
+        F.reconstruct(large["z"], prec="fp32")
+    assert e.value.code == rf.RF_E_UNSUPPORTED
+    F.free()
