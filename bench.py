@@ -580,13 +580,16 @@ def stress_leg(dev, ctx):
             O.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)
 
     stream = torch.cuda.current_stream(dev)
+    log("bench: stress: overlap-save form")
     ols()
     t_ols, _ = timed(ols, 1, 0, stream)
     pmax = max(O.info()["pmax"] for O in plans)
     for O in plans:
         O.free()
+    log("bench: stress: dense split-FP16 reconstruction")
     ratio()
     t_ratio, _ = timed(ratio, 1, 0, stream)
+    log("bench: stress: direct matched filtering")
     direct()
     t_direct, _ = timed(direct, 1, 0, stream)
     # peaks of every neighbour by direct matched filtering (untimed), for the factored form's check
@@ -603,6 +606,7 @@ def stress_leg(dev, ctx):
     t_fbuild = t_fact = 0.0
     fpk, jinfo = [], []
     for r, grp in zip(w["refs"], w["groups"]):
+        log(f"bench: stress: factored set of reference {r}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = rf.Factored(ctx, ksets[w["refs"].index(r)], g, tol=2e-6, jmax=512)
