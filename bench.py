@@ -229,6 +229,7 @@ def headline_leg(dev, steps, warmup, cache_path=None):
         t0 = time.perf_counter()
         chunks = batch.autotune(xf, cache_path)
         t_tune = time.perf_counter() - t0
+        tuning = batch.tuning()
         lens = np.concatenate([k.info()["len"] for k in ksets])
         sum_l = int(lens.sum())
         corr = [k.split_steps(1024) for k in ksets]
@@ -243,7 +244,8 @@ def headline_leg(dev, steps, warmup, cache_path=None):
             rec.append(batch.last_recon_ms())
             return out
 
-        log(f"bench: headline: {ktot} kernels ({lens.min()}..{lens.max()} taps), chunks {chunks}; "
+        log(f"bench: headline: {ktot} kernels ({lens.min()}..{lens.max()} taps), tuning {tuning} "
+            f"(autotune {t_tune:.2f} s); "
             f"{warmup} warm-up + {steps} timed steps")
         for _ in range(warmup):
             step()
@@ -263,7 +265,7 @@ def headline_leg(dev, steps, warmup, cache_path=None):
     for (s_, m1, m2, snr, t0_, phi) in wb["injections"]:
         found += any(t[1] == s_ and abs(t[2] - int(round(t0_ * g.fs))) <= 8 for t in trig_list)
     res = dict(wb=wb, grid=g, nseg=nseg, ktot=ktot, nref=len(wb["refs"]), lens=lens, sum_l=sum_l,
-               corr_frac=corr_steps / max(all_steps, 1), exec_taps=all_steps * 16 * 32, chunks=chunks,
+               corr_frac=corr_steps / max(all_steps, 1), exec_taps=all_steps * 16 * 32, chunks=chunks, tuning=tuning,
                wall_ms=wall, recon_ms=rec[-steps:], build_s=t_build, tune_s=t_tune,
                captures_in_timed=cap1 - cap0, replays_in_timed=rep1 - rep0, ntrig=last["ntrig"],
                peak_max=float(vals.max()), injections_found=found)
@@ -293,6 +295,7 @@ def batched_leg(dev):
         ksets = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(wb["refs"], wb["groups"])]
         batch = rf.Batch(ctx, g, psd, wb["refs"], ksets, nseg=nseg)
         chunks = batch.autotune(xf)
+        tuning = batch.tuning()
         sum_l = sum(sum(k.info()["len"]) for k in ksets)
         peaks = torch.empty((nseg, batch.ktotal, 2), dtype=torch.int32, device=dev)
         trig = torch.empty((1 << 20, 5), dtype=torch.int32, device=dev)
@@ -322,7 +325,7 @@ def batched_leg(dev):
     flops = 4.0 * g.n * sum_l * nseg
     samples = (ktot + len(wb["refs"])) * g.n * nseg
     res = dict(workload=wb["name"] + "-reduced", segments=nseg, references=len(wb["refs"]),
-               kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks, sum_taps=sum_l,
+               kernels=ktot, neighbours_per_ref=[len(x) for x in wb["groups"]], chunks=chunks, tuning=tuning, sum_taps=sum_l,
                batch_ms=t_batch * 1e3, loop_ms=t_loop * 1e3, speedup=t_loop / t_batch,
                graph_captures_while_timed=cap1 - cap0,
                value=samples / t_batch, unit="template-samples/s",
@@ -920,6 +923,21 @@ def c2_legs(dev, args, legs):
         step("fp32")
         e32 = (zout - zall[1:]).abs().max().item()
         res["err_vs_direct"] = dict(split16=e16, fp32=e32)
+        # threshold-unit sensitivity: the same 1e-3 read per tap (|w| >= 1e-3) instead
+        # of per second (|w| >= 1e-3 / fs); shorter kernels, larger truncation error
+        log("bench: kernels thresholded at 1e-3 per tap")
+        Kt = rf.ratio_kernel_build(ctx, g, psd, w["ref"], nbrs, thr=1e-3, unit=rf.RF_THR_PER_TAP)
+        lt = np.array(Kt.info()["len"])
+        ref_mf()
+        rf.snr_reconstruct(ctx, Kt, zref[0], prec="split16", z_out=zout)
+        et = (zout - zall[1:]).abs().max().item()
+        pd = (zout.abs().amax(dim=1) - zall[1:].abs().amax(dim=1)).abs().max().item()
+        tau = rf.template_durations(nbrs, g.f_low)
+        res["per_tap"] = dict(threshold=1e-3, kernel_taps_min=int(lt.min()), kernel_taps_max=int(lt.max()),
+                              kernel_taps_sum=int(lt.sum()), err_vs_direct=et, peak_err_vs_direct=pd,
+                              storage_ratio=float(tau.sum()) / (float(lt.sum()) / g.fs),
+                              storage_ratio_per_second=float(tau.sum()) / (float(lens.sum()) / g.fs))
+        Kt.free()
         del zall
     if "factored" in legs:
         log("bench: factored reconstruction through the kernel-set basis")
@@ -970,6 +988,7 @@ def c2_legs(dev, args, legs):
                                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                          "frac": 16 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS}
         out["err_vs_direct_mf"] = res["err_vs_direct"]
+        out["threshold_per_tap"] = res["per_tap"]
     for key in ("factored", "ols", "bank", "learned"):
         if key in res:
             out[key] = res[key]
@@ -1039,7 +1058,7 @@ def main():
                          "segments": h["nseg"], "n": g.n, "fs": g.fs, "f_low": g.f_low, "f_high": g.f_high,
                          "references": h["nref"], "kernels": h["ktot"], "threshold_per_s": 1e-3,
                          "kernel_taps_min": int(h["lens"].min()), "kernel_taps_max": int(h["lens"].max()),
-                         "kernel_taps_sum": h["sum_l"], "chunks": h["chunks"],
+                         "kernel_taps_sum": h["sum_l"], "chunks": h["chunks"], "tuning": h["tuning"],
                          "precision": "split fp16 hi/lo, hi*lo + lo*hi where large taps, fp32 accumulation"}
         extra["headline"] = {"kernel_build_s": h["build_s"], "autotune_s": h["tune_s"],
                              "recon_ms_per_step": h["recon_ms"], "graph_captures_while_timed": h["captures_in_timed"],

@@ -211,7 +211,7 @@ rf_status snr_peaks(rf_ctx* ctx, const void* z, int32_t nt, int64_t n, float thr
  * reconstruction with its read-out, replayed back to back).  The graphs read
  * and write only buffers of the batch: each run copies the caller's data in
  * before the replay and the read-out out after it, so new pointers do not
- * re-capture them; a new cap or thr, or new chunk sizes, do.  Kernel k of
+ * re-capture them; a new cap or thr, or new launch settings, do.  Kernel k of
  * group r has global index kbase[r] + k.  The batch borrows psd and the kernel
  * sets' contents are copied (the sets may be freed afterwards); it owns its
  * device buffers (about 24 bytes per sample per (segment, reference)). */
@@ -222,16 +222,43 @@ typedef struct rf_batch rf_batch;
 rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, int32_t nref,
                           const rf_tmpl* refs, rf_kernels* const* ksets, int32_t nseg,
                           rf_batch** out);
+/* Launch settings of the persistent reconstruction.  Tiles (32 kernels each)
+ * fall into three length buckets: bucket 0 holds tiles of at most bucket_hi[0]
+ * 16-tap steps, bucket 1 at most bucket_hi[1], bucket 2 the rest (at creation
+ * the bounds are the tertiles of the batch's own tile lengths).  Per bucket:
+ * the window chunk (taps staged per LDS window and accumulated between FP64
+ * folds: 256, 512 or 1024; it changes the rounding order only) and the number
+ * of consecutive 256-time blocks one work item covers (1, 2 or 4).
+ * xcd_queues = 1 deals the tiles, longest first, to 8 work queues in turn (one
+ * per XCD, workgroups being dispatched to the XCDs in turn) so that a tile's
+ * operands are fetched into one XCD's L2; a workgroup drains its own queue and
+ * then takes the others' remaining items.  None of these changes a result but
+ * the chunk. */
+typedef struct {
+  int32_t chunk[3];
+  int32_t blocks[3];
+  int32_t xcd_queues;
+  int32_t pad;
+  int64_t bucket_hi[2];
+} rf_batch_tuning;
 /* Host copies (any pointer may be NULL): total kernels, work items, kbase[nref],
- * chosen chunk sizes (taps) for kernels of <= 1024, <= 8192 and longer taps. */
+ * chosen chunk sizes (taps) of the three tile-length buckets. */
 rf_status rf_batch_info(const rf_batch* b, int32_t* ktotal, int64_t* nitems, int32_t* kbase,
                         int32_t* chunk_per_bucket);
-/* Set the chunk sizes (each 256, 512 or 1024) without timing. */
+/* Set the chunk sizes (each 256, 512 or 1024) without timing, the other settings kept. */
 rf_status rf_batch_set_chunks(rf_batch* b, const int32_t* chunk_per_bucket);
-/* Time each chunk size on each kernel-length bucket's work items with the data
- * xf_segs (device complex128 [nseg][n/2+1]) and keep the fastest; when
- * cache_path is given, a line keyed by the batch's shape and the device name
- * is read if present (no timing) or appended.  Synchronises. */
+/* Read or set every launch setting (no timing); RF_E_INVAL for a value outside
+ * the sets above or bucket bounds that are negative or decreasing. */
+rf_status rf_batch_get_tuning(const rf_batch* b, rf_batch_tuning* t);
+rf_status rf_batch_set_tuning(rf_batch* b, const rf_batch_tuning* t);
+/* Choose the settings by timing with the data xf_segs (device complex128
+ * [nseg][n/2+1]): per bucket every chunk x blocks pair on the same sampled
+ * time blocks (about four per workgroup of the launch, in runs of four spread
+ * over the bucket's tiles, segments and times; best of three launches each),
+ * then one queue against one per XCD on runs of time blocks of up to eight
+ * tiles spread over the lengths; the buckets are the creation's tertiles.  When cache_path is given, a line keyed by the
+ * batch's shape and the device name is read if present (no timing) or
+ * appended.  Synchronises. */
 rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const char* cache_path);
 /* xf_segs: device complex128 [nseg][n/2+1]; peaks: device rf_peak [nseg][ktotal];
  * trig: device rf_trigger [cap] (tmpl = global kernel index, seg = segment);

@@ -7,9 +7,12 @@
 // and replayed.  The graph reads and writes only buffers the batch owns (the
 // caller's data are copied in before a replay, the read-out copied out after
 // it), so a replay does not depend on the caller's pointers.  Work items are
-// ordered longest tile first so the queue ends on short items; the chunk size
-// of each item comes from an autotuner that times the candidate chunk sizes
-// per kernel-length bucket on the device.
+// ordered longest tile first so the queues end on short items.  An autotuner
+// chooses, per tile-length bucket (bounds at the tertiles of the batch's own
+// tile lengths), the window chunk and the number of 256-time blocks per work
+// item, and whether the items sit in one queue or in one queue per XCD (tiles
+// dealt to the queues in turn, so a tile's operands stay in one XCD's L2), by
+// timing the candidates on sampled work items on the device.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -52,8 +55,16 @@ struct rf_batch {
   uint64_t* packed = nullptr;          // [nseg * ktotal] + trigger count
   uint32_t* counter = nullptr;
   int nblocks = 0;
-  // chunk size per kernel-length bucket (taps)
+  size_t items_cap = 0;                // work items the item buffer holds (one block each)
+  // tuning: window chunk (taps) and 256-time blocks per work item for each tile-length
+  // bucket, one queue or one per XCD, bucket bounds (16-tap steps)
   int chunk_for_bucket[3] = {512, 512, 512};
+  int blocks_for_bucket[3] = {1, 1, 1};
+  int xcd_queues = 0;
+  int64_t bucket_hi[2] = {64, 512};
+  int64_t bucket_hi_tertiles[2] = {64, 512};   // the bounds set at creation
+  std::vector<int32_t> order;          // tiles with work, longest first
+  rf::QueueSpec qs{};
   // buffers the captured graph reads and writes (never the caller's)
   double2* xf_own = nullptr;           // [nseg][n/2+1]: copy of the caller's data
   rf_peak* peaks_own = nullptr;        // [nseg][ktotal]
@@ -74,7 +85,9 @@ struct rf_batch {
 namespace rf {
 namespace {
 
-int bucket_of(int64_t ksteps) { return ksteps <= 64 ? 0 : (ksteps <= 512 ? 1 : 2); }
+int bucket_of(const rf_batch* b, int64_t ksteps) {
+  return ksteps <= b->bucket_hi[0] ? 0 : (ksteps <= b->bucket_hi[1] ? 1 : 2);
+}
 
 void drop_graphs(rf_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -96,8 +109,32 @@ void free_batch(rf_batch* b) {
   delete b;
 }
 
+// Work items of `tiles` (positions p in a longest-first list) over segments
+// [0, nseg) and time blocks [0, ntb), each tile's items in queue p % nq.
+void build_items(const rf_batch* b, const std::vector<int32_t>& tiles, int nq, int32_t nseg, int32_t ntb,
+                 std::vector<WorkItem>& items, QueueSpec& qs) {
+  std::vector<std::vector<WorkItem>> lists(static_cast<size_t>(nq));
+  for (size_t p = 0; p < tiles.size(); ++p) {
+    const int32_t t = tiles[p];
+    const int bk = bucket_of(b, b->htiles[t].t.ksteps);
+    const int32_t nb = b->blocks_for_bucket[bk], c = b->chunk_for_bucket[bk];
+    auto& L = lists[p % size_t(nq)];
+    for (int32_t sg = 0; sg < nseg; ++sg)
+      for (int32_t q = 0; q < ntb; q += nb) L.push_back(WorkItem{sg, t, q, c, std::min(nb, ntb - q), 0});
+  }
+  items.clear();
+  qs = QueueSpec{};
+  qs.nq = nq;
+  for (int i = 0; i < nq; ++i) {
+    items.insert(items.end(), lists[size_t(i)].begin(), lists[size_t(i)].end());
+    qs.off[i + 1] = int32_t(items.size());
+  }
+  for (int i = nq + 1; i <= kMaxQueues; ++i) qs.off[i] = int32_t(items.size());
+}
+
 void upload_items(rf_batch* b) {
-  for (auto& it : b->hitems) it.chunk = b->chunk_for_bucket[bucket_of(b->htiles[it.tile].t.ksteps)];
+  build_items(b, b->order, b->xcd_queues ? kMaxQueues : 1, b->nseg, int32_t(b->n / kTimes), b->hitems, b->qs);
+  RF_CHECK(b->hitems.size() <= b->items_cap, "batch: work list larger than its buffer");
   RF_HIP(hipMemcpy(b->items, b->hitems.data(), sizeof(WorkItem) * b->hitems.size(), hipMemcpyHostToDevice));
   drop_graphs(b);
 }
@@ -122,8 +159,8 @@ void enqueue_recon(rf_ctx* ctx, rf_batch* b, float thr, rf_peak* peaks, rf_trigg
   po.thr2 = thr * thr;
   po.seg = 0;
   po.nk = b->ktotal;
-  queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, b->items, int(b->hitems.size()),
-               b->counter, b->b16, b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
+  queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, b->items, b->qs, b->counter, b->b16,
+               b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
   peaks_finalize(ctx, b->packed, np, peaks);
 }
 
@@ -151,11 +188,16 @@ std::string signature(const rf_batch* b) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
-  int64_t counts[3] = {0, 0, 0};
-  for (const auto& t : b->htiles) counts[bucket_of(t.t.ksteps)] += t.t.ksteps;
+  int64_t steps = 0, smin = 0, smax = 0;
+  for (int32_t t : b->order) {
+    const int64_t k = b->htiles[size_t(t)].t.ksteps;
+    steps += k;
+    smin = smin == 0 ? k : std::min(smin, k);
+    smax = std::max(smax, k);
+  }
   std::ostringstream os;
-  os << "arch=" << arch << ";n=" << b->n << ";seg=" << b->nseg << ";ref=" << b->nref
-     << ";k=" << b->ktotal << ";steps=" << counts[0] << "," << counts[1] << "," << counts[2];
+  os << "arch=" << arch << ";n=" << b->n << ";seg=" << b->nseg << ";ref=" << b->nref << ";k=" << b->ktotal
+     << ";tiles=" << b->order.size() << ";steps=" << steps << "," << smin << "," << smax;
   std::string s = os.str();
   for (char& c : s)
     if (c == ' ') c = '_';
@@ -245,21 +287,28 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
       kb += K->nk;
     }
     b->ktotal = kb;
-    // work list: every (segment, tile, time block), longest tiles first
-    std::vector<int32_t> order(b->htiles.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = int32_t(i);
-    std::stable_sort(order.begin(), order.end(),
+    // work list: every (segment, tile, time block), longest tiles first; length
+    // buckets split at the tertiles of the tile lengths
+    for (size_t i = 0; i < b->htiles.size(); ++i)
+      if (b->htiles[i].t.ksteps > 0) b->order.push_back(int32_t(i));
+    std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int a, int c) { return b->htiles[a].t.ksteps > b->htiles[c].t.ksteps; });
-    const int32_t ntb = int32_t(b->n / kTimes);
-    for (int32_t t : order) {
-      if (b->htiles[t].t.ksteps == 0) continue;
-      for (int32_t s = 0; s < nseg; ++s)
-        for (int32_t q = 0; q < ntb; ++q) b->hitems.push_back(WorkItem{s, t, q, int32_t(kChunk)});
+    if (!b->order.empty()) {
+      std::vector<int64_t> ks;
+      for (int32_t t : b->order) ks.push_back(b->htiles[t].t.ksteps);
+      std::sort(ks.begin(), ks.end());
+      b->bucket_hi[0] = ks[(ks.size() - 1) / 3];
+      b->bucket_hi[1] = ks[2 * (ks.size() - 1) / 3];
     }
-    RF_CHECK(b->hitems.size() < size_t(INT32_MAX), "rf_batch_create: too many work items");
+    b->bucket_hi_tertiles[0] = b->bucket_hi[0];
+    b->bucket_hi_tertiles[1] = b->bucket_hi[1];
+    const int32_t ntb = int32_t(b->n / kTimes);
+    const double nitems = double(b->order.size()) * nseg * ntb;
+    RF_CHECK(nitems < double(INT32_MAX), "rf_batch_create: too many work items");
+    b->items_cap = std::max<size_t>(size_t(nitems), 1);
     b->tiles = dev_alloc<BatchTile>(b->htiles.size(), "batch: device allocation failed");
     RF_HIP(hipMemcpy(b->tiles, b->htiles.data(), sizeof(BatchTile) * b->htiles.size(), hipMemcpyHostToDevice));
-    b->items = dev_alloc<WorkItem>(b->hitems.size(), "batch: device allocation failed");
+    b->items = dev_alloc<WorkItem>(b->items_cap, "batch: device allocation failed");
     upload_items(b);
     b->coef = dev_alloc<Tf2Coef>(size_t(nref), "batch: device allocation failed");
     RF_HIP(hipMemcpy(b->coef, coef.data(), sizeof(Tf2Coef) * nref, hipMemcpyHostToDevice));
@@ -274,7 +323,7 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     b->maxbits = dev_alloc<uint32_t>(ns, "batch: device allocation failed");
     b->zinv = dev_alloc<float>(ns, "batch: device allocation failed");
     b->packed = dev_alloc<uint64_t>(size_t(nseg) * b->ktotal + 1, "batch: device allocation failed");
-    b->counter = dev_alloc<uint32_t>(1, "batch: device allocation failed");
+    b->counter = dev_alloc<uint32_t>(kMaxQueues, "batch: device allocation failed");
     b->nblocks = queue_blocks(ctx->device);
     // FFT scratch owned by the batch: the captured graph references it
     b->fa = dev_alloc<float2>(ns * size_t(b->n), "batch: device allocation failed");
@@ -311,13 +360,42 @@ rf_status rf_batch_info(const rf_batch* b, int32_t* ktotal, int64_t* nitems, int
 
 rf_status rf_batch_set_chunks(rf_batch* b, const int32_t* chunk_per_bucket) {
   if (!b || !chunk_per_bucket) return RF_E_INVAL;
+  rf_batch_tuning t{};
+  rf_batch_get_tuning(b, &t);
+  for (int i = 0; i < 3; ++i) t.chunk[i] = chunk_per_bucket[i];
+  return rf_batch_set_tuning(b, &t);
+}
+
+rf_status rf_batch_get_tuning(const rf_batch* b, rf_batch_tuning* t) {
+  if (!b || !t) return RF_E_INVAL;
+  *t = rf_batch_tuning{};
   for (int i = 0; i < 3; ++i) {
-    const int c = chunk_per_bucket[i];
-    if (c != 256 && c != 512 && c != 1024) return RF_E_INVAL;
+    t->chunk[i] = b->chunk_for_bucket[i];
+    t->blocks[i] = b->blocks_for_bucket[i];
   }
+  t->xcd_queues = b->xcd_queues;
+  t->bucket_hi[0] = b->bucket_hi[0];
+  t->bucket_hi[1] = b->bucket_hi[1];
+  return RF_OK;
+}
+
+rf_status rf_batch_set_tuning(rf_batch* b, const rf_batch_tuning* t) {
+  if (!b || !t) return RF_E_INVAL;
+  for (int i = 0; i < 3; ++i) {
+    if (t->chunk[i] != 256 && t->chunk[i] != 512 && t->chunk[i] != 1024) return RF_E_INVAL;
+    if (t->blocks[i] != 1 && t->blocks[i] != 2 && t->blocks[i] != 4) return RF_E_INVAL;
+  }
+  if (t->xcd_queues != 0 && t->xcd_queues != 1) return RF_E_INVAL;
+  if (t->bucket_hi[0] < 0 || t->bucket_hi[1] < t->bucket_hi[0]) return RF_E_INVAL;
   try {
     RF_HIP(hipSetDevice(b->device));
-    for (int i = 0; i < 3; ++i) b->chunk_for_bucket[i] = chunk_per_bucket[i];
+    for (int i = 0; i < 3; ++i) {
+      b->chunk_for_bucket[i] = t->chunk[i];
+      b->blocks_for_bucket[i] = t->blocks[i];
+    }
+    b->xcd_queues = t->xcd_queues;
+    b->bucket_hi[0] = t->bucket_hi[0];
+    b->bucket_hi[1] = t->bucket_hi[1];
     upload_items(b);
   } catch (const Error& e) {
     return e.code;
@@ -327,6 +405,9 @@ rf_status rf_batch_set_chunks(rf_batch* b, const int32_t* chunk_per_bucket) {
 
 rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const char* cache_path) {
   if (!ctx || !b || !xf_segs) return RF_E_INVAL;
+  WorkItem* trial = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  rf_status st = RF_OK;
   try {
     RF_HIP(hipSetDevice(ctx->device));
     const std::string sig = signature(b);
@@ -336,15 +417,18 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
       std::string line;
       while (std::getline(in, line)) {
         std::istringstream ls(line);
-        std::string s;
-        int c0, c1, c2;
-        if ((ls >> s >> c0 >> c1 >> c2) && s == sig) {
-          const int32_t cs[3] = {c0, c1, c2};
-          return rf_batch_set_chunks(b, cs);
-        }
+        std::string sg;
+        rf_batch_tuning t{};
+        if ((ls >> sg >> t.chunk[0] >> t.chunk[1] >> t.chunk[2] >> t.blocks[0] >> t.blocks[1] >> t.blocks[2] >>
+             t.xcd_queues >> t.bucket_hi[0] >> t.bucket_hi[1]) &&
+            sg == sig)
+          return rf_batch_set_tuning(b, &t);
       }
     }
-    // time every candidate on each bucket's own items (fused read-out into scratch)
+    // trial launches on the batch's data with the fused read-out into scratch, on
+    // the buckets set at creation
+    b->bucket_hi[0] = b->bucket_hi_tertiles[0];
+    b->bucket_hi[1] = b->bucket_hi_tertiles[1];
     enqueue_reference(ctx, b, xf_segs);
     const int64_t np = int64_t(b->nseg) * b->ktotal;
     PeakOut po{};
@@ -354,56 +438,107 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
     po.cap = 0;
     po.thr2 = 1e30f;
     po.nk = b->ktotal;
-    WorkItem* scratch = dev_alloc<WorkItem>(b->hitems.size(), "batch: device allocation failed");
-    hipEvent_t e0, e1;
+    trial = dev_alloc<WorkItem>(b->items_cap, "batch: device allocation failed");
     RF_HIP(hipEventCreate(&e0));
     RF_HIP(hipEventCreate(&e1));
-    const int cand[3] = {256, 512, 1024};
-    for (int bk = 0; bk < 3; ++bk) {
-      std::vector<WorkItem> sub;
-      for (const auto& it : b->hitems)
-        if (bucket_of(b->htiles[it.tile].t.ksteps) == bk) sub.push_back(it);
-      if (sub.empty()) continue;
-      // at most ~4 items per workgroup slot keeps the tuning runs short
-      const size_t cap_items = size_t(b->nblocks) * 4;
-      if (sub.size() > cap_items) sub.resize(cap_items);
+    // best of three launches of a trial list
+    auto time_list = [&](const std::vector<WorkItem>& items, const QueueSpec& qs) {
+      RF_HIP(hipMemcpy(trial, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
       float best = 1e30f;
-      for (int c : cand) {
-        for (auto& it : sub) it.chunk = c;
-        RF_HIP(hipMemcpy(scratch, sub.data(), sizeof(WorkItem) * sub.size(), hipMemcpyHostToDevice));
+      for (int rep = 0; rep < 3; ++rep) {
+        fill_u64(ctx, b->packed, 0ull, np + 1);
+        RF_HIP(hipEventRecord(e0, ctx->stream));
+        queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, trial, qs, b->counter, b->b16, b->gflag,
+                     b->colscale, b->slot_kernel, b->zinv, po);
+        RF_HIP(hipEventRecord(e1, ctx->stream));
+        RF_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {
-          fill_u64(ctx, b->packed, 0ull, np + 1);
-          RF_HIP(hipEventRecord(e0, ctx->stream));
-          queue_launch(ctx, b->nblocks, b->zs, b->n, b->nref, b->tiles, scratch, int(sub.size()),
-                       b->counter, b->b16, b->gflag, b->colscale, b->slot_kernel, b->zinv, po);
-          RF_HIP(hipEventRecord(e1, ctx->stream));
-          RF_HIP(hipEventSynchronize(e1));
-          RF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        RF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+      }
+      return best;
+    };
+    auto one_queue = [](size_t count) {
+      QueueSpec qs{};
+      qs.nq = 1;
+      for (int i = 1; i <= kMaxQueues; ++i) qs.off[i] = int32_t(count);
+      return qs;
+    };
+    const int32_t ntb = int32_t(b->n / kTimes);
+    // (1) per bucket, chunk x blocks per item on the same sampled time blocks: about
+    // four per workgroup slot, in groups of four consecutive blocks spread over the
+    // bucket's (tile, segment, block) space
+    const int cand_chunk[3] = {256, 512, 1024};
+    const int cand_blocks[3] = {1, 2, 4};
+    for (int bk = 0; bk < 3; ++bk) {
+      struct Group { int32_t seg, tile, q0, len; };
+      std::vector<Group> all;
+      for (int32_t t : b->order) {
+        if (bucket_of(b, b->htiles[t].t.ksteps) != bk) continue;
+        for (int32_t sg = 0; sg < b->nseg; ++sg)
+          for (int32_t q = 0; q < ntb; q += 4) all.push_back(Group{sg, t, q, std::min(4, ntb - q)});
+      }
+      if (all.empty()) continue;
+      const size_t want = size_t(std::max(1, b->nblocks));
+      const size_t stride = std::max<size_t>(1, all.size() / want);
+      std::vector<Group> groups;
+      for (size_t i = 0; i < all.size() && groups.size() < want; i += stride) groups.push_back(all[i]);
+      float best = 1e30f;
+      for (int c : cand_chunk)
+        for (int nb : cand_blocks) {
+          std::vector<WorkItem> items;
+          for (const Group& g : groups)
+            for (int32_t q = g.q0; q < g.q0 + g.len; q += nb)
+              items.push_back(WorkItem{g.seg, g.tile, q, c, std::min(nb, g.q0 + g.len - q), 0});
+          const float ms = time_list(items, one_queue(items.size()));
+          if (ms < best) {
+            best = ms;
+            b->chunk_for_bucket[bk] = c;
+            b->blocks_for_bucket[bk] = nb;
+          }
         }
+    }
+    // (2) one queue or one per XCD, with the chosen settings, on whole runs of time
+    // blocks of up to eight tiles spread over the order (one per XCD queue), segment 0
+    {
+      std::vector<int32_t> pick;
+      const size_t nt = b->order.size();
+      for (int i = 0; i < kMaxQueues && size_t(i) < nt; ++i) pick.push_back(b->order[size_t(i) * nt / kMaxQueues]);
+      const int32_t run = std::min<int32_t>(ntb, std::max(16, int32_t(16 * size_t(b->nblocks) / std::max<size_t>(pick.size(), 1))));
+      float best = 1e30f;
+      for (int x = 0; x < 2; ++x) {
+        std::vector<WorkItem> items;
+        QueueSpec qs{};
+        build_items(b, pick, x ? kMaxQueues : 1, 1, run, items, qs);
+        const float ms = time_list(items, qs);
         if (ms < best) {
           best = ms;
-          b->chunk_for_bucket[bk] = c;
+          b->xcd_queues = x;
         }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(scratch);
     upload_items(b);
     if (cache_path) {
       std::ofstream outf(cache_path, std::ios::app);
-      outf << sig << " " << b->chunk_for_bucket[0] << " " << b->chunk_for_bucket[1] << " "
-           << b->chunk_for_bucket[2] << "\n";
+      outf << sig;
+      for (int i = 0; i < 3; ++i) outf << " " << b->chunk_for_bucket[i];
+      for (int i = 0; i < 3; ++i) outf << " " << b->blocks_for_bucket[i];
+      outf << " " << b->xcd_queues << " " << b->bucket_hi[0] << " " << b->bucket_hi[1] << "\n";
     }
   } catch (const Error& e) {
     ctx->last_error = e.msg;
-    return e.code;
+    st = e.code;
   } catch (...) {
     ctx->last_error = "rf_batch_autotune: unexpected exception";
-    return RF_E_HIP;
+    st = RF_E_HIP;
   }
-  return RF_OK;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (trial) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(trial);
+  }
+  return st;
 }
 
 rf_status rf_batch_run(rf_ctx* ctx, rf_batch* b, const void* xf_segs, float thr, rf_peak* peaks,

@@ -129,8 +129,17 @@ struct BatchTile {
   int32_t ref;
   int32_t pad;
 };
+// Work item: segment, tile, first time block, window chunk (taps) and the
+// number of consecutive 256-time blocks it covers.
 struct WorkItem {
-  int32_t seg, tile, tblock, chunk;
+  int32_t seg, tile, tblock, chunk, nblk, pad;
+};
+// Queues of the persistent launch: nq (1, or one per XCD) contiguous sublists of
+// the item array, queue i holding items [off[i], off[i + 1]).
+constexpr int kMaxQueues = 8;
+struct QueueSpec {
+  int32_t nq;
+  int32_t off[kMaxQueues + 1];
 };
 
 void recon_launch(rf_ctx* ctx, rf_prec prec, const void* zsrc, int64_t n, const TileDev* tiles,
@@ -140,7 +149,7 @@ void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __
                   float* inv_scale, int nseries = 1);
 int queue_blocks(int device);
 void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
-                  const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
+                  const BatchTile* tiles, const WorkItem* items, const QueueSpec& qs, uint32_t* counter,
                   const __half* b16, const uint32_t* gflag, const float* colscale,
                   const int32_t* slot_kernel, const float* zinv_all, const PeakOut& po);
 void pack_launch(rf_ctx* ctx, const rf_kernels* K, const int64_t* off_dev, const int64_t* mlo_dev,

@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
                                                             int32_t nref,
                                                             const BatchTile* __restrict__ tiles,
                                                             const WorkItem* __restrict__ items,
-                                                            int32_t nitems, uint32_t* counter,
+                                                            QueueSpec qs, uint32_t* counter,
                                                             const __half* b16,
                                                             const uint32_t* __restrict__ gflag,
                                                             const float* __restrict__ colscale,
@@ -578,19 +578,28 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
                                                             PeakOut po) {
   __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWinMax];
   __shared__ int32_t s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = int32_t(atomicAdd(counter, 1u));
-    __syncthreads();
-    const int32_t it = s_item;
-    __syncthreads();
-    if (it >= nitems) break;
-    const WorkItem w = items[it];
-    const BatchTile bt = tiles[w.tile];
-    const int64_t sr = int64_t(w.seg) * nref + bt.ref;
-    PeakOut p = po;
-    p.seg = w.seg;
-    recon_f16_item<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock) * kTimes, w.chunk,
-                                b16, gflag, colscale, slot_kernel, zinv_all[sr], nullptr, p);
+  // the home queue first (workgroups are dispatched to the XCDs in turn, so with
+  // one queue per XCD a workgroup's home queue is its XCD's), then the others'
+  // remaining items; every counter only grows, so each loop ends
+  const int home = qs.nq > 1 ? int(blockIdx.x % unsigned(qs.nq)) : 0;
+  for (int d = 0; d < qs.nq; ++d) {
+    const int qi = (home + d) % qs.nq;
+    const int32_t lo = qs.off[qi], cnt = qs.off[qi + 1] - qs.off[qi];
+    for (;;) {
+      if (threadIdx.x == 0) s_item = int32_t(atomicAdd(counter + qi, 1u));
+      __syncthreads();
+      const int32_t it = s_item;
+      __syncthreads();
+      if (it >= cnt) break;
+      const WorkItem w = items[lo + it];
+      const BatchTile bt = tiles[w.tile];
+      const int64_t sr = int64_t(w.seg) * nref + bt.ref;
+      PeakOut p = po;
+      p.seg = w.seg;
+      for (int b = 0; b < w.nblk; ++b)
+        recon_f16_item<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock + b) * kTimes, w.chunk,
+                                    b16, gflag, colscale, slot_kernel, zinv_all[sr], nullptr, p);
+    }
   }
 }
 
@@ -781,12 +790,14 @@ int queue_blocks(int device) {
 }
 
 void queue_launch(rf_ctx* ctx, int nblocks, const __half* zs_all, int64_t n, int nref,
-                  const BatchTile* tiles, const WorkItem* items, int nitems, uint32_t* counter,
+                  const BatchTile* tiles, const WorkItem* items, const QueueSpec& qs, uint32_t* counter,
                   const __half* b16, const uint32_t* gflag, const float* colscale,
                   const int32_t* slot_kernel, const float* zinv_all, const PeakOut& po) {
-  fill_u32(ctx, counter, 0u, 1);
+  RF_CHECK(qs.nq >= 1 && qs.nq <= kMaxQueues && qs.off[0] == 0, "queue: bad queue layout");
+  for (int i = 0; i < qs.nq; ++i) RF_CHECK(qs.off[i + 1] >= qs.off[i], "queue: bad queue layout");
+  fill_u32(ctx, counter, 0u, qs.nq);
   hipLaunchKernelGGL(k_recon_f16_queue, dim3(unsigned(nblocks)), dim3(256), 0, ctx->stream, zs_all, n,
-                     nref, tiles, items, nitems, counter, b16, gflag, colscale, slot_kernel, zinv_all, po);
+                     nref, tiles, items, qs, counter, b16, gflag, colscale, slot_kernel, zinv_all, po);
   RF_HIP(hipGetLastError());
 }
 

@@ -24,7 +24,7 @@ PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "mf_snr_peaks", "ratio_kernel_build",
             "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct", "snr_reconstruct_noalloc",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
-            "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
+            "rf_batch_get_tuning", "rf_batch_set_tuning", "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
             "rf_surrogate_dataset", "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
             "rf_surrogate_encode", "rf_surrogate_decode",
@@ -41,6 +41,11 @@ class RfGrid(ctypes.Structure):
 
 class RfTmpl(ctypes.Structure):
     _fields_ = [("m1", ctypes.c_double), ("m2", ctypes.c_double)]
+
+
+class RfBatchTuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32 * 3), ("blocks", ctypes.c_int32 * 3), ("xcd_queues", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("bucket_hi", ctypes.c_int64 * 2)]
 
 
 class RfPeak(ctypes.Structure):
@@ -98,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.rf_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32)]
     lib.rf_batch_set_chunks.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.rf_batch_get_tuning.argtypes = [vp, ctypes.POINTER(RfBatchTuning)]
+    lib.rf_batch_set_tuning.argtypes = [vp, ctypes.POINTER(RfBatchTuning)]
     lib.rf_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_char_p]
     lib.rf_batch_run.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
     lib.rf_batch_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
@@ -386,6 +393,24 @@ class Batch:
         st = self.ctx.lib.rf_batch_set_chunks(self.h, arr)
         if st != RF_OK:
             raise RfError(st, "rf_batch_set_chunks failed")
+
+    def tuning(self):
+        """Launch settings: chunk and blocks (per tile-length bucket), xcd_queues, bucket_hi."""
+        t = RfBatchTuning()
+        self.ctx.check(self.ctx.lib.rf_batch_get_tuning(self.h, ctypes.byref(t)))
+        return dict(chunk=list(t.chunk), blocks=list(t.blocks), xcd_queues=int(t.xcd_queues),
+                    bucket_hi=list(t.bucket_hi))
+
+    def set_tuning(self, chunk=None, blocks=None, xcd_queues=None, bucket_hi=None):
+        cur = self.tuning()
+        t = RfBatchTuning()
+        t.chunk = (ctypes.c_int32 * 3)(*(cur["chunk"] if chunk is None else chunk))
+        t.blocks = (ctypes.c_int32 * 3)(*(cur["blocks"] if blocks is None else blocks))
+        t.xcd_queues = int(cur["xcd_queues"] if xcd_queues is None else xcd_queues)
+        t.bucket_hi = (ctypes.c_int64 * 2)(*(cur["bucket_hi"] if bucket_hi is None else bucket_hi))
+        st = self.ctx.lib.rf_batch_set_tuning(self.h, ctypes.byref(t))
+        if st != RF_OK:
+            raise RfError(st, "rf_batch_set_tuning failed")
 
     def _inputs_ready(self, xf_segs):
         _dev_tensor(xf_segs, torch.complex128, shape=(self.nseg, self.n // 2 + 1), what="xf_segs")

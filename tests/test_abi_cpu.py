@@ -53,6 +53,32 @@ def test_struct_layouts():
     assert ctypes.sizeof(rf.RfTrigger) == 20
 
 
+def test_struct_offsets_match_the_header(tmp_path):
+    """Size and every field offset of each binding structure equal what a C
+    compiler makes of include/rf.h."""
+    from paper_2511_12894_amd import rf
+    pairs = [("rf_grid", rf.RfGrid), ("rf_tmpl", rf.RfTmpl), ("rf_peak", rf.RfPeak),
+             ("rf_trigger", rf.RfTrigger), ("rf_peak_args", rf.RfPeakArgs), ("rf_batch_tuning", rf.RfBatchTuning)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
+
+
 def test_null_context_is_rejected_without_gpu(lib):
     lib.mf_ref_snr.restype = ctypes.c_int
     assert lib.mf_ref_snr(None, None, None, None, None, 0, None, None) == 1   # RF_E_INVAL

@@ -107,6 +107,36 @@ def test_batch_matches_per_call_exactly(rf, work, setup, chunk):
     assert got_t == ref_t and len(got_t) > 0
 
 
+@pytest.mark.parametrize("blocks,xcd,bounds", [((2, 4, 1), 0, None), ((1, 1, 1), 1, None),
+                                               ((4, 2, 2), 1, [0, 10 ** 9])])
+def test_batch_launch_settings_keep_results(rf, work, setup, blocks, xcd, bounds):
+    """Time blocks per work item, one queue or one per XCD, and the bucket
+    bounds only move work between workgroups: peaks and triggers stay
+    bit-identical to the per-call path's."""
+    b = setup["batch"]
+    b.set_tuning(chunk=[512, 512, 512], blocks=list(blocks), xcd_queues=xcd, bucket_hi=bounds)
+    t = b.tuning()
+    _say(f"batch tuning {t}, {b.info()['nitems']} work items")
+    assert t["blocks"] == list(blocks) and t["xcd_queues"] == xcd
+    out = b.run(setup["xf"], 6.0)
+    got_p, got_t = _decode(rf, out, 2, b.ktotal)
+    ref_p, ref_t = _per_call(rf, work, setup, 6.0)
+    np.testing.assert_array_equal(got_p, ref_p)
+    assert got_t == ref_t and len(got_t) > 0
+    b.set_tuning(blocks=[1, 1, 1], xcd_queues=0)
+
+
+def test_batch_tuning_rejects_bad_settings(rf, work, setup):
+    b = setup["batch"]
+    t0 = b.tuning()
+    assert 0 <= t0["bucket_hi"][0] <= t0["bucket_hi"][1]
+    for kw in (dict(chunk=[512, 300, 512]), dict(blocks=[1, 3, 1]), dict(xcd_queues=2),
+               dict(bucket_hi=[5, 4]), dict(bucket_hi=[-1, 4])):
+        with pytest.raises(rf.RfError):
+            b.set_tuning(**kw)
+    assert b.tuning() == t0
+
+
 def test_batch_graph_replay_and_recapture(rf, work, setup):
     """New output and input buffers replay the captured graph (it holds only
     the batch's own buffers); a new threshold re-captures it."""
@@ -138,10 +168,15 @@ def test_batch_autotune_and_cache(rf, work, setup, tmp_path):
     b = setup["batch"]
     path = str(tmp_path / "tune.txt")
     chunks = b.autotune(setup["xf"], path)
-    assert all(c in (256, 512, 1024) for c in chunks)
-    assert open(path).read().count("\n") == 1
-    b.set_chunks([256, 256, 256])
+    tuned = b.tuning()
+    _say(f"autotuned {tuned}")
+    assert all(c in (256, 512, 1024) for c in chunks) and tuned["chunk"] == chunks
+    assert all(x in (1, 2, 4) for x in tuned["blocks"]) and tuned["xcd_queues"] in (0, 1)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and len(lines[0].split()) == 10
+    b.set_tuning(chunk=[256, 256, 256], blocks=[1, 1, 1], xcd_queues=1 - tuned["xcd_queues"])
     assert b.autotune(setup["xf"], path) == chunks          # from the cache
+    assert b.tuning() == tuned
     assert open(path).read().count("\n") == 1
     out = b.run(setup["xf"], 6.0)
     got_p, _ = _decode(rf, out, 2, b.ktotal)
