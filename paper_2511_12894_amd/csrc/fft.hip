@@ -7,12 +7,19 @@
 // w_{Ns P}^{r (j mod Ns)} (Ns = P_1 ... P_{i-1}) it takes a P-point DFT of
 // every column and writes element q to (j / Ns) Ns P + (j mod Ns) + q Ns.
 // A workgroup owns 16 consecutive columns, so each global read and write is a
-// run of 16 consecutive complex values; the P-point DFT of a column runs in
-// LDS as a short in-workgroup Stockham sequence of radix-8/4/2 register
-// butterflies.  Twiddles come from sincospi of exact dyadic arguments.  A
+// run of 16 consecutive complex values.
+//
+// FP32 passes split P = R1 R2 into two register radices: a thread loads the R1
+// inputs of its first butterfly straight from memory (elements u + i P / R1 of
+// its column), the inter-pass twiddles advancing by one complex product per
+// element from two sin/cos values of exact dyadic arguments; one exchange
+// through LDS then gives it the R2 inputs of its second butterfly, whose
+// outputs (elements u + q R1) it stores, or reads out, from registers.  A
 // first pass may form its input on the fly instead of reading it: the
 // band-limited products of the factored reconstruction, or a matched filter's
-// weighted template spectrum (FP64 phase), so neither is ever stored.
+// weighted template spectrum (FP64 phase), so neither is ever stored.  FP64
+// passes (kernel builds) run the P-point DFT in LDS as a short in-workgroup
+// Stockham sequence of radix-8/4/2 butterflies.
 #include <type_traits>
 
 #include "recon.h"
@@ -48,13 +55,18 @@ __device__ inline void sincospi_f32(float x, float* s, float* c) {
   *s = (qi & 2) ? -s0 : s0;
   *c = ((qi + 1) & 2) ? -c0 : c0;
 }
-__device__ inline void sc_pi(float x, float* s, float* c) { sincospi_f32(x, s, c); }
 __device__ inline void sc_pi(double x, double* s, double* c) { sincospi(x, s, c); }
 
 template <typename V> __device__ inline V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ inline V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
-template <typename V> __device__ inline V cmul(V a, V b) {
-  return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+// Complex product with the fused multiply-adds written out, and butterflies
+// compiled without contraction (below): a pass rounds the same way whether its
+// outputs are stored or read out.
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return float2{fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x)};
+}
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return double2{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 template <typename V> __device__ inline V mul_i(V a) { return V{-a.y, a.x}; }  // * (+i)
 
@@ -82,6 +94,7 @@ template <typename V> struct Dft<V, 4> {
 
 template <typename V> struct Dft<V, 8> {
   __device__ static void run(V* v) {
+#pragma clang fp contract(off)
     using T = decltype(v[0].x);
     V e[4] = {v[0], v[2], v[4], v[6]};
     V o[4] = {v[1], v[3], v[5], v[7]};
@@ -103,6 +116,41 @@ template <typename V> struct Dft<V, 8> {
   }
 };
 
+// 16 = 4 x 4: DFTs of the four residue classes m (inputs m + 4 p), the twiddles
+// w16^(m k1), then DFTs over m; output k1 + 4 k2.
+template <typename V> struct Dft<V, 16> {
+  __device__ static void run(V* v) {
+#pragma clang fp contract(off)
+    using T = decltype(v[0].x);
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T h = T(0.70710678118654752440084436210485);
+    V y[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) y[m][p] = v[m + 4 * p];
+      Dft<V, 4>::run(y[m]);
+    }
+    // w16^e for e = m k1: 1 = (c1, s1), 2 = (h, h), 3 = (s1, c1), 4 = i, 6 = (-h, h), 9 = (-c1, -s1)
+    y[1][1] = cmul(y[1][1], V{c1, s1});
+    y[1][2] = V{h * (y[1][2].x - y[1][2].y), h * (y[1][2].x + y[1][2].y)};
+    y[1][3] = cmul(y[1][3], V{s1, c1});
+    y[2][1] = V{h * (y[2][1].x - y[2][1].y), h * (y[2][1].x + y[2][1].y)};
+    y[2][2] = mul_i(y[2][2]);
+    y[2][3] = V{-h * (y[2][3].x + y[2][3].y), h * (y[2][3].x - y[2][3].y)};
+    y[3][1] = cmul(y[3][1], V{s1, c1});
+    y[3][2] = V{-h * (y[3][2].x + y[3][2].y), h * (y[3][2].x - y[3][2].y)};
+    y[3][3] = cmul(y[3][3], V{-c1, -s1});
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      V z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<V, 4>::run(z);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+    }
+  }
+};
+
 constexpr int kThreads = 256;
 constexpr int kCols = 16;
 static_assert(kThreads % kCols == 0, "a thread keeps one column through every loop of a pass");
@@ -120,6 +168,24 @@ template <int P> struct Lds<double, P> {
   static constexpr int stride = P == 16 ? 17 : P == 32 ? 35 : P == 64 ? 67 : P == 128 ? 131 : 263;
 };
 template <typename T, int P> using LdsRow = typename C2<T>::t[Lds<T, P>::stride];
+
+// FP32 passes: P = R1 x R2, the radices of a thread's two register butterflies.
+template <int P> struct Radix;
+template <> struct Radix<16> { static constexpr int R1 = 4, R2 = 4; };
+template <> struct Radix<32> { static constexpr int R1 = 4, R2 = 8; };
+template <> struct Radix<64> { static constexpr int R1 = 8, R2 = 8; };
+template <> struct Radix<128> { static constexpr int R1 = 8, R2 = 16; };
+template <> struct Radix<256> { static constexpr int R1 = 16, R2 = 16; };
+
+#ifndef RF_TMPL_PER_BLOCK
+#define RF_TMPL_PER_BLOCK 16
+#endif
+// Columns per workgroup of the FP32 passes: 32 (256-byte runs of every row)
+// where the pass has a multiple of 32 columns, else 16; the workgroup has one
+// thread per butterfly of the larger of its two stages (P / R1 or R1 per column).
+template <int P, int C> constexpr int threads32() {
+  return C * (P / Radix<P>::R1 > Radix<P>::R1 ? P / Radix<P>::R1 : Radix<P>::R1);
+}
 
 // One in-LDS Stockham stage of radix R on every column (sub-length NS done).
 template <typename T, int P, int NS, int R>
@@ -193,13 +259,12 @@ struct TmplIn {
 
 enum PassInput { kPlain = 0, kBand = 1 };
 
-// RO (a pass after the first, FP32): the outputs are not stored but read out
-// (running peak and threshold crossings of series tmpl0 + blockIdx.y).
-template <typename T, int P, int MODE, bool RO = false>
+// FP64 pass (plain input, stored output): columns through LDS, the P-point DFT
+// as in-LDS radix-8/4/2 stages, inter-pass twiddles from sincospi.
+template <typename T, int P>
 __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* __restrict__ in,
-                                                       typename C2<T>::t* __restrict__ out,
-                                                       int64_t n, int64_t ns, BandIn bin, TmplIn tin,
-                                                       PeakOut po) {
+                                                       typename C2<T>::t* __restrict__ out, int64_t n,
+                                                       int64_t ns) {
   using V = typename C2<T>::t;
   __shared__ V s[kCols][Lds<T, P>::stride];
   __shared__ V tw[P];
@@ -220,19 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
     const int c = e % kCols, r = e / kCols;
     const int64_t j = j0 + c;
-    V v;
-    if constexpr (MODE == kBand) {
-      const int64_t i = j + int64_t(r) * ncols - bin.b0;
-      v = V{0, 0};
-      if (i >= 0 && i < bin.nb) {
-        const float2 q = bin.Q[bin.b0 + i];
-        const float2 u = bin.Ub[int64_t(blockIdx.y) * bin.nb + i];
-        const float xr = q.x * bin.inv_n, xi = -q.y * bin.inv_n;
-        v = V{xr * u.x - xi * u.y, xr * u.y + xi * u.x};
-      }
-    } else {
-      v = in[j + int64_t(r) * ncols];
-    }
+    V v = in[j + int64_t(r) * ncols];
     if (ns > 1) {
       const uint32_t k = uint32_t(j) & uint32_t(ns - 1);
       T sn, cs;
@@ -243,21 +296,6 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   }
   __syncthreads();
   inner_dft<T, P, 1>(s, tw);
-  if constexpr (RO) {
-    static_assert(std::is_same<T, float>::value && MODE == kPlain, "read-out: FP32 passes after the first");
-    // output m = (j / ns) ns P + j mod ns + q ns, as in the store below (< n <= 2^24); a
-    // thread's column c is fixed and its q rises along the loop
-    Best best{-1.f, INT32_MAX};
-    const int64_t jt = j0 + (threadIdx.x % kCols);
-    const int32_t base = int32_t((jt / ns) * ns * P + (jt & (ns - 1)));
-    for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
-      const int c = e % kCols, q = e / kCols;
-      const V z = s[c][sw(q)];
-      peak_visit_rising(best, z.x, z.y, base + q * int32_t(ns), po);
-    }
-    peak_commit(best, po);
-    return;
-  }
   if (ns == 1) {
     // out[j P + q]: the block's 16 columns are one contiguous run
     for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
@@ -273,53 +311,166 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(const typename C2<T>::t* 
   }
 }
 
-// First pass of the matched filters of TPW templates sharing one workgroup (the
-// kTmpl input of k_fft_pass): the parts of every bin's phase and amplitude that
-// do not depend on the template -- f^(1/3), ln f, f^(-1/3) in FP64 and
-// f^(-7/6) -- are computed once per bin and kept in registers; each template
-// then takes its phase series from them (v = (pi M)^(1/3) f^(1/3),
-// ln v = ln (pi M)^(1/3) + ln(f) / 3, 1 / v = f^(-1/3) / (pi M)^(1/3)), forms its
-// weighted spectrum, transforms its 16 columns in LDS and stores them.
-template <int P, int TPW>
-__global__ __launch_bounds__(kThreads) void k_fft_tmpl_pass(float2* __restrict__ out, int64_t n, int batch,
-                                                            TmplIn tin) {
+// Inter-pass twiddles w_L^(r k) of a thread's R1 inputs r = u + i Q1 (i < R1),
+// k = j mod ns, L = ns P: sin/cos of the exact arguments 2 (u + i0 Q1) k / L
+// (every 8 elements) and 2 Q1 k / L (r k < L <= 2^24 is exact in 32 bits and as
+// a float, 2 / L a power of two), the twiddle advancing by one complex product
+// per element in between (at most 7 products: about 7 units in the last place).
+template <int R1, int Q1>
+__device__ inline void apply_twiddles(float2* v, uint32_t u, uint32_t k, float two_over_L) {
+  float sn, cs;
+  sincospi_f32(float(uint32_t(Q1) * k) * two_over_L, &sn, &cs);
+  const float2 b{cs, sn};
+#pragma unroll
+  for (int i0 = 0; i0 < R1; i0 += 8) {
+    sincospi_f32(float((u + uint32_t(i0 * Q1)) * k) * two_over_L, &sn, &cs);
+    float2 t{cs, sn};
+#pragma unroll
+    for (int i = i0; i < i0 + 8 && i < R1; ++i) {
+      v[i] = cmul(v[i], t);
+      if (i + 1 < i0 + 8 && i + 1 < R1) t = cmul(t, b);
+    }
+  }
+}
+
+// Second register butterfly of an FP32 pass: thread u < R1 of column c takes the
+// stage-one outputs u + q R1 (q < R2) from LDS, the twiddles w_P^(q u), and a
+// radix-R2 DFT; its outputs are the column's elements u + q R1.
+template <int P>
+__device__ inline void second_stage(const LdsRow<float, P>* s, const float2* tw, int c, int u, float2* v) {
+  constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2;
+#pragma unroll
+  for (int q = 0; q < R2; ++q) v[q] = s[c][sw(u + q * R1)];
+#pragma unroll
+  for (int q = 1; q < R2; ++q) v[q] = cmul(v[q], tw[q * u]);
+  Dft<float2, R2>::run(v);
+}
+
+// FP32 pass.  Thread (c, u) = (threadIdx % 16, threadIdx / 16) of column j = 16
+// blockIdx.x + c: for u < P / R1 its first butterfly on elements u + i P / R1
+// (loaded, or formed from the band products for MODE kBand on a first pass),
+// outputs to LDS at u R1 + i; for u < R1 its second butterfly (second_stage).
+// RO (a pass after the first): the outputs are read out (running peak and
+// threshold crossings of series tmpl0 + blockIdx.y) instead of stored.
+template <int P, int C, int MODE, bool RO>
+__global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __restrict__ in,
+                                                              float2* __restrict__ out, int32_t n, int32_t ns,
+                                                              BandIn bin, PeakOut po) {
   using V = float2;
-  constexpr int PER = (kCols * P + kThreads - 1) / kThreads;
-  __shared__ V s[kCols][Lds<float, P>::stride];
+  constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2, Q1 = P / R1, NT = threads32<P, C>();
+  constexpr int RM = R1 > R2 ? R1 : R2;
+  __shared__ V s[C][Lds<float, P>::stride];
   __shared__ V tw[P];
-  const int64_t ncols = n / P;
-  const int64_t j0 = int64_t(blockIdx.x) * kCols;
-  for (int m = threadIdx.x; m < P; m += kThreads) {
+  const int32_t ncols = n / P;
+  const int c = int(threadIdx.x) % C, u = int(threadIdx.x) / C;
+  const int32_t j0 = int32_t(blockIdx.x) * C, j = j0 + c;
+  in += int64_t(blockIdx.y) * n;
+  out += int64_t(blockIdx.y) * n;
+  for (int m = threadIdx.x; m < P; m += NT) {
+    float sn, cs;
+    sincospi_f32(float(2 * m) / float(P), &sn, &cs);
+    tw[m] = V{cs, sn};
+  }
+  V v[RM];
+  if (u < Q1) {
+#pragma unroll
+    for (int i = 0; i < R1; ++i) {
+      const int32_t x = j + (u + i * Q1) * ncols;
+      if constexpr (MODE == kBand) {
+        const int64_t b = int64_t(x) - bin.b0;
+        v[i] = V{0.f, 0.f};
+        if (b >= 0 && b < bin.nb) {
+          const float2 q = bin.Q[x];
+          const float2 w = bin.Ub[int64_t(blockIdx.y) * bin.nb + b];
+          const float xr = q.x * bin.inv_n, xi = -q.y * bin.inv_n;
+          v[i] = V{xr * w.x - xi * w.y, xr * w.y + xi * w.x};
+        }
+      } else {
+        v[i] = in[x];
+      }
+    }
+    if (ns > 1) apply_twiddles<R1, Q1>(v, uint32_t(u), uint32_t(j) & uint32_t(ns - 1), 2.f / float(ns * P));
+    Dft<V, R1>::run(v);
+#pragma unroll
+    for (int q = 0; q < R1; ++q) s[c][sw(u * R1 + q)] = v[q];
+  }
+  __syncthreads();
+  if (u < R1) second_stage<P>(s, tw, c, u, v);
+  const int32_t base = (j / ns) * ns * P + (j & (ns - 1));   // output m = base + element * ns
+  if constexpr (RO) {
+    static_assert(MODE == kPlain, "read-out: passes after the first");
+    Best best{-1.f, INT32_MAX};
+    if (u < R1) {
+#pragma unroll
+      for (int q = 0; q < R2; ++q) peak_visit_rising(best, v[q].x, v[q].y, base + (u + q * R1) * ns, po);
+    }
+    peak_commit(best, po);
+    return;
+  }
+  if (ns == 1) {
+    // out[j P + q] through LDS: the block's 16 columns are one contiguous run
+    __syncthreads();
+    if (u < R1) {
+#pragma unroll
+      for (int q = 0; q < R2; ++q) s[c][sw(u + q * R1)] = v[q];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < C * P; e += NT) {
+      const int q = e % P, cc = e / P;
+      out[(j0 + cc) * P + q] = s[cc][sw(q)];
+    }
+  } else if (u < R1) {
+#pragma unroll
+    for (int q = 0; q < R2; ++q) out[base + (u + q * R1) * ns] = v[q];
+  }
+}
+
+// First pass of the matched filters of TPW templates sharing one workgroup: the
+// parts of every bin's phase and amplitude that do not depend on the template --
+// f^(1/3), ln f, f^(-1/3) in FP64 and f^(-7/6) -- are computed once per bin and
+// kept in registers; each template then takes its phase series from them
+// (v = (pi M)^(1/3) f^(1/3), ln v = ln (pi M)^(1/3) + ln(f) / 3,
+// 1 / v = f^(-1/3) / (pi M)^(1/3)), forms its weighted spectrum in the
+// registers of the first butterflies (bins j + (u + i P / R1) n / P), transforms
+// its 16 columns as k_pass32 does and stores them.
+template <int P, int C, int TPW>
+__global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* __restrict__ out, int32_t n,
+                                                                     int batch, TmplIn tin) {
+  using V = float2;
+  constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2, Q1 = P / R1, NT = threads32<P, C>();
+  constexpr int RM = R1 > R2 ? R1 : R2;
+  __shared__ V s[C][Lds<float, P>::stride];
+  __shared__ V tw[P];
+  const int32_t ncols = n / P;
+  const int c = int(threadIdx.x) % C, u = int(threadIdx.x) / C;
+  const int32_t j0 = int32_t(blockIdx.x) * C, j = j0 + c;
+  for (int m = threadIdx.x; m < P; m += NT) {
     float sn, cs;
     sincospi_f32(float(2 * m) / float(P), &sn, &cs);
     tw[m] = V{cs, sn};
   }
   const double tg = sqrt(4.0 * tin.df / *tin.moment);
   // per-bin parts (in band: cf > 0)
-  double cf[PER], lf[PER], icf[PER];
-  float a0[PER];
+  double cf[R1], lf[R1], icf[R1];
+  float a0[R1];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+  for (int i = 0; i < R1; ++i) {
     cf[i] = 0.0;
     lf[i] = 0.0;
     icf[i] = 0.0;
     a0[i] = 0.f;
-    if (kCols * P % kThreads == 0 || e < kCols * P) {
-      const int c = e % kCols, r = e / kCols;
-      const int64_t fj = j0 + c + int64_t(r) * ncols;
-      if (fj >= tin.jlo && fj <= tin.jhi) {
-        const double f = double(fj) * tin.df;
-        // f^(1/3): the FP32 root refined by one Newton step (about 46 bits)
-        double x = double(cbrtf(float(f)));
-        const float x32 = float(x);
-        x -= double(float(x * x * x - f) / (3.0f * x32 * x32));
-        cf[i] = x;
-        lf[i] = log(f);
-        icf[i] = 1.0 / x;
-        // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
-        a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
-      }
+    const int32_t fj = j + (u + i * Q1) * ncols;
+    if (u < Q1 && fj >= tin.jlo && fj <= tin.jhi) {
+      const double f = double(fj) * tin.df;
+      // f^(1/3): the FP32 root refined by one Newton step (about 46 bits)
+      double x = double(cbrtf(float(f)));
+      const float x32 = float(x);
+      x -= double(float(x * x * x - f) / (3.0f * x32 * x32));
+      cf[i] = x;
+      lf[i] = log(f);
+      icf[i] = 1.0 / x;
+      // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
+      a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
     }
   }
   const int y0 = int(blockIdx.y) * TPW;
@@ -327,14 +478,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_tmpl_pass(float2* __restrict__
     const int y = y0 + t;
     const Tf2Coef tc = tin.coef[y % tin.nt];
     const float2* qs = tin.q + int64_t(y / tin.nt) * (tin.jhi - tin.jlo + 1);
+    V v[RM];
+    if (u < Q1) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (kCols * P % kThreads == 0 || e < kCols * P) {
-        const int c = e % kCols, r = e / kCols;
-        V v{0.f, 0.f};
+      for (int i = 0; i < R1; ++i) {
+        v[i] = V{0.f, 0.f};
         if (cf[i] > 0.0) {
-          const int64_t fj = j0 + c + int64_t(r) * ncols;
+          const int32_t fj = j + (u + i * Q1) * ncols;
           const double vv = tc.cbrt_piM * cf[i];
           const double lv = tc.ln_cbrt_piM + lf[i] * (1.0 / 3.0);
           const double iv = icf[i] * tc.inv_cbrt_piM;
@@ -346,44 +496,62 @@ __global__ __launch_bounds__(kThreads) void k_fft_tmpl_pass(float2* __restrict__
           float sn, cs;
           sincospi_f32(x, &sn, &cs);
           const float2 q = qs[fj - tin.jlo];
-          v = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
+          v[i] = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
         }
-        s[c][sw(r)] = v;
       }
+      Dft<V, R1>::run(v);
+#pragma unroll
+      for (int q = 0; q < R1; ++q) s[c][sw(u * R1 + q)] = v[q];
     }
     __syncthreads();
-    inner_dft<float, P, 1>(s, tw);
+    if (u < R1) second_stage<P>(s, tw, c, u, v);
+    __syncthreads();
+    if (u < R1) {
+#pragma unroll
+      for (int q = 0; q < R2; ++q) s[c][sw(u + q * R1)] = v[q];
+    }
+    __syncthreads();
     // out[j P + q]: the block's 16 columns are one contiguous run
     float2* o = out + int64_t(y) * n;
-    for (int e = threadIdx.x; e < kCols * P; e += kThreads) {
-      const int q = e % P, c = e / P;
-      o[(j0 + c) * P + q] = s[c][sw(q)];
+    for (int e = threadIdx.x; e < C * P; e += NT) {
+      const int q = e % P, cc = e / P;
+      o[(j0 + cc) * P + q] = s[cc][sw(q)];
     }
     __syncthreads();
   }
 }
 
-// Split log2(n) into at least two passes of at most 8 bits each, as even as
-// possible (16 columns per workgroup need n / P >= 16 in every pass).
-std::vector<int> plan_passes(int lg) {
+// Split log2(n) into at least two passes of at most 8 bits each (16 columns per
+// workgroup need n / P >= 16 in every pass).  FP64: as even as possible.  FP32:
+// as many 256-point passes as fit, the remainder in the first pass (where the
+// matched filters form their spectra: fewer elements per thread there keep the
+// per-bin phase parts in registers at full occupancy), at least 16 points.
+std::vector<int> plan_passes(int lg, bool small_first) {
   int s = (lg + 7) / 8;
   if (s < 2) s = 2;
   std::vector<int> bits(s, lg / s);
-  for (int i = 0; i < lg % s; ++i) bits[i] += 1;
+  if (!small_first) {
+    for (int i = 0; i < lg % s; ++i) bits[i] += 1;
+    return bits;
+  }
+  for (int i = 0; i < s; ++i) bits[i] = 8;
+  int excess = 8 * s - lg;
+  for (int i = 0; excess > 0; i = (i + 1) % s) {
+    const int d = std::min(excess, bits[i] - 4);
+    bits[i] -= d;
+    excess -= d;
+  }
   return bits;
 }
 
-template <typename T, int MODE = kPlain, bool RO = false>
-void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, int64_t n,
-                 int64_t ns, int batch, hipStream_t st, BandIn bin = BandIn{}, TmplIn tin = TmplIn{},
-                 PeakOut po = PeakOut{}) {
+void launch_pass64(int bits, const double2* in, double2* out, int64_t n, int64_t ns, int batch,
+                   hipStream_t st) {
   const int64_t P = int64_t(1) << bits;
   dim3 grid(unsigned((n / P) / kCols), unsigned(batch));
   switch (bits) {
-#define RF_FFT_CASE(B)                                                                            \
-  case B:                                                                                         \
-    hipLaunchKernelGGL((k_fft_pass<T, (1 << B), MODE, RO>), grid, dim3(kThreads), 0, st, in, out, n, \
-                       ns, bin, tin, po);                                                         \
+#define RF_FFT_CASE(B)                                                                                  \
+  case B:                                                                                               \
+    hipLaunchKernelGGL((k_fft_pass<double, (1 << B)>), grid, dim3(kThreads), 0, st, in, out, n, ns);   \
     break;
     RF_FFT_CASE(4)
     RF_FFT_CASE(5)
@@ -397,23 +565,60 @@ void launch_pass(int bits, const typename C2<T>::t* in, typename C2<T>::t* out, 
   RF_HIP(hipGetLastError());
 }
 
+template <int MODE = kPlain, bool RO = false>
+void launch_pass32(int bits, const float2* in, float2* out, int64_t n, int64_t ns, int batch, hipStream_t st,
+                   BandIn bin = BandIn{}, PeakOut po = PeakOut{}) {
+  const int64_t cols = n >> bits;
+  const bool wide = cols % 32 == 0;
+  RF_CHECK(cols % 16 == 0, "fft: fewer columns than a workgroup takes");
+  dim3 grid(unsigned(cols / (wide ? 32 : 16)), unsigned(batch));
+  switch (bits * 2 + (wide ? 1 : 0)) {
+#define RF_FFT_CASE(B, C)                                                                               \
+  case B * 2 + (C == 32 ? 1 : 0):                                                                       \
+    hipLaunchKernelGGL((k_pass32<(1 << B), C, MODE, RO>), grid, dim3(threads32<(1 << B), C>()), 0, st,  \
+                       in, out, int32_t(n), int32_t(ns), bin, po);                                      \
+    break;
+    RF_FFT_CASE(4, 16)
+    RF_FFT_CASE(5, 16)
+    RF_FFT_CASE(6, 16)
+    RF_FFT_CASE(7, 16)
+    RF_FFT_CASE(8, 16)
+    RF_FFT_CASE(4, 32)
+    RF_FFT_CASE(5, 32)
+    RF_FFT_CASE(6, 32)
+    RF_FFT_CASE(7, 32)
+    RF_FFT_CASE(8, 32)
+#undef RF_FFT_CASE
+    default:
+      throw Error{RF_E_UNSUPPORTED, "fft: unsupported pass size"};
+  }
+  RF_HIP(hipGetLastError());
+}
+
 // first pass of matched filters: templates per workgroup
-constexpr int kTmplPerBlock = 4;
+constexpr int kTmplPerBlock = RF_TMPL_PER_BLOCK;
 
 void launch_tmpl_pass(int bits, float2* out, int64_t n, int batch, hipStream_t st, const TmplIn& tin) {
-  const int64_t P = int64_t(1) << bits;
-  dim3 grid(unsigned((n / P) / kCols), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
-  switch (bits) {
-#define RF_TMPL_CASE(B)                                                                                 \
-  case B:                                                                                               \
-    hipLaunchKernelGGL((k_fft_tmpl_pass<(1 << B), kTmplPerBlock>), grid, dim3(kThreads), 0, st, out, n, \
-                       batch, tin);                                                                     \
+  const int64_t cols = n >> bits;
+  const bool wide = cols % 32 == 0;
+  RF_CHECK(cols % 16 == 0, "fft: fewer columns than a workgroup takes");
+  dim3 grid(unsigned(cols / (wide ? 32 : 16)), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
+  switch (bits * 2 + (wide ? 1 : 0)) {
+#define RF_TMPL_CASE(B, C)                                                                              \
+  case B * 2 + (C == 32 ? 1 : 0):                                                                       \
+    hipLaunchKernelGGL((k_fft_tmpl_pass<(1 << B), C, kTmplPerBlock>), grid, dim3(threads32<(1 << B), C>()), \
+                       0, st, out, int32_t(n), batch, tin);                                             \
     break;
-    RF_TMPL_CASE(4)
-    RF_TMPL_CASE(5)
-    RF_TMPL_CASE(6)
-    RF_TMPL_CASE(7)
-    RF_TMPL_CASE(8)
+    RF_TMPL_CASE(4, 16)
+    RF_TMPL_CASE(5, 16)
+    RF_TMPL_CASE(6, 16)
+    RF_TMPL_CASE(7, 16)
+    RF_TMPL_CASE(8, 16)
+    RF_TMPL_CASE(4, 32)
+    RF_TMPL_CASE(5, 32)
+    RF_TMPL_CASE(6, 32)
+    RF_TMPL_CASE(7, 32)
+    RF_TMPL_CASE(8, 32)
 #undef RF_TMPL_CASE
     default:
       throw Error{RF_E_UNSUPPORTED, "fft: unsupported pass size"};
@@ -428,7 +633,7 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
-  std::vector<int> bits = plan_passes(lg);
+  std::vector<int> bits = plan_passes(lg, std::is_same<T, float>::value);
   const int s = int(bits.size());
   V* wa = nullptr;
   V* wb = nullptr;
@@ -444,23 +649,19 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   for (int i = 0; i < s; ++i) {
     V* dst = (i == s - 1) ? out : ((i % 2 == 0) ? wa : wb);
     if constexpr (std::is_same<T, float>::value) {
-      if (i == 0 && (band || tmpl)) {
-        if (band)
-          launch_pass<T, kBand>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
-        else
-          launch_tmpl_pass(bits[i], dst, n, batch, ctx->stream, *tmpl);
-        ns <<= bits[i];
-        src = dst;
-        continue;
-      }
-    }
-    if constexpr (std::is_same<T, float>::value) {
-      if (i == s - 1 && ro) {          // the last pass reads the outputs out instead
-        launch_pass<T, kPlain, true>(bits[i], src, nullptr, n, ns, batch, ctx->stream, BandIn{}, TmplIn{}, *ro);
+      if (i == 0 && band) {
+        launch_pass32<kBand>(bits[i], nullptr, dst, n, ns, batch, ctx->stream, *band);
+      } else if (i == 0 && tmpl) {
+        launch_tmpl_pass(bits[i], dst, n, batch, ctx->stream, *tmpl);
+      } else if (i == s - 1 && ro) {   // the last pass reads the outputs out instead
+        launch_pass32<kPlain, true>(bits[i], src, nullptr, n, ns, batch, ctx->stream, BandIn{}, *ro);
         break;
+      } else {
+        launch_pass32(bits[i], src, dst, n, ns, batch, ctx->stream);
       }
+    } else {
+      launch_pass64(bits[i], src, dst, n, ns, batch, ctx->stream);
     }
-    launch_pass<T>(bits[i], src, dst, n, ns, batch, ctx->stream);
     ns <<= bits[i];
     src = dst;
   }

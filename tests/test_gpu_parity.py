@@ -99,7 +99,7 @@ def test_mf_ref_snr_many_templates_and_tiny_grid(rf, ctx):
         xf_d, psd_d = _dev(xf, torch.complex128), _dev(psd, torch.float64)
         z, sig = rf.mf_ref_snr(ctx, g, xf_d, psd_d, tm)
         # the read-out in the last transform pass (two 16-point passes at n = 256,
-        # a 64- and a 32-point pass at n = 2048)
+        # a 16- and a 128-point pass at n = 2048)
         # equals the read-out of the stored series, with a threshold some samples cross
         thr = float(0.5 * z.abs().max().item())
         a = rf.mf_snr_peaks(ctx, g, xf_d, psd_d, tm, thr)
