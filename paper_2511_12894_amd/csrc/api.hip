@@ -257,14 +257,14 @@ rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const dou
     Tf2Coef* coef_dev = upload(ctx, WS_COEF, coef.data(), coef.size());
     double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
     band_moment(ctx, grid, psd, moment);
-    // conditioned data once, then the templates in batches (FFT scratch up to 2 GiB); each
+    // conditioned data once, then the templates in batches (FFT scratch up to 8 GiB); each
     // template's spectrum is formed inside the first transform pass and never stored
     int64_t jlo, jhi;
     band_limits(grid, &jlo, &jhi);
     float2* q = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(jhi - jlo + 1)));
     condition_data(ctx, grid, static_cast<const double2*>(xf), psd, q);
-    // at most 2^28 / n templates a batch, split evenly (no small last batch)
-    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    // at most 2^30 / n templates a batch, split evenly (no small last batch)
+    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 30) / n)));
     const int nbatch = (nt + cap - 1) / cap;
     const int per = (nt + nbatch - 1) / nbatch;
     float2* zo = static_cast<float2*>(z);
@@ -315,9 +315,9 @@ rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const d
     po.thr2 = out->thr * out->thr;
     po.seg = 0;
     po.nk = nt;
-    // templates in batches (two transform scratch buffers of up to 2 GiB each)
-    // at most 2^28 / n templates a batch, split evenly (no small last batch)
-    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 28) / n)));
+    // templates in batches (two transform scratch buffers of up to 8 GiB each)
+    // at most 2^30 / n templates a batch, split evenly (no small last batch)
+    const int cap = int(std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t(1) << 30) / n)));
     const int nbatch = (nt + cap - 1) / cap;
     const int per = (nt + nbatch - 1) / nbatch;
     for (int t0 = 0; t0 < nt; t0 += per) {

@@ -333,25 +333,33 @@ __device__ inline void apply_twiddles(float2* v, uint32_t u, uint32_t k, float t
   }
 }
 
-// Second register butterfly of an FP32 pass: thread u < R1 of column c takes the
-// stage-one outputs u + q R1 (q < R2) from LDS, the twiddles w_P^(q u), and a
-// radix-R2 DFT; its outputs are the column's elements u + q R1.
+// Twiddles w_P^(q u) and radix-R2 DFT of a thread's second butterfly (inputs
+// v[q] = stage-one output u + q R1 of its column, u < R1); its outputs are the
+// column's elements u + q R1.
 template <int P>
-__device__ inline void second_stage(const LdsRow<float, P>* s, const float2* tw, int c, int u, float2* v) {
-  constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2;
-#pragma unroll
-  for (int q = 0; q < R2; ++q) v[q] = s[c][sw(u + q * R1)];
+__device__ inline void second_butterfly(const float2* tw, int u, float2* v) {
+  constexpr int R2 = Radix<P>::R2;
 #pragma unroll
   for (int q = 1; q < R2; ++q) v[q] = cmul(v[q], tw[q * u]);
   Dft<float2, R2>::run(v);
 }
 
-// FP32 pass.  Thread (c, u) = (threadIdx % 16, threadIdx / 16) of column j = 16
-// blockIdx.x + c: for u < P / R1 its first butterfly on elements u + i P / R1
+// Second register butterfly of an FP32 pass: thread u < R1 of column c takes the
+// stage-one outputs u + q R1 (q < R2) from LDS.
+template <int P>
+__device__ inline void second_stage(const LdsRow<float, P>* s, const float2* tw, int c, int u, float2* v) {
+  constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2;
+#pragma unroll
+  for (int q = 0; q < R2; ++q) v[q] = s[c][sw(u + q * R1)];
+  second_butterfly<P>(tw, u, v);
+}
+
+// FP32 pass.  Thread (c, u) = (threadIdx % C, threadIdx / C) of column j =
+// C blockIdx.x + c: for u < P / R1 its first butterfly on elements u + i P / R1
 // (loaded, or formed from the band products for MODE kBand on a first pass),
-// outputs to LDS at u R1 + i; for u < R1 its second butterfly (second_stage).
-// RO (a pass after the first): the outputs are read out (running peak and
-// threshold crossings of series tmpl0 + blockIdx.y) instead of stored.
+// outputs to LDS at u R1 + i; for u < R1 its second butterfly.  RO (a pass after
+// the first): the outputs are read out (running peak and threshold crossings of
+// series tmpl0 + blockIdx.y) instead of stored.
 template <int P, int C, int MODE, bool RO>
 __global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __restrict__ in,
                                                               float2* __restrict__ out, int32_t n, int32_t ns,
@@ -391,6 +399,8 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __
     }
     if (ns > 1) apply_twiddles<R1, Q1>(v, uint32_t(u), uint32_t(j) & uint32_t(ns - 1), 2.f / float(ns * P));
     Dft<V, R1>::run(v);
+  }
+  if (u < Q1) {
 #pragma unroll
     for (int q = 0; q < R1; ++q) s[c][sw(u * R1 + q)] = v[q];
   }
@@ -408,7 +418,7 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __
     return;
   }
   if (ns == 1) {
-    // out[j P + q] through LDS: the block's 16 columns are one contiguous run
+    // out[j P + q] through LDS: the block's C columns are one contiguous run
     __syncthreads();
     if (u < R1) {
 #pragma unroll
@@ -425,20 +435,24 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __
   }
 }
 
-// First pass of the matched filters of TPW templates sharing one workgroup: the
-// parts of every bin's phase and amplitude that do not depend on the template --
-// f^(1/3), ln f, f^(-1/3) in FP64 and f^(-7/6) -- are computed once per bin and
-// kept in registers; each template then takes its phase series from them
-// (v = (pi M)^(1/3) f^(1/3), ln v = ln (pi M)^(1/3) + ln(f) / 3,
-// 1 / v = f^(-1/3) / (pi M)^(1/3)), forms its weighted spectrum in the
-// registers of the first butterflies (bins j + (u + i P / R1) n / P), transforms
-// its 16 columns as k_pass32 does and stores them.
+// First pass of the matched filters of TPW templates sharing one workgroup.  The
+// phase of a template is a fixed combination of nine functions of the bin,
+// Psi = e0 + e5 x^-5 + e3 x^-3 + e2 x^-2 + e1 x^-1 + el ln f + ex x + exl x ln f
+// + exx x^2 with x = f^(1/3) (the TaylorF2 series in v = (pi M)^(1/3) x); the
+// functions of every bin (FP64) and f^(-7/6) are computed once per workgroup
+// and kept in registers (all eight where a thread has at most four bins, else
+// x, 1 / x and ln f), so a template's phase costs eight FP64 multiply-adds per
+// bin.  Each template forms its weighted spectrum in the registers of the first
+// butterflies (bins j + (u + i P / R1) n / P), transforms its columns as
+// k_pass32 does and stores them.
 template <int P, int C, int TPW>
 __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* __restrict__ out, int32_t n,
                                                                      int batch, TmplIn tin) {
   using V = float2;
   constexpr int R1 = Radix<P>::R1, R2 = Radix<P>::R2, Q1 = P / R1, NT = threads32<P, C>();
   constexpr int RM = R1 > R2 ? R1 : R2;
+  constexpr bool kAll = R1 <= 4;              // keep all eight bin functions
+  constexpr int NG = kAll ? 8 : 3;
   __shared__ V s[C][Lds<float, P>::stride];
   __shared__ V tw[P];
   const int32_t ncols = n / P;
@@ -450,14 +464,14 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
     tw[m] = V{cs, sn};
   }
   const double tg = sqrt(4.0 * tin.df / *tin.moment);
-  // per-bin parts (in band: cf > 0)
-  double cf[R1], lf[R1], icf[R1];
+  // per-bin functions: kAll: x^-5, x^-3, x^-2, x^-1, ln f, x, x ln f, x^2; else x, 1 / x, ln f
+  // (in band: g[0] != 0; out of band all zero)
+  double g[NG][R1];
   float a0[R1];
 #pragma unroll
   for (int i = 0; i < R1; ++i) {
-    cf[i] = 0.0;
-    lf[i] = 0.0;
-    icf[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) g[q][i] = 0.0;
     a0[i] = 0.f;
     const int32_t fj = j + (u + i * Q1) * ncols;
     if (u < Q1 && fj >= tin.jlo && fj <= tin.jhi) {
@@ -466,14 +480,28 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
       double x = double(cbrtf(float(f)));
       const float x32 = float(x);
       x -= double(float(x * x * x - f) / (3.0f * x32 * x32));
-      cf[i] = x;
-      lf[i] = log(f);
-      icf[i] = 1.0 / x;
+      const double ix = 1.0 / x, lf = log(f);
+      if constexpr (kAll) {
+        const double ix2 = ix * ix, ix3 = ix2 * ix;
+        g[0][i] = ix3 * ix2;
+        g[1][i] = ix3;
+        g[2][i] = ix2;
+        g[3][i] = ix;
+        g[4][i] = lf;
+        g[5][i] = x;
+        g[6][i] = x * lf;
+        g[7][i] = x * x;
+      } else {
+        g[0][i] = x;
+        g[1][i] = ix;
+        g[2][i] = lf;
+      }
       // f^(-7/6) = 1 / (f sqrt(f^(1/3)))
       a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
     }
   }
   const int y0 = int(blockIdx.y) * TPW;
+#pragma unroll 1
   for (int t = 0; t < TPW && y0 + t < batch; ++t) {
     const int y = y0 + t;
     const Tf2Coef tc = tin.coef[y % tin.nt];
@@ -483,14 +511,32 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
 #pragma unroll
       for (int i = 0; i < R1; ++i) {
         v[i] = V{0.f, 0.f};
-        if (cf[i] > 0.0) {
+        if (g[0][i] != 0.0) {
           const int32_t fj = j + (u + i * Q1) * ncols;
-          const double vv = tc.cbrt_piM * cf[i];
-          const double lv = tc.ln_cbrt_piM + lf[i] * (1.0 / 3.0);
-          const double iv = icf[i] * tc.inv_cbrt_piM;
           // the phase in FP64 (it reaches ~1e5 rad), reduced in FP64 to psi / pi - 2k in
           // [-1, 1]; the exponential of the reduced angle and the amplitude need only FP32
-          const double psi = tf2_phase_v(tc, vv, lv, iv);
+          double psi;
+          if constexpr (kAll) {
+            psi = fma(tc.e5, g[0][i], tc.e0);
+            psi = fma(tc.e3, g[1][i], psi);
+            psi = fma(tc.e2, g[2][i], psi);
+            psi = fma(tc.e1, g[3][i], psi);
+            psi = fma(tc.el, g[4][i], psi);
+            psi = fma(tc.ex, g[5][i], psi);
+            psi = fma(tc.exl, g[6][i], psi);
+            psi = fma(tc.exx, g[7][i], psi);
+          } else {
+            const double x = g[0][i], ix = g[1][i], lf = g[2][i];
+            const double ix2 = ix * ix, ix3 = ix2 * ix;
+            psi = fma(tc.e5, ix3 * ix2, tc.e0);
+            psi = fma(tc.e3, ix3, psi);
+            psi = fma(tc.e2, ix2, psi);
+            psi = fma(tc.e1, ix, psi);
+            psi = fma(tc.el, lf, psi);
+            psi = fma(tc.ex, x, psi);
+            psi = fma(tc.exl, x * lf, psi);
+            psi = fma(tc.exx, x * x, psi);
+          }
           const double k = rint(psi * 0.15915494309189533577);
           const float x = float(fma(psi, 0.31830988618379067154, -2.0 * k));
           float sn, cs;

@@ -116,6 +116,9 @@ struct Tf2Coef {
   double amp;      // Mc^(5/6)
   double cbrt_piM; // (pi M)^(1/3)
   double ln_cbrt_piM, inv_cbrt_piM;   // ln and reciprocal of (pi M)^(1/3)
+  // the same phase in powers of x = f^(1/3) and ln f (v = (pi M)^(1/3) x):
+  // Psi = e0 + e5 x^-5 + e3 x^-3 + e2 x^-2 + e1 x^-1 + el ln f + ex x + exl x ln f + exx x^2
+  double e0, e5, e3, e2, e1, el, ex, exl, exx;
 };
 Tf2Coef tf2_coef(const rf_tmpl& t);
 

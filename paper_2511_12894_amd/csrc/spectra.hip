@@ -46,6 +46,18 @@ Tf2Coef tf2_coef(const rf_tmpl& t) {
   c.cbrt_piM = std::cbrt(c.piM);
   c.ln_cbrt_piM = std::log(c.cbrt_piM);
   c.inv_cbrt_piM = 1.0 / c.cbrt_piM;
+  // pref [v^-5 + a2 v^-3 + a3 v^-2 + a4 v^-1 + (a5c + a5l ln v) + (a6c + a6l ln v) v + a7 v^2]
+  // with v = k x, ln v = ln k + ln(f) / 3
+  const double k = c.cbrt_piM, lk = c.ln_cbrt_piM, ik = c.inv_cbrt_piM;
+  c.e0 = -0.25 * kPi + c.pref * (c.a5c + c.a5l * lk);
+  c.e5 = c.pref * ik * ik * ik * ik * ik;
+  c.e3 = c.pref * c.a2 * ik * ik * ik;
+  c.e2 = c.pref * c.a3 * ik * ik;
+  c.e1 = c.pref * c.a4 * ik;
+  c.el = c.pref * c.a5l / 3.0;
+  c.ex = c.pref * (c.a6c + c.a6l * lk) * k;
+  c.exl = c.pref * c.a6l * k / 3.0;
+  c.exx = c.pref * c.a7 * k * k;
   return c;
 }
 

@@ -348,14 +348,15 @@ def realistic():
 
 
 def test_direct_mf_readout_full_size(rf, ctx, realistic):
-    """The benchmark's comparator shape: 257 templates of 2^21 samples, three
-    transform batches (template offsets in the read-out), exactly as the stored
-    series read out on their own."""
+    """The benchmark's comparator shape, 2^21 samples, with its 257 templates
+    listed twice (513 series: two transform batches of at most 2^30 / n, so
+    template offsets in the read-out), exactly as the stored series read out on
+    their own."""
     w = realistic
     g = w["grid"]
     xf = _dev(w["xf"], torch.complex128)
     psd = _dev(w["psd"], torch.float64)
-    tm = [w["ref"]] + list(w["nbrs"])
+    tm = ([w["ref"]] + list(w["nbrs"])) * 2
     _say(f"full-size direct read-out: {len(tm)} templates, n = {g.n}")
     z, _ = rf.mf_ref_snr(ctx, g, xf, psd, tm, want_sigma=False)
     ref = rf.snr_peaks(ctx, z, 6.0, trig_cap=1 << 17)
