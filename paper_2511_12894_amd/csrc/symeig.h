@@ -6,8 +6,9 @@
 // Wilkinson, Numer. Math. 12, 1968; also "tqli" in Numerical Recipes): the
 // shift from the leading 2x2 block, the chase of rotations from the bottom of
 // the unreduced block upwards, and the deflation when a rotation radius is 0.  Used for the Gram matrix of a kernel set
-// (a few hundred rows), where O(n^3) host work is negligible next to the GPU
-// build of the kernels.
+// (up to 1024 rows).  The accumulated transform is kept transposed (row i holds
+// column i of Q), so every Householder update and every QL rotation runs over
+// contiguous rows.
 #pragma once
 
 #include <algorithm>
@@ -24,10 +25,11 @@ namespace rf {
 inline void sym_eig(const std::vector<double>& A_in, int n, std::vector<double>& w, std::vector<double>& V) {
   std::vector<double> A(A_in);
   auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
-  std::vector<double> Q(size_t(n) * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[size_t(i) * n + i] = 1.0;
-  auto q = [&](int i, int j) -> double& { return Q[size_t(i) * n + j]; };
-  std::vector<double> v(n), p(n), wv(n);
+  // Qt: row j is column j of the accumulated orthogonal transform Q
+  std::vector<double> Qt(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) Qt[size_t(i) * n + i] = 1.0;
+  auto qrow = [&](int j) -> double* { return Qt.data() + size_t(j) * n; };
+  std::vector<double> v(n), p(n), wv(n), sq(n);
   // Householder: zero column k below the subdiagonal, for k = 0 .. n-3
   for (int k = 0; k + 2 < n; ++k) {
     double sig = 0.0;
@@ -58,11 +60,17 @@ inline void sym_eig(const std::vector<double>& A_in, int n, std::vector<double>&
       for (int j = k + 1; j < n; ++j) a(i, j) -= 2.0 * (v[i] * wv[j] + wv[i] * v[j]);
     a(k + 1, k) = a(k, k + 1) = alpha;
     for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
-    // Q <- Q H
-    for (int r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int j = k + 1; j < n; ++j) s += q(r, j) * v[j];
-      for (int j = k + 1; j < n; ++j) q(r, j) -= 2.0 * s * v[j];
+    // Q <- Q H: column j of Q loses 2 v[j] (Q v), Q v = sum_j v[j] (column j)
+    std::fill(sq.begin(), sq.end(), 0.0);
+    for (int j = k + 1; j < n; ++j) {
+      const double* qj = qrow(j);
+      const double vj = v[j];
+      for (int r = 0; r < n; ++r) sq[r] += vj * qj[r];
+    }
+    for (int j = k + 1; j < n; ++j) {
+      double* qj = qrow(j);
+      const double f = 2.0 * v[j];
+      for (int r = 0; r < n; ++r) qj[r] -= f * sq[r];
     }
   }
   // tridiagonal: diagonal d, off-diagonal e[i] = T(i, i + 1), e[n-1] = 0
@@ -108,10 +116,12 @@ inline void sym_eig(const std::vector<double>& A_in, int n, std::vector<double>&
         pp = s * r;
         d[i + 1] = g + pp;
         g = c * r - b;
-        for (int k = 0; k < n; ++k) {        // rotate eigenvector columns i, i + 1
-          const double qk1 = q(k, i + 1);
-          q(k, i + 1) = s * q(k, i) + c * qk1;
-          q(k, i) = c * q(k, i) - s * qk1;
+        double* qi = qrow(i);                 // rotate eigenvector columns i, i + 1
+        double* qi1 = qrow(i + 1);
+        for (int k = 0; k < n; ++k) {
+          const double a0 = qi[k], a1 = qi1[k];
+          qi1[k] = s * a0 + c * a1;
+          qi[k] = c * a0 - s * a1;
         }
       }
       if (deflated) continue;
@@ -127,7 +137,8 @@ inline void sym_eig(const std::vector<double>& A_in, int n, std::vector<double>&
   V.assign(size_t(n) * n, 0.0);
   for (int c2 = 0; c2 < n; ++c2) {
     w[c2] = d[idx[c2]];
-    for (int k = 0; k < n; ++k) V[size_t(k) * n + c2] = q(k, idx[c2]);
+    const double* qc = qrow(idx[c2]);
+    for (int k = 0; k < n; ++k) V[size_t(k) * n + c2] = qc[k];
   }
 }
 
