@@ -986,7 +986,8 @@ def c2_legs(dev, args, legs):
         out["direct_fft_mf_roofline"] = {"bound": "hbm", "bytes_per_template_sample": 16,
                                          "achieved": 16 * samples / (dms * 1e-3) / 1e9,
                                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                         "frac": 16 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                                         "frac": 16 * samples / (dms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                                         "traffic": counter_traffic("mf_snr_peaks")}
         out["err_vs_direct_mf"] = res["err_vs_direct"]
         out["threshold_per_tap"] = res["per_tap"]
     for key in ("factored", "ols", "bank", "learned"):
