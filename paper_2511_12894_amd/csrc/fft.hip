@@ -17,9 +17,12 @@
 // outputs (elements u + q R1) it stores, or reads out, from registers.  A
 // first pass may form its input on the fly instead of reading it: the
 // band-limited products of the factored reconstruction, or a matched filter's
-// weighted template spectrum (FP64 phase), so neither is ever stored.  FP64
-// passes (kernel builds) run the P-point DFT in LDS as a short in-workgroup
-// Stockham sequence of radix-8/4/2 butterflies.
+// weighted template spectrum (FP64 phase), so neither is ever stored.  Matched
+// filters of 2^20 and 2^21 samples take two passes instead of three (a 1024- or
+// 2048-point first pass of one column per workgroup, then 1024-point columns,
+// 16 a workgroup, in 135 KB of LDS), so their intermediate crosses HBM once.
+// FP64 passes (kernel builds) run the P-point DFT in LDS as a short
+// in-workgroup Stockham sequence of radix-8/4/2 butterflies.
 #include <type_traits>
 
 #include "recon.h"
@@ -56,6 +59,17 @@ __device__ inline void sincospi_f32(float x, float* s, float* c) {
   *c = ((qi + 1) & 2) ? -c0 : c0;
 }
 __device__ inline void sc_pi(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// sin and cos of a template phase psi (FP64, up to ~1e5 rad): psi reduced in FP64
+// to psi / (2 pi) - k in [-1/2, 1/2] turns, then the hardware sine and cosine of
+// an angle in turns (measured here at most 1.3e-7 from the exact values over
+// that range, about two units in the last place of 1).
+__device__ inline void phase_exp(double psi, float* s, float* c) {
+  const double k = rint(psi * 0.15915494309189533577);
+  const float x = float(fma(psi, 0.15915494309189533577, -k));
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
 
 template <typename V> __device__ inline V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
 template <typename V> __device__ inline V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
@@ -177,9 +191,6 @@ template <> struct Radix<64> { static constexpr int R1 = 8, R2 = 8; };
 template <> struct Radix<128> { static constexpr int R1 = 8, R2 = 16; };
 template <> struct Radix<256> { static constexpr int R1 = 16, R2 = 16; };
 
-#ifndef RF_TMPL_PER_BLOCK
-#define RF_TMPL_PER_BLOCK 16
-#endif
 // Columns per workgroup of the FP32 passes: 32 (256-byte runs of every row)
 // where the pass has a multiple of 32 columns, else 16; the workgroup has one
 // thread per butterfly of the larger of its two stages (P / R1 or R1 per column).
@@ -537,10 +548,8 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
             psi = fma(tc.exl, x * lf, psi);
             psi = fma(tc.exx, x * x, psi);
           }
-          const double k = rint(psi * 0.15915494309189533577);
-          const float x = float(fma(psi, 0.31830988618379067154, -2.0 * k));
           float sn, cs;
-          sincospi_f32(x, &sn, &cs);
+          phase_exp(psi, &sn, &cs);
           const float2 q = qs[fj - tin.jlo];
           v[i] = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
         }
@@ -565,6 +574,243 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
     }
     __syncthreads();
   }
+}
+
+// first pass of matched filters: templates per workgroup
+constexpr int kTmplPerBlock = 16;
+
+// ---------------------------------------------------------------- two-pass form
+// Matched filters of n = P_A P_B <= 2^21 samples in two passes (P_B = 1024):
+// pass A (k_tmpl_wide) forms each template's spectrum and takes P_A-point DFTs of
+// single columns through LDS; pass B (k_pass_wide) takes 1024-point DFTs of 16
+// columns (135 KB of LDS) and stores or reads out its outputs.  The intermediate
+// is written and read once, as a transform too large for the chip must.
+
+// Stockham stage (NS done, radix R) on C columns of P points in LDS: butterfly
+// beta = threadIdx.x + k NT (beta < C P / R) is column beta % C, index b = beta / C;
+// it takes elements b + q P / R, the twiddles w_P^(q (b mod NS) P / (NS R)), a
+// radix-R DFT, and writes elements (b / NS) NS R + b mod NS + q NS.
+template <int P, int C, int NT, int NS, int R, int ST>
+__device__ inline void lds_stage(float2 (*s)[ST], const float2* tw) {
+  constexpr int NB = C * P / R, K = (NB + NT - 1) / NT, Q = P / R;
+  float2 v[K][R];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int beta = int(threadIdx.x) + k * NT;
+    if (NB % NT == 0 || beta < NB) {
+      const int c = beta % C, b = beta / C, kk = b % NS;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[k][q] = s[c][sw(b + q * Q)];
+      if (NS > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[k][q] = cmul(v[k][q], tw[q * kk * (P / (NS * R))]);
+      }
+      Dft<float2, R>::run(v[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int beta = int(threadIdx.x) + k * NT;
+    if (NB % NT == 0 || beta < NB) {
+      const int c = beta % C, b = beta / C, kk = b % NS;
+      const int d = (b / NS) * NS * R + kk;
+#pragma unroll
+      for (int q = 0; q < R; ++q) s[c][sw(d + q * NS)] = v[k][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Radices of pass A: a radix-4 first butterfly (four bins a thread keep their
+// phase functions in registers at four waves per SIMD), then 8, 8 and 4 or 8.
+template <int PA> struct WideA;
+template <> struct WideA<1024> { static constexpr int R1 = 4, R2 = 8, R3 = 8, R4 = 4; };
+template <> struct WideA<2048> { static constexpr int R1 = 4, R2 = 8, R3 = 8, R4 = 8; };
+
+// Pass A of the two-pass matched filter: one column j (of n / PA) per workgroup,
+// PA / R1 threads; thread u forms bins j + (u + i PA / R1) n / PA (i < R1) of each
+// of TPW templates from x = f^(1/3), 1 / x and ln f computed once per bin (the
+// phase basis of k_fft_tmpl_pass), its first butterfly in registers, two radix-8
+// stages in LDS, and a last stage whose outputs b + q NS it stores from
+// registers: out[j PA + e].
+template <int PA, int TPW>
+__global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __restrict__ out, int32_t n, int batch,
+                                                                  TmplIn tin) {
+  using V = float2;
+  using W = WideA<PA>;
+  constexpr int R1 = W::R1, R2 = W::R2, R3 = W::R3, R4 = W::R4;
+  constexpr int NT = PA / R1, QA = PA / R1;
+  constexpr int NS4 = R1 * R2 * R3;                 // done before the last stage
+  constexpr int NL = PA / R4;                       // last-stage butterflies
+  constexpr int KL = (NL + NT - 1) / NT;            // per thread
+  static_assert(R1 * R2 * R3 * R4 == PA, "pass A radices");
+  constexpr int ST = PA + PA / 32 + 1;
+  __shared__ V s[1][ST];
+  __shared__ V tw[PA];
+  const int32_t ncols = n / PA;
+  const int u = int(threadIdx.x);
+  const int32_t j = int32_t(blockIdx.x);
+  for (int m = u; m < PA; m += NT) {
+    float sn, cs;
+    sincospi_f32(float(2 * m) / float(PA), &sn, &cs);
+    tw[m] = V{cs, sn};
+  }
+  const double tg = sqrt(4.0 * tin.df / *tin.moment);
+  double gx[R1], gi[R1], gl[R1];                    // x, 1 / x, ln f (in band: gx > 0)
+  float a0[R1];
+#pragma unroll
+  for (int i = 0; i < R1; ++i) {
+    gx[i] = 0.0;
+    gi[i] = 0.0;
+    gl[i] = 0.0;
+    a0[i] = 0.f;
+    const int32_t fj = j + (u + i * QA) * ncols;
+    if (fj >= tin.jlo && fj <= tin.jhi) {
+      const double f = double(fj) * tin.df;
+      double x = double(cbrtf(float(f)));
+      const float x32 = float(x);
+      x -= double(float(x * x * x - f) / (3.0f * x32 * x32));
+      gx[i] = x;
+      gi[i] = 1.0 / x;
+      gl[i] = log(f);
+      a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
+    }
+  }
+  const int y0 = int(blockIdx.y) * TPW;
+#pragma unroll 1
+  for (int t = 0; t < TPW && y0 + t < batch; ++t) {
+    const int y = y0 + t;
+    const Tf2Coef tc = tin.coef[y % tin.nt];
+    const float2* qs = tin.q + int64_t(y / tin.nt) * (tin.jhi - tin.jlo + 1);
+    V v[R1];
+#pragma unroll
+    for (int i = 0; i < R1; ++i) {
+      v[i] = V{0.f, 0.f};
+      if (gx[i] > 0.0) {
+        const int32_t fj = j + (u + i * QA) * ncols;
+        const double x = gx[i], ix = gi[i], lf = gl[i];
+        const double ix2 = ix * ix, ix3 = ix2 * ix;
+        double psi = fma(tc.e5, ix3 * ix2, tc.e0);
+        psi = fma(tc.e3, ix3, psi);
+        psi = fma(tc.e2, ix2, psi);
+        psi = fma(tc.e1, ix, psi);
+        psi = fma(tc.el, lf, psi);
+        psi = fma(tc.ex, x, psi);
+        psi = fma(tc.exl, x * lf, psi);
+        psi = fma(tc.exx, x * x, psi);
+        float sn, cs;
+        phase_exp(psi, &sn, &cs);
+        const float2 q = qs[fj - tin.jlo];
+        v[i] = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
+      }
+    }
+    Dft<V, R1>::run(v);
+#pragma unroll
+    for (int q = 0; q < R1; ++q) s[0][sw(R1 * u + q)] = v[q];
+    __syncthreads();
+    lds_stage<PA, 1, NT, R1, R2, ST>(s, tw);
+    lds_stage<PA, 1, NT, R1 * R2, R3, ST>(s, tw);
+    // last stage (NS = NS4, radix R4): butterflies b = u + k NT, outputs b + q NS4
+    float2* o = out + int64_t(y) * n + int64_t(j) * PA;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int b = u + k * NT;
+      if (NL % NT != 0 && b >= NL) break;
+      V w[R4];
+#pragma unroll
+      for (int q = 0; q < R4; ++q) w[q] = s[0][sw(b + q * NS4)];
+#pragma unroll
+      for (int q = 1; q < R4; ++q) w[q] = cmul(w[q], tw[q * b]);
+      Dft<V, R4>::run(w);
+#pragma unroll
+      for (int q = 0; q < R4; ++q) o[b + q * NS4] = w[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Pass B of the two-pass form (ns = n / 1024 < 2^21 / 1024 columns' worth of
+// pass A): 16 columns j of 1024 points per workgroup, 1024 threads; thread (c, u)
+// = (threadIdx % 16, threadIdx / 16) loads elements u + 64 i (i < 16) of column j,
+// applies the inter-pass twiddles, a radix-16 butterfly, one radix-16 stage in
+// LDS, and a radix-4 last stage whose outputs u + 64 k + 256 q it stores to
+// out[j + e ns], or reads out (RO) in rising order.
+constexpr int kWideB = 1024, kWideC = 16, kWideST = kWideB + kWideB / 32 + 1;
+template <bool RO>
+__global__ __launch_bounds__(1024) void k_pass_wide(const float2* __restrict__ in, float2* __restrict__ out,
+                                                    int32_t n, PeakOut po) {
+  using V = float2;
+  constexpr int C = kWideC, P = kWideB, NT = 1024;
+  __shared__ V s[C][kWideST];
+  __shared__ V tw[P];
+  const int32_t ns = n / P;                          // = columns of this pass
+  const int c = int(threadIdx.x) % C, u = int(threadIdx.x) / C;
+  const int32_t j = int32_t(blockIdx.x) * C + c;
+  in += int64_t(blockIdx.y) * n;
+  out += int64_t(blockIdx.y) * n;
+  for (int m = int(threadIdx.x); m < P; m += NT) {
+    float sn, cs;
+    sincospi_f32(float(2 * m) / float(P), &sn, &cs);
+    tw[m] = V{cs, sn};
+  }
+  V v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = in[j + (u + i * 64) * ns];
+  // w_n^(r j), r = u + 64 i; j < ns so j mod ns = j; 2 / n is exact
+  apply_twiddles<16, 64>(v, uint32_t(u), uint32_t(j), 2.f / float(n));
+  Dft<V, 16>::run(v);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s[c][sw(16 * u + q)] = v[q];
+  __syncthreads();
+  lds_stage<P, C, NT, 16, 16, kWideST>(s, tw);
+  // last stage (NS = 256, radix 4): butterflies b = u + 64 k (k < 4) of column c
+  V w[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = u + 64 * k;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[k][q] = s[c][sw(b + q * 256)];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) w[k][q] = cmul(w[k][q], tw[q * b]);
+    Dft<V, 4>::run(w[k]);
+  }
+  if constexpr (RO) {
+    Best best{-1.f, INT32_MAX};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        peak_visit_rising(best, w[k][q].x, w[k][q].y, j + (u + 64 * k + 256 * q) * ns, po);
+    peak_commit(best, po);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[j + (u + 64 * k + 256 * q) * ns] = w[k][q];
+  }
+}
+
+// the two-pass form applies to n = 2^20 and 2^21
+bool wide_tmpl(int64_t n) { return n == (int64_t(1) << 20) || n == (int64_t(1) << 21); }
+
+void launch_tmpl_wide(float2* mid, const float2* mid_in, float2* out, int64_t n, int batch, hipStream_t st,
+                      const TmplIn& tin, const PeakOut* ro) {
+  const int64_t PA = n / kWideB;
+  dim3 ga(unsigned(n / PA), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
+  if (PA == 1024)
+    hipLaunchKernelGGL((k_tmpl_wide<1024, kTmplPerBlock>), ga, dim3(1024 / WideA<1024>::R1), 0, st, mid,
+                       int32_t(n), batch, tin);
+  else
+    hipLaunchKernelGGL((k_tmpl_wide<2048, kTmplPerBlock>), ga, dim3(2048 / WideA<2048>::R1), 0, st, mid,
+                       int32_t(n), batch, tin);
+  RF_HIP(hipGetLastError());
+  dim3 gb(unsigned(PA / kWideC), unsigned(batch));
+  if (ro)
+    hipLaunchKernelGGL(k_pass_wide<true>, gb, dim3(1024), 0, st, mid_in, nullptr, int32_t(n), *ro);
+  else
+    hipLaunchKernelGGL(k_pass_wide<false>, gb, dim3(1024), 0, st, mid_in, out, int32_t(n), PeakOut{});
+  RF_HIP(hipGetLastError());
 }
 
 // Split log2(n) into at least two passes of at most 8 bits each (16 columns per
@@ -641,8 +887,6 @@ void launch_pass32(int bits, const float2* in, float2* out, int64_t n, int64_t n
   RF_HIP(hipGetLastError());
 }
 
-// first pass of matched filters: templates per workgroup
-constexpr int kTmplPerBlock = RF_TMPL_PER_BLOCK;
 
 void launch_tmpl_pass(int bits, float2* out, int64_t n, int batch, hipStream_t st, const TmplIn& tin) {
   const int64_t cols = n >> bits;
@@ -679,6 +923,13 @@ void fft_inverse(rf_ctx* ctx, const typename C2<T>::t* in, typename C2<T>::t* ou
   using V = typename C2<T>::t;
   RF_CHECK(is_pow2(n) && n >= 256 && n <= (int64_t(1) << 24), "fft: n must be a power of two in [2^8, 2^24]");
   const int lg = ilog2(n);
+  if constexpr (std::is_same<T, float>::value) {
+    if (tmpl && wide_tmpl(n)) {        // two passes through one intermediate
+      V* mid = wsa_in ? wsa_in : static_cast<V*>(ctx->ws[WS_FFT_A].ensure(sizeof(V) * size_t(n) * batch));
+      launch_tmpl_wide(mid, mid, out, n, batch, ctx->stream, *tmpl, ro);
+      return;
+    }
+  }
   std::vector<int> bits = plan_passes(lg, std::is_same<T, float>::value);
   const int s = int(bits.size());
   V* wa = nullptr;
