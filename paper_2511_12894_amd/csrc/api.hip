@@ -326,6 +326,7 @@ rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const d
       fft_inverse_tmpl_peaks_f32(ctx, grid, q, coef_dev + t0, cnt, moment, cnt, po);
     }
     peaks_finalize(ctx, packed, nt, out->peaks);
+    trig_finish(ctx, out->trig, po.count, out->cap);   // the passes wrote raw (re, im)
     unsigned long long c = 0;
     RF_HIP(hipMemcpyAsync(&c, po.count, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);

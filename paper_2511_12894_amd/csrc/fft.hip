@@ -423,7 +423,7 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_pass32(const float2* __
     Best best{-1.f, INT32_MAX};
     if (u < R1) {
 #pragma unroll
-      for (int q = 0; q < R2; ++q) peak_visit_rising(best, v[q].x, v[q].y, base + (u + q * R1) * ns, po);
+      for (int q = 0; q < R2; ++q) peak_visit_rising_raw(best, v[q].x, v[q].y, base + (u + q * R1) * ns, po);
     }
     peak_commit(best, po);
     return;
@@ -730,12 +730,12 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
   }
 }
 
-// Pass B of the two-pass form (ns = n / 1024 < 2^21 / 1024 columns' worth of
-// pass A): 16 columns j of 1024 points per workgroup, 1024 threads; thread (c, u)
-// = (threadIdx % 16, threadIdx / 16) loads elements u + 64 i (i < 16) of column j,
-// applies the inter-pass twiddles, a radix-16 butterfly, one radix-16 stage in
-// LDS, and a radix-4 last stage whose outputs u + 64 k + 256 q it stores to
-// out[j + e ns], or reads out (RO) in rising order.
+// Pass B of the two-pass form (ns = n / 1024 columns of 1024 points): 16 columns
+// j per workgroup, 1024 threads; thread (c, u) = (threadIdx % 16, threadIdx / 16)
+// loads elements u + 64 i (i < 16) of column j, applies the inter-pass twiddles,
+// a radix-16 butterfly, one radix-16 stage in LDS and a radix-4 last stage whose
+// outputs u + 64 k + 256 q it stores to out[j + e ns], or reads out (RO, trigger
+// records raw until trig_finish).
 constexpr int kWideB = 1024, kWideC = 16, kWideST = kWideB + kWideB / 32 + 1;
 template <bool RO>
 __global__ __launch_bounds__(1024) void k_pass_wide(const float2* __restrict__ in, float2* __restrict__ out,
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(1024) void k_pass_wide(const float2* __restrict__ i
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        peak_visit_rising(best, w[k][q].x, w[k][q].y, j + (u + 64 * k + 256 * q) * ns, po);
+        peak_visit_rising_raw(best, w[k][q].x, w[k][q].y, j + (u + 64 * k + 256 * q) * ns, po);
     peak_commit(best, po);
   } else {
 #pragma unroll

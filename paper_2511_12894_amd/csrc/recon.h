@@ -73,6 +73,23 @@ __device__ inline void crossing(float a2, float re, float im, int64_t m, const P
   }
 }
 
+// The same, the record holding the raw (re, im) in (absz, argz) for trig_finish
+// to complete after the launch (the read-out code stays small).
+__device__ inline void crossing_raw(float a2, float re, float im, int64_t m, const PeakOut& po) {
+  if (a2 > po.thr2) {
+    const unsigned long long slot_t = atomicAdd(po.count, 1ull);
+    if (int64_t(slot_t) < po.cap) {
+      rf_trigger tr;
+      tr.tmpl = po.tmpl0 + int32_t(blockIdx.y);
+      tr.seg = po.seg;
+      tr.idx = int32_t(m);
+      tr.absz = re;
+      tr.argz = im;
+      po.trig[slot_t] = tr;
+    }
+  }
+}
+
 // One sample of a read-out: running peak and threshold crossing.
 __device__ inline void peak_visit(Best& best, float re, float im, int64_t m, const PeakOut& po) {
   const float a2 = abs2_rn(re, im);
@@ -90,6 +107,15 @@ __device__ inline void peak_visit_rising(Best& best, float re, float im, int32_t
     best.idx = m;
   }
   crossing(a2, re, im, m, po);
+}
+// ... with raw trigger records (trig_finish completes them)
+__device__ inline void peak_visit_rising_raw(Best& best, float re, float im, int32_t m, const PeakOut& po) {
+  const float a2 = abs2_rn(re, im);
+  if (a2 > best.a2) {
+    best.a2 = a2;
+    best.idx = m;
+  }
+  crossing_raw(a2, re, im, m, po);
 }
 
 // A workgroup's running peaks (every thread's) merged into packed[seg * nk +
@@ -162,7 +188,8 @@ void peaks_finalize(rf_ctx* ctx, const uint64_t* packed, int64_t count, rf_peak*
 void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count, int64_t cap);
 // Matched filter of `batch` templates (a multiple of nt, coefficients coef[b % nt])
 // against the conditioned data q, as fft_inverse_tmpl_f32, with the last
-// transform pass reading the series out into po instead of storing them.
+// transform pass reading the series out into po instead of storing them; its
+// trigger records hold the raw (re, im) until trig_finish.
 void fft_inverse_tmpl_peaks_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
                                 const double* moment, int batch, const PeakOut& po);
 
