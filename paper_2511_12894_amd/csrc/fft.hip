@@ -650,7 +650,10 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
   __shared__ V tw[PA];
   const int32_t ncols = n / PA;
   const int u = int(threadIdx.x);
-  const int32_t j = int32_t(blockIdx.x);
+  // workgroups go to the 8 XCDs in turn: give each XCD a contiguous range of
+  // columns, so the workgroups running together on one XCD read neighbouring
+  // bins of the conditioned data and share its cache lines in that XCD's L2
+  const int32_t j = int32_t(blockIdx.x % 8u) * (ncols / 8) + int32_t(blockIdx.x / 8u);
   for (int m = u; m < PA; m += NT) {
     float sn, cs;
     sincospi_f32(float(2 * m) / float(PA), &sn, &cs);
@@ -797,6 +800,7 @@ bool wide_tmpl(int64_t n) { return n == (int64_t(1) << 20) || n == (int64_t(1) <
 void launch_tmpl_wide(float2* mid, const float2* mid_in, float2* out, int64_t n, int batch, hipStream_t st,
                       const TmplIn& tin, const PeakOut* ro) {
   const int64_t PA = n / kWideB;
+  RF_CHECK((n / PA) % 8 == 0, "fft: two-pass form needs a multiple of 8 columns");
   dim3 ga(unsigned(n / PA), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
   if (PA == 1024)
     hipLaunchKernelGGL((k_tmpl_wide<1024, kTmplPerBlock>), ga, dim3(1024 / WideA<1024>::R1), 0, st, mid,
