@@ -681,17 +681,31 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
     }
   }
   const int y0 = int(blockIdx.y) * TPW;
+  // the conditioned data times f^(-7/6) of the thread's bins, for the segment of
+  // the templates in hand (read again only when the segment changes)
+  V aq[R1];
+  int seg = -1;
 #pragma unroll 1
   for (int t = 0; t < TPW && y0 + t < batch; ++t) {
     const int y = y0 + t;
     const Tf2Coef tc = tin.coef[y % tin.nt];
-    const float2* qs = tin.q + int64_t(y / tin.nt) * (tin.jhi - tin.jlo + 1);
+    if (y / tin.nt != seg) {
+      seg = y / tin.nt;
+      const float2* qs = tin.q + int64_t(seg) * (tin.jhi - tin.jlo + 1);
+#pragma unroll
+      for (int i = 0; i < R1; ++i) {
+        aq[i] = V{0.f, 0.f};
+        if (gx[i] > 0.0) {
+          const float2 q = qs[j + (u + i * QA) * ncols - tin.jlo];
+          aq[i] = V{a0[i] * q.x, a0[i] * q.y};
+        }
+      }
+    }
     V v[R1];
 #pragma unroll
     for (int i = 0; i < R1; ++i) {
       v[i] = V{0.f, 0.f};
       if (gx[i] > 0.0) {
-        const int32_t fj = j + (u + i * QA) * ncols;
         const double x = gx[i], ix = gi[i], lf = gl[i];
         const double ix2 = ix * ix, ix3 = ix2 * ix;
         double psi = fma(tc.e5, ix3 * ix2, tc.e0);
@@ -704,8 +718,7 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
         psi = fma(tc.exx, x * x, psi);
         float sn, cs;
         phase_exp(psi, &sn, &cs);
-        const float2 q = qs[fj - tin.jlo];
-        v[i] = V{a0[i] * (q.x * cs - q.y * sn), a0[i] * (q.x * sn + q.y * cs)};
+        v[i] = cmul(aq[i], V{cs, sn});
       }
     }
     Dft<V, R1>::run(v);
