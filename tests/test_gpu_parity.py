@@ -117,6 +117,31 @@ def test_mf_ref_snr_many_templates_and_tiny_grid(rf, ctx):
             assert sig[i] == pytest.approx(no, rel=1e-12)
 
 
+def test_two_pass_matched_filter_sizes(rf, ctx):
+    """The two-pass form (n = 2^20: 1024 x 1024 points; n = 2^21: 2048 x 1024) on
+    a few templates: every sample of the stored series within 1e-5 of the FP64
+    oracle, and the read-out inside the second pass equal to the read-out of the
+    stored series, bit for bit, crossings included."""
+    for n, fs in ((1 << 20, 4096.0), (1 << 21, 4096.0)):
+        g = synth.make_grid(fs, n, 20.0)
+        psd = synth.make_psd(g)
+        xf = synth.noise(g, psd, seed=31 + n)
+        tm = [(1.4, 1.3), (2.6, 1.9), (1.1, 1.0)]
+        _say(f"two-pass mf n={n}")
+        xf_d, psd_d = _dev(xf, torch.complex128), _dev(psd, torch.float64)
+        z, sig = rf.mf_ref_snr(ctx, g, xf_d, psd_d, tm)
+        thr = float(0.6 * z.abs().max().item())
+        a = rf.mf_snr_peaks(ctx, g, xf_d, psd_d, tm, thr, trig_cap=1 << 18)
+        b = rf.snr_peaks(ctx, z, thr, trig_cap=1 << 18)
+        assert not a["overflow"] and not b["overflow"]
+        _same_readout(rf, a, b)
+        zc = z.cpu().numpy()
+        for i, t in enumerate(tm):
+            zo, no = omf.grid_snr_series(g, xf, psd, *t)
+            assert np.abs(zc[i] - zo).max() <= TOL_SAME_KERNELS
+            assert sig[i] == pytest.approx(no, rel=1e-12)
+
+
 def test_direct_mf_of_neighbours(rf, ctx, small, small_gpu):
     w = small["w"]
     z, _ = rf.mf_ref_snr(ctx, w["grid"], small_gpu["xf"], small_gpu["psd"], w["nbrs"])
