@@ -18,9 +18,10 @@
 // first pass may form its input on the fly instead of reading it: the
 // band-limited products of the factored reconstruction, or a matched filter's
 // weighted template spectrum (FP64 phase), so neither is ever stored.  Matched
-// filters of 2^20 and 2^21 samples take two passes instead of three (a 1024- or
-// 2048-point first pass of one column per workgroup, then 1024-point columns,
-// 16 a workgroup, in 135 KB of LDS), so their intermediate crosses HBM once.
+// filters of 2^20 to 2^23 samples take two passes instead of three (a 1024- to
+// 4096-point first pass of one column per workgroup, then 1024- or 2048-point
+// columns, 16 or 8 a workgroup, in 135 KB of LDS), so their intermediate crosses
+// HBM once.
 // FP64 passes (kernel builds) run the P-point DFT in LDS as a short
 // in-workgroup Stockham sequence of radix-8/4/2 butterflies.
 #include <type_traits>
@@ -580,10 +581,10 @@ __global__ __launch_bounds__((threads32<P, C>())) void k_fft_tmpl_pass(float2* _
 constexpr int kTmplPerBlock = 16;
 
 // ---------------------------------------------------------------- two-pass form
-// Matched filters of n = P_A P_B <= 2^21 samples in two passes (P_B = 1024):
-// pass A (k_tmpl_wide) forms each template's spectrum and takes P_A-point DFTs of
-// single columns through LDS; pass B (k_pass_wide) takes 1024-point DFTs of 16
-// columns (135 KB of LDS) and stores or reads out its outputs.  The intermediate
+// Matched filters of n = P_A P_B <= 2^23 samples in two passes (P_B = 1024 up to
+// 2^21, then 2048): pass A (k_tmpl_wide) forms each template's spectrum and takes
+// P_A-point DFTs of single columns through LDS; pass B (k_pass_wide) takes P_B-point
+// DFTs of 16 or 8 columns (135 KB of LDS) and stores or reads out its outputs.  The intermediate
 // is written and read once, as a transform too large for the chip must.
 
 // Stockham stage (NS done, radix R) on C columns of P points in LDS: butterfly
@@ -623,16 +624,18 @@ __device__ inline void lds_stage(float2 (*s)[ST], const float2* tw) {
 }
 
 // Radices of pass A: a radix-4 first butterfly (four bins a thread keep their
-// phase functions in registers at four waves per SIMD), then 8, 8 and 4 or 8.
+// phase functions in registers at four waves per SIMD), then 8, 8 and 4 or 8;
+// at 4096 points 16, 8 and 8 (the order that fits 128 registers a thread).
 template <int PA> struct WideA;
 template <> struct WideA<1024> { static constexpr int R1 = 4, R2 = 8, R3 = 8, R4 = 4; };
 template <> struct WideA<2048> { static constexpr int R1 = 4, R2 = 8, R3 = 8, R4 = 8; };
+template <> struct WideA<4096> { static constexpr int R1 = 4, R2 = 16, R3 = 8, R4 = 8; };
 
 // Pass A of the two-pass matched filter: one column j (of n / PA) per workgroup,
 // PA / R1 threads; thread u forms bins j + (u + i PA / R1) n / PA (i < R1) of each
 // of TPW templates from x = f^(1/3), 1 / x and ln f computed once per bin (the
-// phase basis of k_fft_tmpl_pass), its first butterfly in registers, two radix-8
-// stages in LDS, and a last stage whose outputs b + q NS it stores from
+// phase basis of k_fft_tmpl_pass), its first butterfly in registers, two stages
+// in LDS (radices R2, R3), and a last stage whose outputs b + q NS it stores from
 // registers: out[j PA + e].
 template <int PA, int TPW>
 __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __restrict__ out, int32_t n, int batch,
@@ -661,13 +664,11 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
   }
   const double tg = sqrt(4.0 * tin.df / *tin.moment);
   double gx[R1], gi[R1], gl[R1];                    // x, 1 / x, ln f (in band: gx > 0)
-  float a0[R1];
 #pragma unroll
   for (int i = 0; i < R1; ++i) {
     gx[i] = 0.0;
     gi[i] = 0.0;
     gl[i] = 0.0;
-    a0[i] = 0.f;
     const int32_t fj = j + (u + i * QA) * ncols;
     if (fj >= tin.jlo && fj <= tin.jhi) {
       const double f = double(fj) * tin.df;
@@ -677,7 +678,6 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
       gx[i] = x;
       gi[i] = 1.0 / x;
       gl[i] = log(f);
-      a0[i] = float(tg) / (float(f) * sqrtf(float(x)));
     }
   }
   const int y0 = int(blockIdx.y) * TPW;
@@ -696,8 +696,10 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
       for (int i = 0; i < R1; ++i) {
         aq[i] = V{0.f, 0.f};
         if (gx[i] > 0.0) {
-          const float2 q = qs[j + (u + i * QA) * ncols - tin.jlo];
-          aq[i] = V{a0[i] * q.x, a0[i] * q.y};
+          const int32_t fj = j + (u + i * QA) * ncols;
+          const float2 q = qs[fj - tin.jlo];
+          const float a0 = float(tg) / (float(double(fj) * tin.df) * sqrtf(float(gx[i])));
+          aq[i] = V{a0 * q.x, a0 * q.y};
         }
       }
     }
@@ -706,7 +708,11 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
     for (int i = 0; i < R1; ++i) {
       v[i] = V{0.f, 0.f};
       if (gx[i] > 0.0) {
-        const double x = gx[i], ix = gi[i], lf = gl[i];
+        double x = gx[i], ix = gi[i], lf = gl[i];
+        // at 4096 points the products of x, 1 / x and ln f are formed again for
+        // every template rather than held across the loop: 1024 threads a
+        // workgroup leave 128 registers a thread
+        if constexpr (PA >= 4096) asm volatile("" : "+v"(x), "+v"(ix), "+v"(lf));
         const double ix2 = ix * ix, ix3 = ix2 * ix;
         double psi = fma(tc.e5, ix3 * ix2, tc.e0);
         psi = fma(tc.e3, ix3, psi);
@@ -746,25 +752,34 @@ __global__ __launch_bounds__(PA / WideA<PA>::R1) void k_tmpl_wide(float2* __rest
   }
 }
 
-// Pass B of the two-pass form (ns = n / 1024 columns of 1024 points): 16 columns
-// j per workgroup, 1024 threads; thread (c, u) = (threadIdx % 16, threadIdx / 16)
-// loads elements u + 64 i (i < 16) of column j, applies the inter-pass twiddles,
-// a radix-16 butterfly, one radix-16 stage in LDS and a radix-4 last stage whose
-// outputs u + 64 k + 256 q it stores to out[j + e ns], or reads out (RO, trigger
-// records raw until trig_finish).
-constexpr int kWideB = 1024, kWideC = 16, kWideST = kWideB + kWideB / 32 + 1;
-template <bool RO>
+// Pass B of the two-pass form (ns = n / P columns of P = 1024 or 2048 points):
+// C = 16 or 8 columns j per workgroup, 1024 threads; thread (c, u) = (threadIdx %
+// C, threadIdx / C), u < U = P / 16, loads elements u + U i (i < 16) of column j,
+// applies the inter-pass twiddles, a radix-16 butterfly, one radix-16 stage in
+// LDS and a radix-(P / 256) last stage whose outputs u + U k + 256 q it stores to
+// out[j + e ns], or reads out (RO, trigger records raw until trig_finish).  With
+// 8 columns (64 bytes of a row) per workgroup, each XCD takes a contiguous range
+// of column groups, so the two halves of a 128-byte line go to one L2 together.
+template <int P> struct WideB {
+  static constexpr int C = 16384 / P, U = P / 16, R3 = P / 256, K = 256 / U;
+  static constexpr int ST = P + P / 32 + 1;
+};
+template <int P, bool RO>
 __global__ __launch_bounds__(1024) void k_pass_wide(const float2* __restrict__ in, float2* __restrict__ out,
                                                     int32_t n, PeakOut po) {
   using V = float2;
-  constexpr int C = kWideC, P = kWideB, NT = 1024;
-  __shared__ V s[C][kWideST];
+  using W = WideB<P>;
+  constexpr int C = W::C, U = W::U, R3 = W::R3, K = W::K, NT = 1024;
+  static_assert(C * U == NT && U * K == 256 && 256 * R3 == P, "pass B shape");
+  __shared__ V s[C][W::ST];
   __shared__ V tw[P];
   const int32_t ns = n / P;                          // = columns of this pass
   const int c = int(threadIdx.x) % C, u = int(threadIdx.x) / C;
-  const int32_t j = int32_t(blockIdx.x) * C + c;
+  int32_t grp = int32_t(blockIdx.x);
+  if (C < 16) grp = int32_t(blockIdx.x % 8u) * int32_t(gridDim.x / 8u) + int32_t(blockIdx.x / 8u);
+  const int32_t j = grp * C + c;
   in += int64_t(blockIdx.y) * n;
-  out += int64_t(blockIdx.y) * n;
+  if (!RO) out += int64_t(blockIdx.y) * n;
   for (int m = int(threadIdx.x); m < P; m += NT) {
     float sn, cs;
     sincospi_f32(float(2 * m) / float(P), &sn, &cs);
@@ -772,61 +787,79 @@ __global__ __launch_bounds__(1024) void k_pass_wide(const float2* __restrict__ i
   }
   V v[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = in[j + (u + i * 64) * ns];
-  // w_n^(r j), r = u + 64 i; j < ns so j mod ns = j; 2 / n is exact
-  apply_twiddles<16, 64>(v, uint32_t(u), uint32_t(j), 2.f / float(n));
+  for (int i = 0; i < 16; ++i) v[i] = in[j + (u + i * U) * ns];
+  // w_n^(r j), r = u + U i; j < ns so j mod ns = j; 2 / n is exact
+  apply_twiddles<16, U>(v, uint32_t(u), uint32_t(j), 2.f / float(n));
   Dft<V, 16>::run(v);
 #pragma unroll
   for (int q = 0; q < 16; ++q) s[c][sw(16 * u + q)] = v[q];
   __syncthreads();
-  lds_stage<P, C, NT, 16, 16, kWideST>(s, tw);
-  // last stage (NS = 256, radix 4): butterflies b = u + 64 k (k < 4) of column c
-  V w[4][4];
+  lds_stage<P, C, NT, 16, 16, W::ST>(s, tw);
+  // last stage (NS = 256, radix R3): butterflies b = u + U k (k < K) of column c
+  V w[K][R3];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int b = u + 64 * k;
+  for (int k = 0; k < K; ++k) {
+    const int b = u + U * k;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w[k][q] = s[c][sw(b + q * 256)];
+    for (int q = 0; q < R3; ++q) w[k][q] = s[c][sw(b + q * 256)];
 #pragma unroll
-    for (int q = 1; q < 4; ++q) w[k][q] = cmul(w[k][q], tw[q * b]);
-    Dft<V, 4>::run(w[k]);
+    for (int q = 1; q < R3; ++q) w[k][q] = cmul(w[k][q], tw[q * b]);
+    Dft<V, R3>::run(w[k]);
   }
   if constexpr (RO) {
     Best best{-1.f, INT32_MAX};
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < R3; ++q)
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        peak_visit_rising_raw(best, w[k][q].x, w[k][q].y, j + (u + 64 * k + 256 * q) * ns, po);
+      for (int k = 0; k < K; ++k)
+        peak_visit_rising_raw(best, w[k][q].x, w[k][q].y, j + (u + U * k + 256 * q) * ns, po);
     peak_commit(best, po);
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < R3; ++q)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) out[j + (u + 64 * k + 256 * q) * ns] = w[k][q];
+      for (int k = 0; k < K; ++k) out[j + (u + U * k + 256 * q) * ns] = w[k][q];
   }
 }
 
-// the two-pass form applies to n = 2^20 and 2^21
-bool wide_tmpl(int64_t n) { return n == (int64_t(1) << 20) || n == (int64_t(1) << 21); }
+// the two-pass form applies to n = 2^20 ... 2^23
+bool wide_tmpl(int64_t n) { return n >= (int64_t(1) << 20) && n <= (int64_t(1) << 23); }
+
+// second-pass length: 1024 points up to n = 2^21, 2048 above
+int64_t wide_pb(int64_t n) { return n <= (int64_t(1) << 21) ? 1024 : 2048; }
 
 void launch_tmpl_wide(float2* mid, const float2* mid_in, float2* out, int64_t n, int batch, hipStream_t st,
                       const TmplIn& tin, const PeakOut* ro) {
-  const int64_t PA = n / kWideB;
-  RF_CHECK((n / PA) % 8 == 0, "fft: two-pass form needs a multiple of 8 columns");
-  dim3 ga(unsigned(n / PA), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
-  if (PA == 1024)
-    hipLaunchKernelGGL((k_tmpl_wide<1024, kTmplPerBlock>), ga, dim3(1024 / WideA<1024>::R1), 0, st, mid,
-                       int32_t(n), batch, tin);
-  else
-    hipLaunchKernelGGL((k_tmpl_wide<2048, kTmplPerBlock>), ga, dim3(2048 / WideA<2048>::R1), 0, st, mid,
-                       int32_t(n), batch, tin);
+  const int64_t PB = wide_pb(n), PA = n / PB;
+  RF_CHECK(PB % 8 == 0 && (PA / WideB<2048>::C) % 8 == 0, "fft: two-pass form needs a multiple of 8 columns");
+  dim3 ga(unsigned(PB), unsigned((batch + kTmplPerBlock - 1) / kTmplPerBlock));
+  switch (PA) {
+#define RF_WIDE_CASE(P)                                                                                 \
+  case P:                                                                                               \
+    hipLaunchKernelGGL((k_tmpl_wide<P, kTmplPerBlock>), ga, dim3(P / WideA<P>::R1), 0, st, mid, int32_t(n), \
+                       batch, tin);                                                                     \
+    break;
+    RF_WIDE_CASE(1024)
+    RF_WIDE_CASE(2048)
+    RF_WIDE_CASE(4096)
+#undef RF_WIDE_CASE
+    default:
+      throw Error{RF_E_UNSUPPORTED, "fft: unsupported two-pass size"};
+  }
   RF_HIP(hipGetLastError());
-  dim3 gb(unsigned(PA / kWideC), unsigned(batch));
-  if (ro)
-    hipLaunchKernelGGL(k_pass_wide<true>, gb, dim3(1024), 0, st, mid_in, nullptr, int32_t(n), *ro);
-  else
-    hipLaunchKernelGGL(k_pass_wide<false>, gb, dim3(1024), 0, st, mid_in, out, int32_t(n), PeakOut{});
+  if (PB == 1024) {
+    dim3 gb(unsigned(PA / WideB<1024>::C), unsigned(batch));
+    if (ro)
+      hipLaunchKernelGGL((k_pass_wide<1024, true>), gb, dim3(1024), 0, st, mid_in, nullptr, int32_t(n), *ro);
+    else
+      hipLaunchKernelGGL((k_pass_wide<1024, false>), gb, dim3(1024), 0, st, mid_in, out, int32_t(n), PeakOut{});
+  } else {
+    dim3 gb(unsigned(PA / WideB<2048>::C), unsigned(batch));
+    if (ro)
+      hipLaunchKernelGGL((k_pass_wide<2048, true>), gb, dim3(1024), 0, st, mid_in, nullptr, int32_t(n), *ro);
+    else
+      hipLaunchKernelGGL((k_pass_wide<2048, false>), gb, dim3(1024), 0, st, mid_in, out, int32_t(n), PeakOut{});
+  }
   RF_HIP(hipGetLastError());
 }
 

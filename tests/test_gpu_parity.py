@@ -118,12 +118,14 @@ def test_mf_ref_snr_many_templates_and_tiny_grid(rf, ctx):
 
 
 def test_two_pass_matched_filter_sizes(rf, ctx):
-    """The two-pass form (n = 2^20: 1024 x 1024 points; n = 2^21: 2048 x 1024) on
-    a few templates: every sample of the stored series within 1e-5 of the FP64
-    oracle, and the read-out inside the second pass equal to the read-out of the
-    stored series, bit for bit, crossings included."""
-    for n, fs in ((1 << 20, 4096.0), (1 << 21, 4096.0)):
-        g = synth.make_grid(fs, n, 20.0)
+    """The two-pass form (n = 2^20: 1024 x 1024 points; 2^21: 2048 x 1024; 2^22:
+    2048 x 2048; 2^23: 4096 x 2048) on a few templates: every sample of the
+    stored series within 1e-5 of the FP64 oracle, and the read-out inside the
+    second pass equal to the read-out of the stored series, bit for bit,
+    crossings included."""
+    for n, fs, fl in ((1 << 20, 4096.0, 20.0), (1 << 21, 4096.0, 20.0), (1 << 22, 4096.0, 20.0),
+                      (1 << 23, 4096.0, 10.0)):
+        g = synth.make_grid(fs, n, fl)
         psd = synth.make_psd(g)
         xf = synth.noise(g, psd, seed=31 + n)
         tm = [(1.4, 1.3), (2.6, 1.9), (1.1, 1.0)]
