@@ -864,7 +864,7 @@ def c2_legs(dev, args, legs):
     lens = np.array(info["len"])
     sum_l = int(lens.sum())
     corr_steps, all_steps = K.split_steps(1024)
-    exec_taps = all_steps * 16 * 32                 # 16-tap steps of 32-kernel tiles
+    exec_taps = all_steps * 16 * 32                 # steps in units of a 32-kernel tile's step
     corr_frac = corr_steps / max(all_steps, 1)      # steps that also take the two correction products
     log(f"bench: kernel build {build_s:.3f} s, taps {lens.min()}..{lens.max()} (sum {sum_l})")
 

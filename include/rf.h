@@ -146,14 +146,18 @@ rf_status rf_kernels_info(const rf_kernels* k, int32_t* nk, int64_t* m_lo, int32
 rf_status rf_kernels_taps_fp64(const rf_kernels* k, int32_t idx, double* host_out);
 /* Work of the split-FP16 reconstruction with window chunks of `chunk` taps (a
  * multiple of 256 in [256, 1024]; single calls use 1024): *all_steps receives the
- * number of 16-tap steps over all 32-kernel tiles, *corr_steps the number of
- * those that carry the two correction products: a step takes the hi*hi
- * product alone when no kernel of its tile has a tap with |w| s_k >= 1/2 (s_k
- * the kernel's FP16 scale; such taps are below 2^-14 of the kernel's largest)
- * in the 512-tap block, counted from the tile's first tap, that holds the
- * step.  Neither count depends on `chunk` (the correction pass uses 512-tap
- * chunks whatever the first pass uses); it is checked for validity only.
- * Either pointer may be NULL.  Synchronises (reads the tiles' granule flags). */
+ * number of 16-tap steps over all tiles, *corr_steps the number of those that
+ * carry the two correction products, both in units of a 32-kernel tile's step
+ * (kernels sorted by first tap fill tiles of 32; a last tile of at most 16
+ * kernels is paired: each kernel also sits in a second column 32 taps later,
+ * its support extended by 32 taps, and one of its steps counts one half).  A
+ * step takes the hi*hi product alone when no column of its tile has a tap with
+ * |w| s_k >= 1/2 (s_k the kernel's FP16 scale; such taps are below 2^-14 of the
+ * kernel's largest) in the 512-tap block, counted from the tile's first tap,
+ * that holds the step.  Neither count depends on `chunk` (the correction pass
+ * uses 512-tap chunks whatever the first pass uses); it is checked for validity
+ * only.  Either pointer may be NULL.  Synchronises (reads the tiles' granule
+ * flags). */
 rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* corr_steps, int64_t* all_steps);
 rf_status rf_kernels_free(rf_kernels* k);
 

@@ -134,7 +134,9 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
   if (K->total_taps)
     RF_HIP(hipMemcpy(K->taps64, taps_host.data(), sizeof(double) * taps_host.size(), hipMemcpyHostToDevice));
 
-  // tiles: kernels sorted by first tap, 32 per tile, union support per tile
+  // tiles: kernels sorted by first tap, 32 per tile, union support per tile; a
+  // last tile of at most 16 kernels is paired (each kernel in two columns, the
+  // second 32 taps later), so it costs half a tile's matrix products
   std::vector<int32_t> order(nk);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return K->m_lo[a] < K->m_lo[b]; });
@@ -164,7 +166,12 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
       T.ksteps = 0;
     } else {
       T.m0 = lo & ~int64_t(3);            // a multiple of 4: the window refill moves 4-sample blocks
-      T.ksteps = ((hi - T.m0 + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign;
+      auto steps_for = [&](int64_t end) { return ((end - T.m0 + 16 * kStepAlign - 1) / (16 * kStepAlign)) * kStepAlign; };
+      T.ksteps = steps_for(hi);
+      if (T.count <= kPairKernels && steps_for(hi + kPairShift) * 16 <= K->n_build) {
+        T.pair = 1;
+        T.ksteps = steps_for(hi + kPairShift);
+      }
     }
     T.b32_off = b32_total;
     T.b16_off = b16_total;
@@ -491,13 +498,14 @@ rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* co
   int64_t corr = 0, all = 0;
   for (const rf::TileDev& T : k->tiles) {
     const int64_t ntaps = T.ksteps * 16;
-    all += T.ksteps;
+    const int64_t per = T.pair ? 2 : 1;     // a paired tile's step is half a step's products
+    all += T.ksteps / per;                  // ksteps: a multiple of 8
     // the corrections run over chunks of kCorrChunk taps, whatever `chunk` is
     for (int64_t t0 = 0; t0 < ntaps; t0 += rf::kCorrChunk) {
       const int64_t b = std::min<int64_t>(t0 + rf::kCorrChunk, ntaps);
       uint32_t need = 0;
       for (int64_t g = t0 / 256; g < (b + 255) / 256; ++g) need |= flags[size_t(T.gflag_off + g)];
-      if (need & 1) corr += (b - t0) / 16;   // bit 1: the correction products
+      if (need & 1) corr += (b - t0) / 16 / per;   // bit 1: the correction products
     }
   }
   if (corr_steps) *corr_steps = corr;

@@ -291,8 +291,9 @@ rf_status rf_batch_create(rf_ctx* ctx, const rf_grid* grid, const double* psd, i
     // buckets split at the tertiles of the tile lengths
     for (size_t i = 0; i < b->htiles.size(); ++i)
       if (b->htiles[i].t.ksteps > 0) b->order.push_back(int32_t(i));
-    std::stable_sort(b->order.begin(), b->order.end(),
-                     [&](int a, int c) { return b->htiles[a].t.ksteps > b->htiles[c].t.ksteps; });
+    // longest work first: a paired tile's step costs half a step of the others
+    auto work = [&](int t) { return b->htiles[size_t(t)].t.ksteps * (b->htiles[size_t(t)].t.pair ? 1 : 2); };
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) { return work(a) > work(c); });
     if (!b->order.empty()) {
       std::vector<int64_t> ks;
       for (int32_t t : b->order) ks.push_back(b->htiles[t].t.ksteps);

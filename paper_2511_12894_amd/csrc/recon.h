@@ -6,6 +6,8 @@
 namespace rf {
 
 constexpr int kTileKernels = 32;   // kernels per tile (one 32-wide MFMA block)
+constexpr int kPairKernels = 16;   // kernels of a paired tile (each in two columns)
+constexpr int kPairShift = 32;     // taps (and output times) between a paired tile's two columns
 constexpr int kTimes = 256;        // output times per workgroup (4 waves x 64)
 constexpr int kChunk = 512;        // taps per LDS window chunk / accumulation chunk
 constexpr int kChunkMax = 1024;    // largest chunk a split-FP16 work item may use

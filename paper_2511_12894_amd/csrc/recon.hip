@@ -52,20 +52,24 @@ namespace {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 // Epilogue shared by both forms: scale, store and/or fold into the read-out.
-// tot[tb][ri] holds the wave's two time blocks, real and imaginary part.
-template <bool STORE, bool FUSED>
-__device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t n, int64_t t_base,
+// tot[tb][ri] holds the wave's time blocks (NTB = 2: times t_base + 32 tb of
+// column slot; NTB = 1, a paired tile: times t_base + 32 (column / 16) of slot
+// column % 16), real and imaginary part.
+template <bool STORE, bool FUSED, int NTB>
+__device__ __attribute__((always_inline)) inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t n, int64_t t_base,
                                 int lane, const float* __restrict__ colscale,
                                 const int32_t* __restrict__ slot_kernel, float extra_scale,
                                 float2* __restrict__ zout, const PeakOut& po) {
-  const int slot = lane & 31;
+  const int col = lane & 31;
+  const int slot = NTB == 1 ? (col & (kPairKernels - 1)) : col;
+  const int64_t t_col = t_base + (NTB == 1 ? (col / kPairKernels) * kPairShift : 0);
   const bool live = slot < T.count;
   const int k = live ? slot_kernel[T.first + slot] : 0;
   const float cs = live ? colscale[T.first + slot] * extra_scale : 0.f;
   Best best{-1.f, INT32_MAX};
 #pragma unroll
-  for (int tb = 0; tb < 2; ++tb) {
-    const int64_t base = t_base + 32 * tb;
+  for (int tb = 0; tb < NTB; ++tb) {
+    const int64_t base = t_col + 32 * tb;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int64_t m = base + acc_row(i, lane);
@@ -93,7 +97,11 @@ __device__ inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t
   if (FUSED) {
     Best o{__shfl_xor(best.a2, 32), __shfl_xor(best.idx, 32)};
     best = better(best, o);
-    if (live && lane < 32) {
+    if (NTB == 1) {   // the slot's other column (lane ^ 16) holds its later times
+      Best o2{__shfl_xor(best.a2, kPairKernels), __shfl_xor(best.idx, kPairKernels)};
+      best = better(best, o2);
+    }
+    if (live && lane < (NTB == 1 ? kPairKernels : 32)) {
       const uint64_t key = (uint64_t(__float_as_uint(best.a2)) << 32) |
                            uint64_t(0xFFFFFFFFu - uint32_t(best.idx));
       atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k),
@@ -141,9 +149,10 @@ __device__ inline void zero64(Tot64& t) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) t.v[x][y][i] = 0.0;
 }
+template <int NTB>
 __device__ inline void fold64(Tot64& t, floatx16 (&a)[2][2]) {
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < NTB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
 #pragma unroll
@@ -151,25 +160,24 @@ __device__ inline void fold64(Tot64& t, floatx16 (&a)[2][2]) {
       a[x][y] = floatx16{};
     }
 }
+template <int NTB>
 __device__ inline void to_f32(const Tot64& t, floatx16 (&o)[2][2]) {
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < NTB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 16; ++i) o[x][y][i] = float(t.v[x][y][i]);
 }
 
-template <bool STORE, bool FUSED>
-__global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__ z, int64_t n,
-                                                      const TileDev* __restrict__ tiles,
-                                                      const float* b32,
-                                                      const float* __restrict__ colscale,
-                                                      const int32_t* __restrict__ slot_kernel,
-                                                      float2* __restrict__ zout, PeakOut po) {
-  __shared__ float zr[2][kWin];
-  __shared__ float zi[2][kWin];
-  const TileDev T = tiles[blockIdx.y];
+// FP32 form, one workgroup: output times [n0, n0 + kTimes) of tile T; NTB time
+// blocks a wave (1 for a paired tile).
+template <bool STORE, bool FUSED, int NTB>
+__device__ __attribute__((always_inline)) inline void recon_f32_block(float (*zr)[kWin], float (*zi)[kWin], const float2* __restrict__ z,
+                                       int64_t n, const TileDev& T, const float* b32,
+                                       const float* __restrict__ colscale,
+                                       const int32_t* __restrict__ slot_kernel, float2* __restrict__ zout,
+                                       const PeakOut& po) {
   const int64_t n0 = int64_t(blockIdx.x) * kTimes;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
@@ -221,14 +229,14 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
       const int64_t g = s0 + st < last2 ? s0 + st : last2;
       bb = B[g * 64];
 #pragma unroll
-      for (int tb = 0; tb < 2; ++tb) {
+      for (int tb = 0; tb < NTB; ++tb) {
         aa[tb][0] = wr[32 * tb + 2 * st];
         aa[tb][1] = wi[32 * tb + 2 * st];
       }
     };
     auto mma = [&](float bb, const float (&aa)[2][2]) {
 #pragma unroll
-      for (int tb = 0; tb < 2; ++tb)
+      for (int tb = 0; tb < NTB; ++tb)
 #pragma unroll
         for (int ri = 0; ri < 2; ++ri)
           acc[tb][ri] = __builtin_amdgcn_mfma_f32_32x32x2f32(aa[tb][ri], bb, acc[tb][ri], 0, 0, 0);
@@ -237,7 +245,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
     auto interleave = [] {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
       __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < 2 * NTB - 1; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
       }
@@ -265,14 +273,30 @@ __global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__
         mma(bq[3], aq[3]);
         interleave();
       }
-      fold64(tot, acc);
+      fold64<NTB>(tot, acc);
     }
     if (more) put(buf ^ 1);
     __syncthreads();
   }
   floatx16 totf[2][2];
-  to_f32(tot, totf);
-  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, 1.f, zout, po);
+  to_f32<NTB>(tot, totf);
+  epilogue<STORE, FUSED, NTB>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, 1.f, zout, po);
+}
+
+template <bool STORE, bool FUSED>
+__global__ __launch_bounds__(256, 2) void k_recon_f32(const float2* __restrict__ z, int64_t n,
+                                                      const TileDev* __restrict__ tiles,
+                                                      const float* b32,
+                                                      const float* __restrict__ colscale,
+                                                      const int32_t* __restrict__ slot_kernel,
+                                                      float2* __restrict__ zout, PeakOut po) {
+  __shared__ float zr[2][kWin];
+  __shared__ float zi[2][kWin];
+  const TileDev T = tiles[blockIdx.y];
+  if (T.pair)
+    recon_f32_block<STORE, FUSED, 1>(zr, zi, z, n, T, b32, colscale, slot_kernel, zout, po);
+  else
+    recon_f32_block<STORE, FUSED, 2>(zr, zi, z, n, T, b32, colscale, slot_kernel, zout, po);
 }
 
 // LDS window of the split reference series: 4 planes (re_hi, re_lo, im_hi,
@@ -296,8 +320,8 @@ __device__ inline half8 lds_frag(const _Float16* p) {
 
 // One work item of the split form: output times [n0, n0 + kTimes) of tile T,
 // window chunks of `chunk` taps (256, 512 or 1024; a multiple of 64).
-template <bool STORE, bool FUSED>
-__device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
+template <bool STORE, bool FUSED, int NTB>
+__device__ __attribute__((always_inline)) inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
                                       int64_t n, const TileDev& T, int64_t n0, int chunk,
                                       const __half* b16, const uint32_t* __restrict__ gflag,
                                       const float* __restrict__ colscale,
@@ -313,7 +337,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   floatx16 acc[2][2], cor[2][2];
   Tot64 tot;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < NTB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -322,7 +346,7 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   zero(cor);
   auto fold64 = [&](floatx16 (&a)[2][2]) {
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < NTB; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
 #pragma unroll
@@ -449,14 +473,15 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
         for (int pl = 0; pl < 4; ++pl)
           if (CORR || pl % 2 == 0) ff[pl] = lds_frag(wb[pl] + 64 * j);
       };
-      // step s: time block 0 uses F(s), time block 1 uses F(s + 2); pass 1 the
-      // hi*hi product, pass 2 the hi*lo and lo*hi products, consecutive MFMAs
-      // feeding independent accumulators
+      // step s: time block 0 uses F(s), time block 1 uses F(s + 2) (a paired
+      // tile has one block: its later times come from its shifted columns);
+      // pass 1 the hi*hi product, pass 2 the hi*lo and lo*hi products,
+      // consecutive MFMAs feeding independent accumulators
       auto mma = [&](const half8 (&f0)[4], const half8 (&f1)[4], const half8& h, const half8& l) {
 #pragma unroll
         for (int part = CORR ? 1 : 0; part < (CORR ? 3 : 1); ++part)
 #pragma unroll
-          for (int tb = 0; tb < 2; ++tb)
+          for (int tb = 0; tb < NTB; ++tb)
 #pragma unroll
             for (int ri = 0; ri < 2; ++ri) {
               const half8 av = (tb == 0 ? f0 : f1)[2 * ri + (part == 2 ? 1 : 0)];
@@ -479,7 +504,13 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
           mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
           // the step's loads issued one behind each of its first MFMAs, so that
           // every load issues while a matrix instruction runs
-          if constexpr (CORR) {
+          if constexpr (NTB == 1) {
+            for (int i = 0; i < (CORR ? 4 : 2); ++i) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            }
+            __builtin_amdgcn_sched_group_barrier(0x020, CORR ? 2 : 1, 0);   // global read
+          } else if constexpr (CORR) {
             for (int i = 0; i < 4; ++i) {
               __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
               __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
@@ -540,12 +571,26 @@ __device__ inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __h
   fold64(cor);
   floatx16 totf[2][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < NTB; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int i = 0; i < 16; ++i) totf[x][y][i] = float(tot.v[x][y][i]);
-  epilogue<STORE, FUSED>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, zinv, zout, po);
+  epilogue<STORE, FUSED, NTB>(totf, T, n, n0 + 64 * wave, lane, colscale, slot_kernel, zinv, zout, po);
+}
+
+// A work item on either tile kind (the branch is uniform over the workgroup).
+template <bool STORE, bool FUSED>
+__device__ __attribute__((always_inline)) inline void recon_f16_any(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
+                                     int64_t n, const TileDev& T, int64_t n0, int chunk,
+                                     const __half* b16, const uint32_t* __restrict__ gflag,
+                                     const float* __restrict__ colscale,
+                                     const int32_t* __restrict__ slot_kernel, float zinv,
+                                     float2* __restrict__ zout, const PeakOut& po) {
+  if (T.pair)
+    recon_f16_item<STORE, FUSED, 1>(win, zs, n, T, n0, chunk, b16, gflag, colscale, slot_kernel, zinv, zout, po);
+  else
+    recon_f16_item<STORE, FUSED, 2>(win, zs, n, T, n0, chunk, b16, gflag, colscale, slot_kernel, zinv, zout, po);
 }
 
 template <bool STORE, bool FUSED>
@@ -558,8 +603,8 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16(const __half* __restrict__
                                                       const float* __restrict__ zinv,
                                                       float2* __restrict__ zout, PeakOut po, int chunk) {
   __shared__ __attribute__((aligned(16))) _Float16 win[2][4][4 * kWinMax];
-  recon_f16_item<STORE, FUSED>(win, zs, n, tiles[blockIdx.y], int64_t(blockIdx.x) * kTimes, chunk, b16,
-                               gflag, colscale, slot_kernel, *zinv, zout, po);
+  recon_f16_any<STORE, FUSED>(win, zs, n, tiles[blockIdx.y], int64_t(blockIdx.x) * kTimes, chunk, b16,
+                              gflag, colscale, slot_kernel, *zinv, zout, po);
 }
 
 // Persistent form over a work list: every workgroup takes items
@@ -597,8 +642,8 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
       PeakOut p = po;
       p.seg = w.seg;
       for (int b = 0; b < w.nblk; ++b)
-        recon_f16_item<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock + b) * kTimes, w.chunk,
-                                    b16, gflag, colscale, slot_kernel, zinv_all[sr], nullptr, p);
+        recon_f16_any<false, true>(win, zs_all + sr * 4 * n, n, bt.t, int64_t(w.tblock + b) * kTimes, w.chunk,
+                                   b16, gflag, colscale, slot_kernel, zinv_all[sr], nullptr, p);
     }
   }
 }
@@ -648,7 +693,13 @@ __device__ inline double tap_of(const double* __restrict__ taps64, const int64_t
   return (l >= 0 && l < len[k]) ? taps64[off[k] + l] : 0.0;
 }
 
-// FP32 operand of a tile: per 2-tap step g, lane l holds w_{slot l%32}[m0 + 2 g + l/32].
+// Kernel slot and tap shift of operand column c of tile T: column c holds slot c,
+// or in a paired tile slot c mod 16, its taps kPairShift later in columns 16..31.
+__device__ inline int col_slot(const TileDev& T, int c) { return T.pair ? (c & (kPairKernels - 1)) : c; }
+__device__ inline int col_shift(const TileDev& T, int c) { return T.pair && c >= kPairKernels ? kPairShift : 0; }
+
+// FP32 operand of a tile: per 2-tap step g, lane l holds column l%32 at tap
+// m0 + 2 g + l/32 (w_{slot}[tap - shift]).
 __global__ void k_pack_b32(const double* __restrict__ taps64, const int64_t* __restrict__ off,
                            const int64_t* __restrict__ mlo, const int32_t* __restrict__ len,
                            const TileDev* __restrict__ tiles, const int32_t* __restrict__ slot_kernel,
@@ -659,16 +710,18 @@ __global__ void k_pack_b32(const double* __restrict__ taps64, const int64_t* __r
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t g = e / 64;
     const int lane = int(e & 63);
-    const int slot = lane & 31;
+    const int slot = col_slot(T, lane & 31);
     double v = 0.0;
-    if (slot < T.count) v = tap_of(taps64, off, mlo, len, slot_kernel[T.first + slot], T.m0 + 2 * g + (lane >> 5));
+    if (slot < T.count)
+      v = tap_of(taps64, off, mlo, len, slot_kernel[T.first + slot],
+                 T.m0 + 2 * g + (lane >> 5) - col_shift(T, lane & 31));
     b32[T.b32_off + e] = float(v);
   }
 }
 
 // FP16 operand of a tile: per 16-tap step s, the hi fragment then the lo
-// fragment; lane l holds 8 halves w_{slot l%32}[m0 + 16 s + 8 (l/32) + 0..7]
-// (scaled by the kernel's power-of-two s_k).  Also marks the tile's 256-tap
+// fragment; lane l holds 8 halves of column l%32 at taps m0 + 16 s + 8 (l/32) +
+// 0..7 (w_{slot}[tap - shift], scaled by the kernel's power-of-two s_k).  Also marks the tile's 256-tap
 // granules (gflag, zeroed before): bit 1 where a scaled tap reaches 1/2 (the
 // correction products), bit 2 where one reaches kFoldTap (the short folds).
 __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __restrict__ off,
@@ -681,11 +734,12 @@ __global__ void k_pack_b16(const double* __restrict__ taps64, const int64_t* __r
        e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t s = e / 1024;
     const int part = int((e / 512) & 1), lane = int((e / 8) & 63), ee = int(e & 7);
-    const int slot = lane & 31;
+    const int slot = col_slot(T, lane & 31);
     float out = 0.f;
     if (slot < T.count) {
       const int k = slot_kernel[T.first + slot];
-      const double v = tap_of(taps64, off, mlo, len, k, T.m0 + 16 * s + 8 * (lane >> 5) + ee) * kscale[k];
+      const double v =
+          tap_of(taps64, off, mlo, len, k, T.m0 + 16 * s + 8 * (lane >> 5) + ee - col_shift(T, lane & 31)) * kscale[k];
       // a tap of at least half an FP16 unit (scaled) needs the correction products
       if (part == 0 && fabs(v) >= 0.5) atomicOr(&gflag[T.gflag_off + s / 16], fabs(v) >= kFoldTap ? 3u : 1u);
       const __half hi = __float2half_rn(float(v));

@@ -207,6 +207,10 @@ struct TileDev {
   int64_t gflag_off; // offset of the tile's granule flags (one per 256 taps; bit 1 corrections, bit 2 folds)
   int32_t first;    // first slot of the tile in the slot arrays
   int32_t count;    // live kernels in the tile
+  int32_t pair;     // 1: at most 16 kernels, operand columns 16..31 repeating columns 0..15
+                    // 32 taps later (their outputs are 32 times later), so one 32 x 32
+                    // product per plane covers a wave's 64 output times
+  int32_t pad;
 };
 }  // namespace rf
 

@@ -31,12 +31,16 @@ def rf():
     return rfmod
 
 
-def _expected_steps(info, taps, chunk):
+def _expected_steps(info, taps, chunk, n):
     """Tiles: kernels sorted by first tap (stable), 32 per tile, union support
-    from a multiple of 4, rounded up to 128 taps; a 256-tap granule is marked
-    where a kernel has |w| s_k >= 1/2 (s_k = 2^(14 - e), e the binary exponent
-    of the largest |w| as an FP32 value); a step takes the corrections when
-    its 512-tap block holds a marked granule, whatever the window chunk."""
+    from a multiple of 4, rounded up to 128 taps; a tile of at most 16 kernels
+    is paired: each kernel also sits in a second column 32 taps later, so its
+    support reaches 32 taps further (if it then still fits the n-sample
+    segment); a 256-tap granule is marked where a column has |w| s_k >= 1/2
+    (s_k = 2^(14 - e), e the binary exponent of the largest |w| as an FP32
+    value); a step takes the corrections when its 512-tap block holds a marked
+    granule, whatever the window chunk.  Counts are in steps of a 32-kernel
+    tile: a paired tile's step counts one half."""
     nk = len(info["len"])
     order = sorted(range(nk), key=lambda k: info["m_lo"][k])
     corr = total = 0
@@ -46,24 +50,28 @@ def _expected_steps(info, taps, chunk):
             continue
         m0 = (min(info["m_lo"][k] for k in ks) // 4) * 4
         hi = max(info["m_lo"][k] + info["len"][k] for k in ks)
+        shifts, per = [0], 1
+        if len(order[t:t + 32]) <= 16 and -(-(hi + 32 - m0) // 128) * 128 <= n:
+            shifts, hi, per = [0, 32], hi + 32, 2
         ntaps = -(-(hi - m0) // 128) * 128
         marked = np.zeros(ntaps // 256 + 1, bool)
         for k in ks:
             w = taps[k]
             e = np.frexp(np.float32(np.abs(w).max()))[1]
             s = 2.0 ** (14 - int(e))
-            pos = np.nonzero(np.abs(w * s) >= 0.5)[0] + (info["m_lo"][k] - m0)
-            marked[np.unique(pos // 256)] = True
-        total += ntaps // 16
+            for sh in shifts:
+                pos = np.nonzero(np.abs(w * s) >= 0.5)[0] + (info["m_lo"][k] - m0) + sh
+                marked[np.unique(pos // 256)] = True
+        total += ntaps // 16 // per
         for t0 in range(0, ntaps, 512):
             b = min(t0 + 512, ntaps)
             if marked[t0 // 256: -(-b // 256)].any():
-                corr += (b - t0) // 16
+                corr += (b - t0) // 16 // per
     return corr, total
 
 
 def test_flags_and_step_counts_match_the_rule(rf):
-    w = synth.workload_realistic(n_nbr=40, duration=64.0)        # a full and a ragged tile
+    w = synth.workload_realistic(n_nbr=40, duration=64.0)        # a full and a paired tile
     g = w["grid"]
     ctx = rf.Context(0)
     psd = torch.from_numpy(w["psd"]).cuda()
@@ -72,7 +80,7 @@ def test_flags_and_step_counts_match_the_rule(rf):
     taps = [K.taps(k) for k in range(K.nk)]
     for chunk in (256, 512, 1024):
         got = K.split_steps(chunk)
-        exp = _expected_steps(info, taps, chunk)
+        exp = _expected_steps(info, taps, chunk, g.n)
         _say(f"chunk {chunk}: correction steps {got[0]} of {got[1]} (expected {exp[0]} of {exp[1]})")
         assert got == exp
         assert got[0] < 0.6 * got[1]
