@@ -160,6 +160,24 @@ rf_status rf_kernels_taps_fp64(const rf_kernels* k, int32_t idx, double* host_ou
  * flags). */
 rf_status rf_kernels_split_steps(const rf_kernels* k, int32_t chunk, int64_t* corr_steps, int64_t* all_steps);
 rf_status rf_kernels_free(rf_kernels* k);
+/* Kernel sets stored and reused (section II.B: the ratio kernels are computed
+ * once and kept; the storage figure of section IV is what such a file holds).
+ * rf_kernels_save writes k to the file at `path` (created or replaced): an
+ * 8-byte tag "RFKSET01", then in the host's byte order (little-endian) int32
+ * version 1, int32 nk, int64 n_build, double fs, int64 total_taps, the per-kernel
+ * arrays m_lo (int64), len (int32), off (int64, first tap in the concatenated
+ * taps), norm_ratio, df_low and kscale (double, the FP16 scale s_k), the FP64
+ * taps (total_taps doubles), and a 64-bit FNV-1a hash of every byte after the
+ * tag.  rf_kernels_load reads such a file into a new set on ctx's device (tiles
+ * and packed operands rebuilt as ratio_kernel_build makes them) and stores its
+ * handle in *out; the caller frees it with rf_kernels_free.  Errors:
+ * RF_E_INVAL for null pointers, a file that cannot be opened, read or written,
+ * and a file that is not a kernel set (tag, version, sizes, hash, or field
+ * ranges: lengths within n_build, taps inside the file, finite positive norm
+ * ratios and scales); RF_E_NOMEM / RF_E_HIP as elsewhere; *out is NULL after a
+ * failed load.  Both synchronise ctx's stream. */
+rf_status rf_kernels_save(rf_ctx* ctx, const rf_kernels* k, const char* path);
+rf_status rf_kernels_load(rf_ctx* ctx, const char* path, rf_kernels** out);
 
 /* Reconstructed SNR series of every kernel's target (section II.B, equation
  * convolution, on the circular segment):

@@ -2,6 +2,7 @@
 // kernels in fft.hip, spectra.hip and recon.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -213,6 +214,46 @@ void finalize_kernel_set(rf_ctx* ctx, rf_kernels* K, const std::vector<double>& 
     (void)hipFree(ks_d);
   }
 }
+
+namespace {
+
+// FNV-1a, 64 bit, over a byte range, continued from h
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+constexpr uint64_t kFnvBasis = 14695981039346656037ull;
+constexpr char kSetTag[8] = {'R', 'F', 'K', 'S', 'E', 'T', '0', '1'};
+
+// Sequential writer / reader of the kernel-set file, hashing the bytes after the tag.
+struct SetWriter {
+  std::FILE* f;
+  uint64_t h = kFnvBasis;
+  void put(const void* p, size_t n) {
+    RF_CHECK(n == 0 || std::fwrite(p, 1, n, f) == n, "rf_kernels_save: write failed");
+    h = fnv1a(h, p, n);
+  }
+};
+struct SetReader {
+  std::FILE* f;
+  uint64_t h = kFnvBasis;
+  void get(void* p, size_t n) {
+    RF_CHECK(n == 0 || std::fread(p, 1, n, f) == n, "rf_kernels_load: file shorter than its header states");
+    h = fnv1a(h, p, n);
+  }
+};
+struct FileCloser {
+  std::FILE* f;
+  ~FileCloser() {
+    if (f) std::fclose(f);
+  }
+};
+
+}  // namespace
 
 }  // namespace rf
 
@@ -466,6 +507,109 @@ rf_status ratio_kernel_build(rf_ctx* ctx, const rf_grid* grid, const double* psd
       taps_host.insert(taps_host.end(), chunk_taps.begin(), chunk_taps.begin() + tot);
     }
     finalize_kernel_set(ctx, K, taps_host);
+    *out = K;
+  });
+  if (st != RF_OK && K) {
+    free_kernels(K);
+    if (out) *out = nullptr;
+  }
+  return st;
+}
+
+rf_status rf_kernels_save(rf_ctx* ctx, const rf_kernels* k, const char* path) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    RF_CHECK(k && path, "rf_kernels_save: null pointer");
+    RF_CHECK(k->device == ctx->device, "rf_kernels_save: kernel set on another device");
+    std::vector<double> taps(static_cast<size_t>(k->total_taps));
+    if (k->total_taps > 0)
+      copy_sync(ctx, taps.data(), k->taps64, sizeof(double) * taps.size(), hipMemcpyDeviceToHost);
+    std::FILE* f = std::fopen(path, "wb");
+    RF_CHECK(f != nullptr, std::string("rf_kernels_save: cannot open ") + path);
+    FileCloser fc{f};
+    RF_CHECK(std::fwrite(kSetTag, 1, 8, f) == 8, "rf_kernels_save: write failed");
+    SetWriter w{f};
+    const int32_t version = 1, nk = k->nk;
+    const size_t n = size_t(nk);
+    w.put(&version, 4);
+    w.put(&nk, 4);
+    w.put(&k->n_build, 8);
+    w.put(&k->fs, 8);
+    w.put(&k->total_taps, 8);
+    w.put(k->m_lo.data(), 8 * n);
+    w.put(k->len.data(), 4 * n);
+    w.put(k->off.data(), 8 * n);
+    w.put(k->norm_ratio.data(), 8 * n);
+    w.put(k->df_low.data(), 8 * n);
+    w.put(k->kscale.data(), 8 * n);
+    w.put(taps.data(), 8 * taps.size());
+    const uint64_t h = w.h;
+    RF_CHECK(std::fwrite(&h, 1, 8, f) == 8, "rf_kernels_save: write failed");
+    fc.f = nullptr;
+    RF_CHECK(std::fclose(f) == 0, "rf_kernels_save: write failed");
+  });
+}
+
+rf_status rf_kernels_load(rf_ctx* ctx, const char* path, rf_kernels** out) {
+  if (out) *out = nullptr;
+  if (!ctx) return RF_E_INVAL;
+  rf_kernels* K = nullptr;
+  rf_status st = guarded(ctx, [&] {
+    RF_CHECK(path && out, "rf_kernels_load: null pointer");
+    std::FILE* f = std::fopen(path, "rb");
+    RF_CHECK(f != nullptr, std::string("rf_kernels_load: cannot open ") + path);
+    FileCloser fc{f};
+    char tag[8];
+    RF_CHECK(std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kSetTag, 8) == 0,
+             "rf_kernels_load: not a kernel-set file");
+    SetReader r{f};
+    int32_t version = 0, nk = 0;
+    int64_t n_build = 0, total = 0;
+    double fs = 0;
+    r.get(&version, 4);
+    r.get(&nk, 4);
+    r.get(&n_build, 8);
+    r.get(&fs, 8);
+    r.get(&total, 8);
+    RF_CHECK(version == 1, "rf_kernels_load: unknown version");
+    RF_CHECK(nk >= 1 && nk <= (1 << 24), "rf_kernels_load: bad kernel count");
+    RF_CHECK(is_pow2(n_build) && n_build >= 256 && n_build <= (int64_t(1) << 24), "rf_kernels_load: bad n_build");
+    RF_CHECK(std::isfinite(fs) && fs > 0, "rf_kernels_load: bad sampling rate");
+    RF_CHECK(total >= 0 && total <= int64_t(nk) * n_build, "rf_kernels_load: bad tap count");
+    K = new rf_kernels();
+    K->device = ctx->device;
+    K->nk = nk;
+    K->n_build = n_build;
+    K->fs = fs;
+    const size_t n = size_t(nk);
+    K->m_lo.resize(n);
+    K->len.resize(n);
+    K->off.resize(n);
+    K->norm_ratio.resize(n);
+    K->df_low.resize(n);
+    K->kscale.resize(n);
+    r.get(K->m_lo.data(), 8 * n);
+    r.get(K->len.data(), 4 * n);
+    r.get(K->off.data(), 8 * n);
+    r.get(K->norm_ratio.data(), 8 * n);
+    r.get(K->df_low.data(), 8 * n);
+    r.get(K->kscale.data(), 8 * n);
+    for (size_t i = 0; i < n; ++i) {
+      RF_CHECK(K->len[i] >= 0 && K->len[i] <= n_build, "rf_kernels_load: bad kernel length");
+      RF_CHECK(K->off[i] >= 0 && K->off[i] + K->len[i] <= total, "rf_kernels_load: taps outside the file");
+      RF_CHECK(K->m_lo[i] > -n_build && K->m_lo[i] < n_build, "rf_kernels_load: bad first tap");
+      RF_CHECK(std::isfinite(K->norm_ratio[i]) && K->norm_ratio[i] > 0, "rf_kernels_load: bad norm ratio");
+      RF_CHECK(std::isfinite(K->df_low[i]) && K->df_low[i] >= 0, "rf_kernels_load: bad taper width");
+      int ex = 0;
+      RF_CHECK(std::isfinite(K->kscale[i]) && K->kscale[i] > 0 && std::frexp(K->kscale[i], &ex) == 0.5,
+               "rf_kernels_load: bad FP16 scale");
+    }
+    std::vector<double> taps(static_cast<size_t>(total));
+    r.get(taps.data(), 8 * taps.size());
+    uint64_t h = 0;
+    RF_CHECK(std::fread(&h, 1, 8, f) == 8 && h == r.h, "rf_kernels_load: hash mismatch (file damaged)");
+    RF_CHECK(std::fgetc(f) == EOF, "rf_kernels_load: bytes after the hash");
+    finalize_kernel_set(ctx, K, taps);
     *out = K;
   });
   if (st != RF_OK && K) {

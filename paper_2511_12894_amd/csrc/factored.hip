@@ -1031,8 +1031,9 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
       po.nk = F->nk;
     }
     fill_u32(ctx, F->zmax, 0u, 1);
-    hipLaunchKernelGGL(k_conj_max, dim3(nblocks(n)), dim3(256), 0, ctx->stream, static_cast<const float2*>(z_ref),
-                       n, F->Qin, F->zmax);
+    // 512 workgroups at most: one atomic each on the one maximum (4096 took 50 us at 2^20)
+    hipLaunchKernelGGL(k_conj_max, dim3(nblocks(n, 512)), dim3(256), 0, ctx->stream,
+                       static_cast<const float2*>(z_ref), n, F->Qin, F->zmax);
     RF_HIP(hipGetLastError());
     fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
     // basis correlations: the band products formed inside the first transform pass, in

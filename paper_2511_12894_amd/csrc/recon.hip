@@ -648,9 +648,11 @@ __global__ __launch_bounds__(256, 1) void k_recon_f16_queue(const __half* __rest
   }
 }
 
-// max(|re|, |im|) over the series, as float bits (non-negative floats order as integers)
+// max(|re|, |im|) over the series, as float bits (non-negative floats order as
+// integers); one atomic per workgroup
 __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ z, int64_t n,
                                                 uint32_t* out) {
+  __shared__ float wmax[4];
   z += int64_t(blockIdx.y) * n;
   out += blockIdx.y;
   float m = 0.f;
@@ -659,7 +661,10 @@ __global__ __launch_bounds__(256) void k_absmax(const float2* __restrict__ z, in
     m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(out, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // Split into 4 FP16 planes after scaling by s = 2^e, max * s in [2^13, 2^14).
@@ -829,7 +834,8 @@ void split_launch(rf_ctx* ctx, const float2* z, int64_t n, uint32_t* maxbits, __
                   float* inv_scale, int nseries) {
   fill_u32(ctx, maxbits, 0u, nseries);
   const unsigned per = nblk(n, unsigned(std::max(64, 2048 / nseries)));
-  hipLaunchKernelGGL(k_absmax, dim3(per, unsigned(nseries)), dim3(256), 0, ctx->stream, z, n, maxbits);
+  hipLaunchKernelGGL(k_absmax, dim3(std::min(per, 512u), unsigned(nseries)), dim3(256), 0, ctx->stream, z, n,
+                     maxbits);
   RF_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_split, dim3(per, unsigned(nseries)), dim3(256), 0, ctx->stream, z, n, maxbits,
                      zs, inv_scale);

@@ -22,7 +22,8 @@ RF_PREC_FP32, RF_PREC_SPLIT_FP16 = 0, 1
 PREC = {"fp32": RF_PREC_FP32, "split16": RF_PREC_SPLIT_FP16}
 
 EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "mf_snr_peaks", "ratio_kernel_build",
-            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free", "snr_reconstruct", "snr_reconstruct_noalloc",
+            "rf_kernels_info", "rf_kernels_taps_fp64", "rf_kernels_split_steps", "rf_kernels_free",
+            "rf_kernels_save", "rf_kernels_load", "snr_reconstruct", "snr_reconstruct_noalloc",
             "snr_peaks", "rf_batch_create", "rf_batch_info", "rf_batch_set_chunks",
             "rf_batch_get_tuning", "rf_batch_set_tuning", "rf_batch_autotune", "rf_batch_run", "rf_batch_graph_stats", "rf_batch_free", "rf_surrogate_create",
             "rf_surrogate_info", "rf_surrogate_set_params", "rf_surrogate_get_params",
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.rf_kernels_taps_fp64.argtypes = [vp, i32, ctypes.POINTER(dbl)]
     lib.rf_kernels_split_steps.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rf_kernels_free.argtypes = [vp]
+    lib.rf_kernels_save.argtypes = [vp, vp, ctypes.c_char_p]
+    lib.rf_kernels_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
     lib.snr_reconstruct.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
     lib.snr_reconstruct_noalloc.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(RfPeakArgs)]
     lib.snr_peaks.argtypes = [vp, vp, i32, i64, ctypes.c_float, vp, vp, i64, ctypes.POINTER(i64)]
@@ -286,6 +289,20 @@ def mf_snr_peaks(ctx: Context, grid, xf: torch.Tensor, psd: torch.Tensor, templa
     if st not in (RF_OK, RF_E_OVERFLOW):
         ctx.check(st)
     return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
+
+
+def kernels_save(ctx: Context, kernels: "Kernels", path: str):
+    """Write a kernel set to `path` (rf_kernels_save)."""
+    ctx.check(ctx.lib.rf_kernels_save(ctx.h, kernels.h, os.fsencode(path)))
+
+
+def kernels_load(ctx: Context, path: str) -> "Kernels":
+    """Read a kernel set written by kernels_save onto ctx's device (rf_kernels_load)."""
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.rf_kernels_load(ctx.h, os.fsencode(path), ctypes.byref(h)))
+    nk = ctypes.c_int32()
+    ctx.check(ctx.lib.rf_kernels_info(h, ctypes.byref(nk), None, None, None, None))
+    return Kernels(ctx, h, nk.value)
 
 
 def ratio_kernel_build(ctx: Context, grid, psd: torch.Tensor, ref, nbrs, thr: float = 1e-3,

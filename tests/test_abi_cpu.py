@@ -84,3 +84,10 @@ def test_null_context_is_rejected_without_gpu(lib):
     assert lib.mf_ref_snr(None, None, None, None, None, 0, None, None) == 1   # RF_E_INVAL
     lib.rf_ctx_create.restype = ctypes.c_int
     assert lib.rf_ctx_create(0, None, None) == 1
+    # kernel-set files: a null context is rejected before any file or device access
+    lib.rf_kernels_save.restype = ctypes.c_int
+    lib.rf_kernels_load.restype = ctypes.c_int
+    assert lib.rf_kernels_save(None, None, b"/nonexistent/x") == 1
+    out = ctypes.c_void_p(7)
+    assert lib.rf_kernels_load(None, b"/nonexistent/x", ctypes.byref(out)) == 1
+    assert out.value is None
