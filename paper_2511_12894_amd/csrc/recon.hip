@@ -13,7 +13,11 @@
 // all XCDs -- sweep the time axis of the same tile.
 //
 // A workgroup owns 256 output times x 32 kernels; each of its four wavefronts
-// owns 64 times as two 32 x 32 MFMA tiles (real and imaginary part each).  The
+// owns 64 times as two 32 x 32 MFMA tiles (real and imaginary part each).  A
+// set's last tile of at most 16 kernels is paired: its columns 16..31 hold the
+// same kernels with their taps 32 later, B[s][16 + k] = w_k[s + m0 - 32], which
+// gives the outputs 32 times later from the same rows of A, so one 32 x 32 tile
+// per part covers a wave's 64 times and the tile costs half the products.  The
 // Hankel operand comes from a sliding window of z_ref staged in LDS (double
 // buffered: the next chunk's window is loaded into registers and stored to
 // the idle buffer while the current chunk computes); B is pre-packed in
