@@ -481,9 +481,10 @@ def factored_batched_leg(dev, max_set=256, tol=2e-6):
     of at most 256 consecutive lattice points, each set with its own basis
     (kernel and basis builds timed apart); per segment and reference, the
     reference matched filter and the factored reconstruction of every set with
-    the fused read-out (series not stored).  The peaks of every series are
-    compared with direct matched filtering of the same templates (read-out in
-    the transform), which is timed over the same segments."""
+    the fused read-out (series not stored), timed as per-call loop and as one
+    batched call (whose peaks must equal the loop's).  The peaks of every series
+    are compared with direct matched filtering of the same templates (read-out
+    in the transform), which is timed over the same segments."""
     wb = synth.workload_batched()
     g = wb["grid"]
     nseg = len(wb["segments"])
@@ -492,12 +493,11 @@ def factored_batched_leg(dev, max_set=256, tol=2e-6):
     psd = torch.from_numpy(wb["psd"]).to(dev)
     xf = torch.from_numpy(np.stack(wb["segments"])).to(dev)
     zref = torch.empty((1, g.n), dtype=torch.complex64, device=dev)
-    t_build = t_rec = t_direct = 0.0
-    jvals, resid, err = [], [], 0.0
-    nser = 0
+    jvals, resid = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_ref = []                     # per reference: its sets (kernels, basis)
     for r, (ref, grp) in enumerate(zip(wb["refs"], wb["groups"])):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         sets = []
         for a in range(0, len(grp), max_set):
             K = rf.ratio_kernel_build(ctx, g, psd, ref, list(grp[a:a + max_set]))
@@ -506,26 +506,47 @@ def factored_batched_leg(dev, max_set=256, tol=2e-6):
             jvals.append(inf["J"])
             resid.append(max(inf["resid"]))
             sets.append((K, F))
-        torch.cuda.synchronize()
-        t_build += time.perf_counter() - t0
-        pk = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s_ in range(nseg):
+        per_ref.append(sets)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    # per-(segment, reference) calls: the reference matched filter, then each set
+    pk = [[None] * len(wb["refs"]) for _ in range(nseg)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(nseg):
+        for r, ref in enumerate(wb["refs"]):
             rf.mf_ref_snr(ctx, g, xf[s_], psd, [ref], z=zref, want_sigma=False)
-            for K, F in sets:
-                pk.append(F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)["peaks"])
+            pk[s_][r] = [F.reconstruct(zref[0], store=False, fused_thr=6.0, trig_cap=1 << 18)["peaks"]
+                         for K, F in per_ref[r]]
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    # the same in one call (every segment and set, one synchronisation)
+    all_sets = [F for sets in per_ref for K, F in sets]
+    all_refs = [ref for ref, sets in zip(wb["refs"], per_ref) for _ in sets]
+    rf.factored_batch(ctx, g, xf, psd, all_sets, all_refs, 6.0, trig_cap=1 << 18)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bo = rf.factored_batch(ctx, g, xf, psd, all_sets, all_refs, 6.0, trig_cap=1 << 18)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    bv, bi = rf.decode_peaks(bo["peaks"].view(-1, 2))
+    cv = np.concatenate([np.concatenate([rf.decode_peaks(p)[0] for p in pk[s_][r]])
+                         for s_ in range(nseg) for r in range(len(wb["refs"]))])
+    batch_equal = bool(np.array_equal(bv, cv))
+    # direct matched filtering of the same templates, and the peaks against it
+    t_direct, err, nser = 0.0, 0.0, 0
+    for r, grp in enumerate(wb["groups"]):
         torch.cuda.synchronize()
-        t_rec += time.perf_counter() - t0
         t0 = time.perf_counter()
         dpk = [rf.mf_snr_peaks(ctx, g, xf[s_], psd, list(grp), 6.0, trig_cap=1 << 18)["peaks"] for s_ in range(nseg)]
         torch.cuda.synchronize()
         t_direct += time.perf_counter() - t0
         for s_ in range(nseg):
-            fv = np.concatenate([rf.decode_peaks(p)[0] for p in pk[s_ * len(sets):(s_ + 1) * len(sets)]])
+            fv = np.concatenate([rf.decode_peaks(p)[0] for p in pk[s_][r]])
             dv = rf.decode_peaks(dpk[s_])[0]
             err = max(err, float(np.abs(fv - dv).max()))
             nser += len(grp)
+    for sets in per_ref:
         for K, F in sets:
             F.free()
             K.free()
@@ -535,9 +556,11 @@ def factored_batched_leg(dev, max_set=256, tol=2e-6):
     return dict(workload=f"batched-{nseg}seg-256s-4096Hz-{len(wb['refs'])}ref-{ktot}kernels", sets=len(jvals),
                 J_min=min(jvals), J_max=max(jvals), J_mean=float(np.mean(jvals)), resid_max=float(max(resid)),
                 build_s=t_build, recon_s=t_rec, value=samples / t_rec, unit="template-samples/s",
+                batch_s=t_batch, batch_value=samples / t_batch, batch_peaks_equal_per_call=batch_equal,
                 direct_s=t_direct, direct_value=samples / t_direct, series_checked=nser,
                 peak_err_vs_direct=err, within_2e_4=err <= 2e-4,
-                note="per-(segment, reference) calls: reference MF + factored reconstruction of each set")
+                note="recon_s: per-(segment, reference) calls (reference MF + factored reconstruction of each "
+                     "set); batch_s: every segment and set in one snr_reconstruct_factored_batch call")
 
 
 def stress_leg(dev, ctx):

@@ -416,6 +416,22 @@ rf_status rf_factored_info(const rf_factored* F, int32_t* J, int64_t* m0, int64_
  * Synchronises when fused. */
 rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec,
                                    void* z_out, const rf_peak_args* fused);
+/* Many segments and sets in one call (sec. II.B per reference; the batching is
+ * an implementation form): for every segment s < nseg of xf_segs (device
+ * complex128 [nseg][n/2+1], the whitened data as for mf_ref_snr) and every set
+ * r < nset, the matched-filter series of reference refs[r] (as mf_ref_snr
+ * computes it) and the factored reconstruction of set sets[r] from it (as
+ * snr_reconstruct_factored with the fused read-out), all enqueued on ctx's
+ * stream with one synchronisation at the end.  Every set must be built for
+ * grid->n samples and reside on ctx's device.  out->peaks: device rf_peak
+ * [nseg][ktot], ktot = the sets' kernel counts summed, kernel k of set r at
+ * index kbase_r + k (kbase_r = the counts of sets 0..r-1); trigger records
+ * carry (kbase_r + k, s, sample, |z|, arg z); overflow as in snr_peaks.  The
+ * peaks and triggers equal those of the per-(segment, set) calls bit for bit.
+ * The conditioned data are formed once per segment. */
+rf_status snr_reconstruct_factored_batch(rf_ctx* ctx, const rf_grid* grid, const void* xf_segs, int32_t nseg,
+                                         const double* psd, int32_t nset, const rf_factored* const* sets,
+                                         const rf_tmpl* refs, rf_prec prec, const rf_peak_args* out);
 rf_status rf_factored_free(rf_factored* F);
 
 /* ---- blocked frequency-domain reconstruction (overlap-save) ----

@@ -330,6 +330,72 @@ rf_status mf_ref_snr(rf_ctx* ctx, const rf_grid* grid, const void* xf, const dou
   });
 }
 
+rf_status snr_reconstruct_factored_batch(rf_ctx* ctx, const rf_grid* grid, const void* xf_segs, int32_t nseg,
+                                         const double* psd, int32_t nset, const rf_factored* const* sets,
+                                         const rf_tmpl* refs, rf_prec prec, const rf_peak_args* out) {
+  if (!ctx) return RF_E_INVAL;
+  return guarded(ctx, [&] {
+    validate_grid(grid);
+    RF_CHECK(xf_segs && psd && sets && refs && out, "snr_reconstruct_factored_batch: null pointer");
+    RF_CHECK(nseg >= 1 && nset >= 1, "snr_reconstruct_factored_batch: need nseg >= 1 and nset >= 1");
+    RF_CHECK(prec == RF_PREC_FP32 || prec == RF_PREC_SPLIT_FP16, "snr_reconstruct_factored_batch: bad precision");
+    RF_CHECK(out->peaks && out->ntrig && out->cap >= 0 && (out->cap == 0 || out->trig),
+             "snr_reconstruct_factored_batch: bad read-out arguments");
+    RF_CHECK(std::isfinite(out->thr) && out->thr >= 0, "snr_reconstruct_factored_batch: bad threshold");
+    const int64_t n = grid->n;
+    std::vector<int32_t> kbase(static_cast<size_t>(nset) + 1, 0);
+    std::vector<Tf2Coef> coef(static_cast<size_t>(nset));
+    for (int r = 0; r < nset; ++r) {
+      RF_CHECK(sets[r] != nullptr, "snr_reconstruct_factored_batch: null set");
+      const FactoredView v = factored_view(sets[r]);
+      RF_CHECK(v.device == ctx->device, "snr_reconstruct_factored_batch: set on another device");
+      RF_CHECK(v.n == n, "snr_reconstruct_factored_batch: set built for another series length");
+      RF_CHECK(!(v.large && prec != RF_PREC_SPLIT_FP16),
+               "snr_reconstruct_factored_batch: large sets mix in split FP16 only");
+      RF_CHECK(int64_t(kbase[r]) + v.nk <= INT32_MAX, "snr_reconstruct_factored_batch: too many kernels");
+      kbase[r + 1] = kbase[r] + v.nk;
+      validate_tmpl(refs[r]);
+      coef[r] = tf2_coef(refs[r]);
+    }
+    const int64_t ktot = kbase[nset];
+    RF_CHECK(int64_t(nseg) * ktot < (int64_t(1) << 40), "snr_reconstruct_factored_batch: too many series");
+    Tf2Coef* coef_dev = upload(ctx, WS_COEF, coef.data(), coef.size());
+    double* moment = static_cast<double*>(ctx->ws[WS_SCALAR].ensure(64));
+    band_moment(ctx, grid, psd, moment);
+    int64_t jlo, jhi;
+    band_limits(grid, &jlo, &jhi);
+    float2* q = static_cast<float2*>(ctx->ws[WS_Y].ensure(sizeof(float2) * size_t(jhi - jlo + 1)));
+    float2* zref = static_cast<float2*>(ctx->ws[WS_ZREF].ensure(sizeof(float2) * size_t(n)));
+    const int64_t np = int64_t(nseg) * ktot;
+    uint64_t* packed = static_cast<uint64_t*>(ctx->ws[WS_PEAK].ensure(sizeof(uint64_t) * size_t(np + 1)));
+    fill_u64(ctx, packed, 0ull, np + 1);
+    PeakOut po{};
+    po.packed = packed;
+    po.count = reinterpret_cast<unsigned long long*>(packed + np);
+    po.trig = out->trig;
+    po.cap = out->cap;
+    po.thr2 = out->thr * out->thr;
+    po.nk = int32_t(ktot);
+    const double2* xs = static_cast<const double2*>(xf_segs);
+    for (int32_t sg = 0; sg < nseg; ++sg) {
+      condition_data(ctx, grid, xs + int64_t(sg) * (n / 2 + 1), psd, q);
+      for (int r = 0; r < nset; ++r) {
+        fft_inverse_tmpl_f32(ctx, grid, q, coef_dev + r, 1, moment, zref, 1);
+        po.seg = sg;
+        po.tmpl0 = kbase[r];
+        factored_enqueue(ctx, sets[r], zref, n, prec, nullptr, &po);
+      }
+    }
+    trig_finish(ctx, out->trig, po.count, out->cap);
+    peaks_finalize(ctx, packed, np, out->peaks);
+    unsigned long long c = 0;
+    RF_HIP(hipMemcpyAsync(&c, po.count, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    *out->ntrig = int64_t(c);
+    if (int64_t(c) > out->cap) throw Error{RF_E_OVERFLOW, "snr_reconstruct_factored_batch: trigger buffer overflow"};
+  });
+}
+
 rf_status mf_snr_peaks(rf_ctx* ctx, const rf_grid* grid, const void* xf, const double* psd,
                        const rf_tmpl* tmpl, int32_t nt, const rf_peak_args* out) {
   if (!ctx) return RF_E_INVAL;

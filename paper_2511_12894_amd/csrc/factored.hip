@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
                 const unsigned long long sl = atomicAdd(po.count, 1ull);
                 if (int64_t(sl) < po.cap) {
                   rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
-                  tr.tmpl = kb + acc_row(i, 0);
+                  tr.tmpl = po.tmpl0 + kb + acc_row(i, 0);
                   tr.seg = po.seg;
                   tr.idx = int32_t(m);
                   tr.absz = cre[t][i];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64 * mix_waves<JP>(), 1) void k_mix(const float2* _
     for (int k = threadIdx.x; k < nk; k += 64 * kMixWaves) {
       unsigned long long b = 0ull;
       for (int s2 = 0; s2 < S; ++s2) b = max(b, keys[k * S + s2]);
-      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 + k), b);
     }
   }
 }
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(64 * mix16_waves<JP>(), 1) void k_mix16(const float
                 const unsigned long long sl = atomicAdd(po.count, 1ull);
                 if (int64_t(sl) < po.cap) {
                   rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
-                  tr.tmpl = kb + acc_row(i, 0);
+                  tr.tmpl = po.tmpl0 + kb + acc_row(i, 0);
                   tr.seg = po.seg;
                   tr.idx = int32_t(m);
                   tr.absz = cre[t][i];
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(64 * mix16_waves<JP>(), 1) void k_mix16(const float
     for (int k = threadIdx.x; k < nk; k += 64 * W) {
       unsigned long long b = 0ull;
       for (int s2 = 0; s2 < S; ++s2) b = max(b, keys[k * S + s2]);
-      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 + k), b);
     }
   }
 }
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256, 1) void k_mix16L(const float2* __restrict__ Y,
                 const unsigned long long sl = atomicAdd(po.count, 1ull);
                 if (int64_t(sl) < po.cap) {
                   rf_trigger tr;            // (re, im) for now; finished by k_trig_finish
-                  tr.tmpl = kb + acc_row(i, lane);
+                  tr.tmpl = po.tmpl0 + kb + acc_row(i, lane);
                   tr.seg = po.seg;
                   tr.idx = int32_t(m);
                   tr.absz = acc[a][b][0][i];
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(256, 1) void k_mix16L(const float2* __restrict__ Y,
       if (k >= nk) continue;
       unsigned long long b = 0ull;
       for (int s2 = 0; s2 < kLgSlots; ++s2) b = max(b, keys[kl * kLgSlots + s2]);
-      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + k), b);
+      if (b) atomicMax(reinterpret_cast<unsigned long long*>(po.packed + int64_t(po.seg) * po.nk + po.tmpl0 + k), b);
     }
   }
 }
@@ -781,6 +781,32 @@ void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count,
   if (cap <= 0) return;
   hipLaunchKernelGGL(k_trig_finish, dim3(nblocks(cap, 1024)), dim3(256), 0, ctx->stream, trig, count, cap);
   RF_HIP(hipGetLastError());
+}
+
+
+FactoredView factored_view(const rf_factored* F) { return FactoredView{F->device, F->n, F->nk, F->large}; }
+
+void factored_enqueue(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec, void* z_out,
+                      const PeakOut* po) {
+  fill_u32(ctx, F->zmax, 0u, 1);
+  // 512 workgroups at most: one atomic each on the one maximum (4096 took 50 us at 2^20)
+  hipLaunchKernelGGL(k_conj_max, dim3(nblocks(n, 512)), dim3(256), 0, ctx->stream,
+                     static_cast<const float2*>(z_ref), n, F->Qin, F->zmax);
+  RF_HIP(hipGetLastError());
+  fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
+  // basis correlations: the band products formed inside the first transform pass, in
+  // batches of at most 2^28 / n transforms (bounded transform scratch)
+  const int per = int(std::max<int64_t>(1, std::min<int64_t>(F->J, (int64_t(1) << 28) / n)));
+  for (int j0 = 0; j0 < F->J; j0 += per)
+    fft_inverse_band_f32(ctx, F->Q, F->Ub + int64_t(j0) * F->nb, F->b0, F->nb, float(1.0 / double(n)),
+                         F->Y + int64_t(j0) * n, n, std::min(per, F->J - j0));
+  const PeakOut p = po ? *po : PeakOut{};
+  if (F->large)
+    mix16L_launch(ctx, F, static_cast<float2*>(z_out), p, po != nullptr);
+  else if (prec == RF_PREC_SPLIT_FP16)
+    mix16_launch(ctx, F, static_cast<float2*>(z_out), p, po != nullptr);
+  else
+    mix_launch(ctx, F, static_cast<float2*>(z_out), p, po != nullptr);
 }
 
 }  // namespace rf
@@ -1030,24 +1056,7 @@ rf_status snr_reconstruct_factored(rf_ctx* ctx, const rf_factored* F, const void
       po.seg = 0;
       po.nk = F->nk;
     }
-    fill_u32(ctx, F->zmax, 0u, 1);
-    // 512 workgroups at most: one atomic each on the one maximum (4096 took 50 us at 2^20)
-    hipLaunchKernelGGL(k_conj_max, dim3(nblocks(n, 512)), dim3(256), 0, ctx->stream,
-                       static_cast<const float2*>(z_ref), n, F->Qin, F->zmax);
-    RF_HIP(hipGetLastError());
-    fft_inverse_f32(ctx, F->Qin, F->Q, n, 1);
-    // basis correlations: the band products formed inside the first transform pass, in
-    // batches of at most 2^28 / n transforms (bounded transform scratch)
-    const int per = int(std::max<int64_t>(1, std::min<int64_t>(F->J, (int64_t(1) << 28) / n)));
-    for (int j0 = 0; j0 < F->J; j0 += per)
-      fft_inverse_band_f32(ctx, F->Q, F->Ub + int64_t(j0) * F->nb, F->b0, F->nb, float(1.0 / double(n)),
-                           F->Y + int64_t(j0) * n, n, std::min(per, F->J - j0));
-    if (F->large)
-      mix16L_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
-    else if (prec == RF_PREC_SPLIT_FP16)
-      mix16_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
-    else
-      mix_launch(ctx, F, static_cast<float2*>(z_out), po, fused != nullptr);
+    factored_enqueue(ctx, F, z_ref, n, prec, z_out, fused ? &po : nullptr);
     if (fused) trig_finish(ctx, fused->trig, po.count, fused->cap);
     if (fused) {
       peaks_finalize(ctx, packed, F->nk, fused->peaks);

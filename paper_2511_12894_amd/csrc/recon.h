@@ -195,4 +195,18 @@ void trig_finish(rf_ctx* ctx, rf_trigger* trig, const unsigned long long* count,
 void fft_inverse_tmpl_peaks_f32(rf_ctx* ctx, const rf_grid* g, const float2* q, const Tf2Coef* coef, int nt,
                                 const double* moment, int batch, const PeakOut& po);
 
+// A factored set's reconstruction of one series z_ref (n samples), enqueued on the
+// context's stream: the basis correlations and the mixing into z_out and/or the
+// read-out po (packed peaks at po->seg * po->nk + po->tmpl0 + k, trigger records
+// raw until trig_finish).  Arguments checked by the caller.
+struct FactoredView {
+  int device;
+  int64_t n;
+  int32_t nk;
+  bool large;
+};
+FactoredView factored_view(const rf_factored* F);
+void factored_enqueue(rf_ctx* ctx, const rf_factored* F, const void* z_ref, int64_t n, rf_prec prec, void* z_out,
+                      const PeakOut* po);
+
 }  // namespace rf

@@ -93,7 +93,7 @@ void copy_sync(rf_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyK
 
 enum WsSlot {
   WS_FFT_A = 0, WS_FFT_B = 1, WS_RED = 2, WS_SPLIT = 3, WS_PEAK = 4, WS_COEF = 5, WS_BUILD = 6,
-  WS_Y = 7, WS_SCALAR = 8, WS_SCAN = 9, WS_TGT = 10
+  WS_Y = 7, WS_SCALAR = 8, WS_SCAN = 9, WS_TGT = 10, WS_ZREF = 11
 };
 
 inline bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }

@@ -30,6 +30,7 @@ EXPORTED = ("rf_ctx_create", "rf_ctx_destroy", "rf_last_error", "mf_ref_snr", "m
             "rf_surrogate_dataset", "rf_surrogate_grad", "rf_surrogate_train", "rf_surrogate_predict", "rf_surrogate_project",
             "rf_surrogate_encode", "rf_surrogate_decode",
             "rf_surrogate_kernels", "rf_factored_build", "rf_factored_info", "snr_reconstruct_factored",
+            "snr_reconstruct_factored_batch",
             "rf_factored_free", "rf_ols_build", "rf_ols_info", "snr_reconstruct_ols", "rf_ols_free",
             "rf_template_durations", "rf_bank_organise", "rf_surrogate_free")
 
@@ -133,6 +134,9 @@ def load(path: str = LIB_PATH):
     lib.rf_factored_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.snr_reconstruct_factored.argtypes = [vp, vp, vp, i64, i32, vp, ctypes.POINTER(RfPeakArgs)]
+    lib.snr_reconstruct_factored_batch.argtypes = [vp, ctypes.POINTER(RfGrid), vp, i32, vp, i32,
+                                                   ctypes.POINTER(vp), ctypes.POINTER(RfTmpl), i32,
+                                                   ctypes.POINTER(RfPeakArgs)]
     lib.rf_factored_free.argtypes = [vp]
     lib.rf_ols_build.argtypes = [vp, vp, i64, ctypes.POINTER(vp)]
     lib.rf_ols_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -629,6 +633,32 @@ class Surrogate:
             self.free()
         except Exception:
             pass
+
+
+def factored_batch(ctx: Context, grid, xf_segs: torch.Tensor, psd: torch.Tensor, sets, refs, thr: float,
+                   trig_cap: int = 1 << 16, prec: str = "split16"):
+    """snr_reconstruct_factored_batch: every (segment, set) pair's reference matched
+    filter and factored reconstruction with the fused read-out, one synchronisation.
+    peaks [nseg, ktot, 2] int32 (RfPeak bytes; set r's kernels from the sum of the
+    earlier sets' counts), triggers, count."""
+    n = int(grid.n)
+    _dev_tensor(xf_segs, torch.complex128, what="xf_segs")
+    _require(xf_segs.dim() == 2 and xf_segs.shape[1] == n // 2 + 1, "xf_segs: expected [nseg, n/2+1]")
+    _dev_tensor(psd, torch.float64, n // 2 + 1, what="psd")
+    _require(len(sets) == len(refs) and len(sets) >= 1, "sets and refs: one reference per set")
+    nseg = int(xf_segs.shape[0])
+    ktot = sum(F.nk for F in sets)
+    peaks = torch.empty((nseg, ktot, 2), dtype=torch.int32, device=xf_segs.device)
+    trig = torch.empty((max(trig_cap, 1), 5), dtype=torch.int32, device=xf_segs.device)
+    cnt = ctypes.c_int64(0)
+    args = RfPeakArgs(float(thr), peaks.data_ptr(), trig.data_ptr(), int(trig_cap), ctypes.pointer(cnt))
+    handles = (ctypes.c_void_p * len(sets))(*[F.h.value for F in sets])
+    g = to_grid(grid)
+    st = ctx.lib.snr_reconstruct_factored_batch(ctx.h, ctypes.byref(g), _ptr(xf_segs), nseg, _ptr(psd), len(sets),
+                                                handles, _tmpl_array(refs), PREC[prec], ctypes.byref(args))
+    if st not in (RF_OK, RF_E_OVERFLOW):
+        ctx.check(st)
+    return dict(peaks=peaks, trig=trig, ntrig=int(cnt.value), overflow=(st == RF_E_OVERFLOW))
 
 
 class Factored:

@@ -282,3 +282,60 @@ def test_large_set_matches_the_oracle_projection(rf, ctx, large, tol, jmax):
         F.reconstruct(large["z"], prec="fp32")
     assert e.value.code == rf.RF_E_UNSUPPORTED
     F.free()
+
+
+def test_batch_equals_per_call(rf, ctx):
+    """snr_reconstruct_factored_batch over several segments and sets (ragged kernel
+    counts): peaks bit-equal to the per-(segment, set) calls (mf_ref_snr of the
+    reference, then snr_reconstruct_factored), triggers the same records with the
+    set's kernel offset and the segment, and the overflow count exact."""
+    w = synth.workload_batched(n_seg=3, n_ref=4, duration=32.0, fs=1024.0, f_low=25.0, seed=1003,
+                               nbr_range=(8, 90))
+    g = w["grid"]
+    psd = torch.from_numpy(w["psd"]).cuda()
+    xf = torch.from_numpy(np.stack(w["segments"])).cuda()
+    ks = [rf.ratio_kernel_build(ctx, g, psd, r, grp) for r, grp in zip(w["refs"], w["groups"])]
+    sets = [rf.Factored(ctx, K, g, tol=2e-6, jmax=128) for K in ks]
+    counts = [K.nk for K in ks]
+    kbase = np.concatenate([[0], np.cumsum(counts)])
+    _say(f"factored batch: {len(sets)} sets of {counts} kernels, J = {[F.info()['J'] for F in sets]}")
+    thr = 4.0
+    b = rf.factored_batch(ctx, g, xf, psd, sets, w["refs"], thr, trig_cap=1 << 16)
+    assert not b["overflow"] and b["ntrig"] > 0
+    pv, pi = rf.decode_peaks(b["peaks"].view(-1, 2))
+    trig_b = sorted(rf.decode_triggers(b["trig"], b["ntrig"]))
+    trig_c, nt = [], 0
+    for s in range(len(w["segments"])):
+        for r, (ref, F) in enumerate(zip(w["refs"], sets)):
+            z, _ = rf.mf_ref_snr(ctx, g, xf[s], psd, [ref], want_sigma=False)
+            o = F.reconstruct(z[0].contiguous(), store=False, fused_thr=thr, trig_cap=1 << 16)
+            v, i = rf.decode_peaks(o["peaks"])
+            sl = slice(s * kbase[-1] + kbase[r], s * kbase[-1] + kbase[r + 1])
+            np.testing.assert_array_equal(pv[sl], v)
+            np.testing.assert_array_equal(pi[sl], i)
+            for (k, seg, m, a, ph) in rf.decode_triggers(o["trig"], o["ntrig"]):
+                trig_c.append((int(k + kbase[r]), s, m, a, ph))
+            nt += o["ntrig"]
+    assert b["ntrig"] == nt
+    assert trig_b == sorted(trig_c)
+    # a too small trigger buffer reports the true count
+    o = rf.factored_batch(ctx, g, xf, psd, sets, w["refs"], thr, trig_cap=3)
+    assert o["overflow"] and o["ntrig"] == nt
+    # argument errors
+    import ctypes
+    hs = (ctypes.c_void_p * 1)(sets[0].h.value)
+    gg = rf.to_grid(g)
+    args = rf.RfPeakArgs(thr, b["peaks"].data_ptr(), b["trig"].data_ptr(), 16, ctypes.pointer(ctypes.c_int64()))
+    f = ctx.lib.snr_reconstruct_factored_batch
+    assert f(ctx.h, ctypes.byref(gg), rf._ptr(xf), 0, rf._ptr(psd), 1, hs, rf._tmpl_array(w["refs"][:1]),
+             rf.PREC["split16"], ctypes.byref(args)) == rf.RF_E_INVAL
+    assert f(ctx.h, ctypes.byref(gg), rf._ptr(xf), 1, rf._ptr(psd), 1, hs, None,
+             rf.PREC["split16"], ctypes.byref(args)) == rf.RF_E_INVAL
+    g2 = synth.make_grid(g.fs, g.n * 2, g.f_low)
+    gg2 = rf.to_grid(g2)
+    assert f(ctx.h, ctypes.byref(gg2), rf._ptr(xf), 1, rf._ptr(psd), 1, hs, rf._tmpl_array(w["refs"][:1]),
+             rf.PREC["split16"], ctypes.byref(args)) == rf.RF_E_INVAL
+    for F in sets:
+        F.free()
+    for K in ks:
+        K.free()
