@@ -60,10 +60,12 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 // column slot; NTB = 1, a paired tile: times t_base + 32 (column / 16) of slot
 // column % 16), real and imaginary part.
 template <bool STORE, bool FUSED, int NTB>
-__device__ __attribute__((always_inline)) inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T, int64_t n, int64_t t_base,
-                                int lane, const float* __restrict__ colscale,
-                                const int32_t* __restrict__ slot_kernel, float extra_scale,
-                                float2* __restrict__ zout, const PeakOut& po) {
+__device__ __attribute__((always_inline)) inline void epilogue(floatx16 (&tot)[2][2], const TileDev& T,
+                                                               int64_t n, int64_t t_base, int lane,
+                                                               const float* __restrict__ colscale,
+                                                               const int32_t* __restrict__ slot_kernel,
+                                                               float extra_scale, float2* __restrict__ zout,
+                                                               const PeakOut& po) {
   const int col = lane & 31;
   const int slot = NTB == 1 ? (col & (kPairKernels - 1)) : col;
   const int64_t t_col = t_base + (NTB == 1 ? (col / kPairKernels) * kPairShift : 0);
@@ -177,11 +179,13 @@ __device__ inline void to_f32(const Tot64& t, floatx16 (&o)[2][2]) {
 // FP32 form, one workgroup: output times [n0, n0 + kTimes) of tile T; NTB time
 // blocks a wave (1 for a paired tile).
 template <bool STORE, bool FUSED, int NTB>
-__device__ __attribute__((always_inline)) inline void recon_f32_block(float (*zr)[kWin], float (*zi)[kWin], const float2* __restrict__ z,
-                                       int64_t n, const TileDev& T, const float* b32,
-                                       const float* __restrict__ colscale,
-                                       const int32_t* __restrict__ slot_kernel, float2* __restrict__ zout,
-                                       const PeakOut& po) {
+__device__ __attribute__((always_inline)) inline void recon_f32_block(float (*zr)[kWin], float (*zi)[kWin],
+                                                                      const float2* __restrict__ z, int64_t n,
+                                                                      const TileDev& T, const float* b32,
+                                                                      const float* __restrict__ colscale,
+                                                                      const int32_t* __restrict__ slot_kernel,
+                                                                      float2* __restrict__ zout,
+                                                                      const PeakOut& po) {
   const int64_t n0 = int64_t(blockIdx.x) * kTimes;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
@@ -325,12 +329,10 @@ __device__ inline half8 lds_frag(const _Float16* p) {
 // One work item of the split form: output times [n0, n0 + kTimes) of tile T,
 // window chunks of `chunk` taps (256, 512 or 1024; a multiple of 64).
 template <bool STORE, bool FUSED, int NTB>
-__device__ __attribute__((always_inline)) inline void recon_f16_item(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
-                                      int64_t n, const TileDev& T, int64_t n0, int chunk,
-                                      const __half* b16, const uint32_t* __restrict__ gflag,
-                                      const float* __restrict__ colscale,
-                                      const int32_t* __restrict__ slot_kernel, float zinv,
-                                      float2* __restrict__ zout, const PeakOut& po) {
+__device__ __attribute__((always_inline)) inline void recon_f16_item(
+    _Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs, int64_t n, const TileDev& T, int64_t n0,
+    int chunk, const __half* b16, const uint32_t* __restrict__ gflag, const float* __restrict__ colscale,
+    const int32_t* __restrict__ slot_kernel, float zinv, float2* __restrict__ zout, const PeakOut& po) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 31, kh = lane >> 5;
   const int sigma = row & 3;
@@ -585,12 +587,10 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(_Float16 (*
 
 // A work item on either tile kind (the branch is uniform over the workgroup).
 template <bool STORE, bool FUSED>
-__device__ __attribute__((always_inline)) inline void recon_f16_any(_Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs,
-                                     int64_t n, const TileDev& T, int64_t n0, int chunk,
-                                     const __half* b16, const uint32_t* __restrict__ gflag,
-                                     const float* __restrict__ colscale,
-                                     const int32_t* __restrict__ slot_kernel, float zinv,
-                                     float2* __restrict__ zout, const PeakOut& po) {
+__device__ __attribute__((always_inline)) inline void recon_f16_any(
+    _Float16 (*win)[4][4 * kWinMax], const __half* __restrict__ zs, int64_t n, const TileDev& T, int64_t n0,
+    int chunk, const __half* b16, const uint32_t* __restrict__ gflag, const float* __restrict__ colscale,
+    const int32_t* __restrict__ slot_kernel, float zinv, float2* __restrict__ zout, const PeakOut& po) {
   if (T.pair)
     recon_f16_item<STORE, FUSED, 1>(win, zs, n, T, n0, chunk, b16, gflag, colscale, slot_kernel, zinv, zout, po);
   else

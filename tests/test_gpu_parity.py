@@ -335,16 +335,20 @@ def test_empty_kernels_give_zero_series(rf, ctx, small, small_gpu):
     K.free()
 
 
-def test_ragged_tiles_and_reference_delta(rf, ctx, small, small_gpu):
-    """130 kernels (two tiles, the second holding 2) including the reference
-    itself, whose kernel reproduces z_ref up to truncation."""
+@pytest.mark.parametrize("prec", ["split16", "fp32"])
+def test_ragged_tiles_and_reference_delta(rf, ctx, small, small_gpu, prec):
+    """130 kernels (four full tiles and a paired last tile holding 2) including
+    the reference itself, whose kernel reproduces z_ref up to truncation; the
+    fused read-out of the paired tile equals the read-out of its stored series."""
     w = small["w"]
     g = w["grid"]
     nbrs = (w["nbrs"] * 9)[:129] + [w["ref"]]
     K = rf.ratio_kernel_build(ctx, g, small_gpu["psd"], w["ref"], nbrs)
-    out = rf.snr_reconstruct(ctx, K, small_gpu["zref"], prec="split16")
+    out = rf.snr_reconstruct(ctx, K, small_gpu["zref"], prec=prec, fused_thr=3.0, trig_cap=1 << 16)
+    ref = rf.snr_peaks(ctx, out["z"], 3.0, trig_cap=1 << 16)
+    _same_readout(rf, out, ref)
     z = out["z"].cpu().numpy()
-    for k in (0, 17, 128, 129):
+    for k in (0, 17, 127, 128, 129):
         kb = orat.build_kernel(g, w["ref"], nbrs[k])
         nk = omf.norm(g.fs, g.n, g.f_low, g.f_high, w["psd"], omf.template_spectrum(g.fs, g.n, *nbrs[k]))
         zo = orat.reconstruct(small["zr"], kb["m_lo"], kb["taps"], small["nr"] / nk)
