@@ -344,8 +344,9 @@ def test_ragged_tiles_and_reference_delta(rf, ctx, small, small_gpu, prec):
     g = w["grid"]
     nbrs = (w["nbrs"] * 9)[:129] + [w["ref"]]
     K = rf.ratio_kernel_build(ctx, g, small_gpu["psd"], w["ref"], nbrs)
-    out = rf.snr_reconstruct(ctx, K, small_gpu["zref"], prec=prec, fused_thr=3.0, trig_cap=1 << 16)
-    ref = rf.snr_peaks(ctx, out["z"], 3.0, trig_cap=1 << 16)
+    out = rf.snr_reconstruct(ctx, K, small_gpu["zref"], prec=prec, fused_thr=4.0, trig_cap=1 << 16)
+    ref = rf.snr_peaks(ctx, out["z"], 4.0, trig_cap=1 << 16)
+    assert not out["overflow"] and not ref["overflow"]
     _same_readout(rf, out, ref)
     z = out["z"].cpu().numpy()
     for k in (0, 17, 127, 128, 129):
