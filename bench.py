@@ -64,20 +64,26 @@ def timed(fn, steps, warmup, stream):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
-def counter_traffic(name):
-    """Calibrated HBM bytes per launch of a kernel from the committed rocprofv3
-    counter summary profiles/<name>_counters.json, or None when any source the
-    kernel is built from (the files listed there, headers included) changed
-    since the counters were taken."""
+def counter_summary(name):
+    """The committed rocprofv3 counter summary profiles/<name>_counters.json, or
+    None when any source the kernel is built from (the files listed there,
+    headers included) changed since the counters were taken."""
     import hashlib
     try:
         d = json.load(open(os.path.join(ROOT, "profiles", f"{name}_counters.json")))
         for rel, digest in d["sources_sha256"].items():
             if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != digest:
                 return None
-    except (OSError, ValueError, KeyError, AttributeError):
+        float(d["traffic_bytes_per_dispatch"])
+    except (OSError, ValueError, KeyError, AttributeError, TypeError):
         return None
-    return float(d["traffic_bytes_per_dispatch"])
+    return d
+
+
+def counter_traffic(name):
+    """Calibrated HBM bytes per launch of a kernel from its counter summary (None as above)."""
+    d = counter_summary(name)
+    return None if d is None else float(d["traffic_bytes_per_dispatch"])
 
 
 def host_cpu():
@@ -1035,6 +1041,9 @@ def main():
                     help="comma list of legs: headline (the batched workload at full shape), and on the "
                          "realistic workload step,fp32,direct,factored,ols,bank,learned, then batched (reduced), "
                          "factored_batched, stress (default: all of these); sweep only when named")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="launch-settings cache of the headline batch (read if it holds this shape, else "
+                         "appended after autotuning), so that profiled runs take the timed run's settings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -1060,7 +1069,7 @@ def main():
     extra = {}
     h = None
     if "headline" in legs:
-        h = headline_leg(dev, args.steps, args.warmup)
+        h = headline_leg(dev, args.steps, args.warmup, args.tuning_cache)
         g = h["grid"]
         samples = (h["ktot"] + h["nref"]) * g.n * h["nseg"]
         ms = h["wall_ms"] / args.steps
@@ -1068,8 +1077,13 @@ def main():
         alg = 4.0 * g.n * h["sum_l"] * h["nseg"]          # complex x real MAC per kept tap and output sample
         ach = alg / t_rec / 1e12
         out.update(value=samples / (ms * 1e-3), unit="template-samples/s", ms_per_step=ms)
+        cq = counter_summary("k_recon_f16_queue")
         out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / PEAK_FP16_TFLOPS, "traffic": counter_traffic("k_recon_f16_queue"),
+                           "frac": ach / PEAK_FP16_TFLOPS,
+                           "traffic": None if cq is None else float(cq["traffic_bytes_per_dispatch"]),
+                           # the launch settings the counters were taken at (traffic depends on them;
+                           # the run's own are config.tuning)
+                           "traffic_tuning": None if cq is None else cq.get("tuning"),
                            "kernel": "k_recon_f16_queue (persistent split-FP16 reconstruction, fused read-out)",
                            "kernel_ms": t_rec * 1e3, "flops_per_launch": alg,
                            "timed": "reconstruction graph per step (persistent launch + peak finalisation), "

@@ -278,7 +278,10 @@ rf_status rf_batch_set_tuning(rf_batch* b, const rf_batch_tuning* t);
  * time blocks (about four per workgroup of the launch, in runs of four spread
  * over the bucket's tiles, segments and times; best of three launches each),
  * then one queue against one per XCD on runs of time blocks of up to eight
- * tiles spread over the lengths; the buckets are the creation's tertiles.  When cache_path is given, a line keyed by the
+ * tiles spread over the lengths; the buckets are the creation's tertiles.  The
+ * candidates are tried in order of less memory traffic (chunks 1024, 512, 256;
+ * blocks 4, 2, 1; per-XCD queues before one queue) and a later one is taken only
+ * when more than 1 % faster.  When cache_path is given, a line keyed by the
  * batch's shape and the device name is read if present (no timing) or
  * appended.  Synchronises. */
 rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const char* cache_path);

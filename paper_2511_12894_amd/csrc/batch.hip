@@ -466,11 +466,17 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
       return qs;
     };
     const int32_t ntb = int32_t(b->n / kTimes);
+    // Candidates come in order of less memory traffic first (longer window chunks,
+    // more time blocks per item: fewer operand and window reloads and fewer item
+    // starts; per-XCD queues: a tile's operand stays in one L2), and a later one
+    // must be faster by more than 1 % to replace an earlier one: at a near tie the
+    // launch keeps the setting that moves less data.
+    auto better = [](float ms, float best) { return ms < 0.99f * best; };
     // (1) per bucket, chunk x blocks per item on the same sampled time blocks: about
     // four per workgroup slot, in groups of four consecutive blocks spread over the
     // bucket's (tile, segment, block) space
-    const int cand_chunk[3] = {256, 512, 1024};
-    const int cand_blocks[3] = {1, 2, 4};
+    const int cand_chunk[3] = {1024, 512, 256};
+    const int cand_blocks[3] = {4, 2, 1};
     for (int bk = 0; bk < 3; ++bk) {
       struct Group { int32_t seg, tile, q0, len; };
       std::vector<Group> all;
@@ -492,7 +498,7 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
             for (int32_t q = g.q0; q < g.q0 + g.len; q += nb)
               items.push_back(WorkItem{g.seg, g.tile, q, c, std::min(nb, g.q0 + g.len - q), 0});
           const float ms = time_list(items, one_queue(items.size()));
-          if (ms < best) {
+          if (better(ms, best)) {
             best = ms;
             b->chunk_for_bucket[bk] = c;
             b->blocks_for_bucket[bk] = nb;
@@ -507,12 +513,12 @@ rf_status rf_batch_autotune(rf_ctx* ctx, rf_batch* b, const void* xf_segs, const
       for (int i = 0; i < kMaxQueues && size_t(i) < nt; ++i) pick.push_back(b->order[size_t(i) * nt / kMaxQueues]);
       const int32_t run = std::min<int32_t>(ntb, std::max(16, int32_t(16 * size_t(b->nblocks) / std::max<size_t>(pick.size(), 1))));
       float best = 1e30f;
-      for (int x = 0; x < 2; ++x) {
+      for (int x = 1; x >= 0; --x) {
         std::vector<WorkItem> items;
         QueueSpec qs{};
         build_items(b, pick, x ? kMaxQueues : 1, 1, run, items, qs);
         const float ms = time_list(items, qs);
-        if (ms < best) {
+        if (better(ms, best)) {
           best = ms;
           b->xcd_queues = x;
         }
