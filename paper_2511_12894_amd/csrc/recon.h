@@ -20,7 +20,7 @@ constexpr int kCorrChunk = 512;
 constexpr int kStepAlign = 8;      // tiles span a multiple of 8 16-tap steps
 constexpr int kB32PerStep = 512;   // FP32 operand floats per 16-tap step of a tile
 constexpr int kB16PerStep = 1024;  // FP16 operand halves per 16-tap step (hi + lo)
-constexpr int kOperandPadSteps = 8; // zero steps after the last tile: operand prefetch past a
+constexpr int kOperandPadSteps = 16; // zero steps after the last tile: operand prefetch past a
                                     // tile's end stays inside the buffer
 
 

@@ -123,6 +123,10 @@ __device__ __attribute__((always_inline)) inline void epilogue(floatx16 (&tot)[2
 // where the kernels' large taps are.  At |z| ~ 20 the FP32 roundings of longer
 // partial sums reached 1.1e-5 (split) and 1.4e-5 (FP32) on some outputs.
 constexpr int kFoldF16 = 8;
+// Steps the split form's first pass loads its B fragments ahead.
+constexpr int kAheadB1 = 12;
+static_assert(kFoldF16 == 8, "pass 1 folds after every 8-step half of its 16-step groups");
+static_assert(kAheadB1 < 16 && kAheadB1 <= kOperandPadSteps, "B ring period and operand padding");
 constexpr int kFoldF32 = 16;
 // Split form: the hi*hi sums are folded every kFoldF16 steps only in the
 // 1024-tap blocks that hold a scaled tap of at least kFoldTap (1/64..1/32 of
@@ -424,8 +428,12 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(
   auto foldflag = [&](int c) {
     return (flagbits((int64_t(c) * chunk / 1024) * 1024, (int64_t(c + 1) * chunk + 1023) / 1024 * 1024) & 2) != 0;
   };
-  // B ring (slot = step % 8, six steps ahead); it runs on across consecutive chunks
-  half8 bh[8], bl[8];
+  // B ring, run on across consecutive chunks.  Pass 1 needs only the hi
+  // fragment: step s in slot s % 16, loaded kAheadB1 steps ahead, which also
+  // covers the window refill loads that the in-order load counter puts ahead
+  // of the later B loads.  Pass 2: hi and lo fragments of step s in slots
+  // s % 8 and 8 + s % 8, loaded six steps (of twice the matrix work) ahead.
+  half8 br[16];
   // Two passes over the item's window chunks.  Pass 1 (CORR false): the
   // hi*hi product of every chunk of `chunk` taps into `acc`, folded into the
   // FP64 total every kFoldF16 steps of the chunks with bit 2 and at the pass's
@@ -444,7 +452,7 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(
         while (c < nch && !flagged(c)) ++c;
       return c;
     };
-    auto loadB = [&](int64_t st, half8& h, half8& l) {   // st <= ksteps + 5: inside the padding
+    auto loadB = [&](int64_t st, half8& h, half8& l) {   // st < ksteps + kAheadB1: inside the padding
       if (CORR) l = B[st * 128 + 64];
       h = B[st * 128];
     };
@@ -466,8 +474,18 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(
       if (more) gather(tn, threadIdx.x);
       const int64_t s0 = t0 / 16;
       if (prev != c - 1) {
+        if constexpr (CORR) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) loadB(s0 + j, bh[j], bl[j]);
+          for (int j = 0; j < 6; ++j) loadB(s0 + j, br[j], br[8 + j]);
+        } else {
+          // in slot order: the load counter's waits in the step loop then
+          // hold the same slack on entry as from one group to the next
+#pragma unroll
+          for (int j = 0; j < kAheadB1; ++j) {
+            loadB(s0 + j, br[j], br[j]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
       }
       const _Float16* wb[4];
 #pragma unroll
@@ -500,14 +518,23 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(
       };
 #pragma unroll
       for (int j = 0; j < 4; ++j) loadF(j, f[j]);
-      // F runs four steps ahead, B six (slots step % 8); the LDS counter holds
-      // at most 15 fragment reads in flight, so more would only wait by count
-      auto steps = [&](int q, auto count) {
+      // F runs four steps ahead (slots step % 8); the LDS counter holds at most
+      // 15 fragment reads in flight, so more would only wait by count.  q is a
+      // multiple of 8 and, in pass 1, q % 16 == base; `pre` false: no B
+      // prefetch (pass 1's last group of a tile, which no chunk follows).
+      auto steps = [&](int q, auto count, auto base, auto pre) {
+        constexpr int B0 = decltype(base)::value;
 #pragma unroll
         for (int h = 0; h < decltype(count)::value; ++h) {
           loadF(q + h + 4, f[(h + 4) & 7]);
-          loadB(s0 + q + h + 6, bh[(h + 6) & 7], bl[(h + 6) & 7]);
-          mma(f[h & 7], f[(h + 2) & 7], bh[h & 7], bl[h & 7]);
+          if constexpr (CORR) {
+            loadB(s0 + q + h + 6, br[(h + 6) & 7], br[8 + ((h + 6) & 7)]);
+            mma(f[h & 7], f[(h + 2) & 7], br[h & 7], br[8 + (h & 7)]);
+          } else {
+            if constexpr (decltype(pre)::value)
+              loadB(s0 + q + h + kAheadB1, br[(B0 + h + kAheadB1) & 15], br[(B0 + h + kAheadB1) & 15]);
+            mma(f[h & 7], f[(h + 2) & 7], br[(B0 + h) & 15], br[(B0 + h) & 15]);
+          }
           // the step's loads issued one behind each of its first MFMAs, so that
           // every load issues while a matrix instruction runs
           if constexpr (NTB == 1) {
@@ -547,22 +574,32 @@ __device__ __attribute__((always_inline)) inline void recon_f16_item(
       const bool fold_here = !CORR && foldflag(c);
       bool round1 = false;
       int q = 0;
-      constexpr int P = CORR ? 32 : kFoldF16;
+      // pass 1: groups of 16 steps (the B ring's period), folded after each 8
+      constexpr int P = CORR ? 32 : 16;
       for (; q + P <= nst; q += P) {
-        steps(q, std::integral_constant<int, P>{});
-        if (fold_here) fold64(acc);
+        if constexpr (CORR) {
+          steps(q, std::integral_constant<int, 32>{}, std::integral_constant<int, 0>{}, std::true_type{});
+        } else {
+          steps(q, std::integral_constant<int, 8>{}, std::integral_constant<int, 0>{}, std::true_type{});
+          if (fold_here) fold64(acc);
+          steps(q + 8, std::integral_constant<int, 8>{}, std::integral_constant<int, 8>{}, std::true_type{});
+          if (fold_here) fold64(acc);
+        }
         if (more && !round1 && q + P >= 32) {
           put(buf ^ 1, threadIdx.x);
           gather(tn, threadIdx.x + 256);
           round1 = true;
         }
       }
-      if (q < nst) {
-        for (; q < nst; q += 8) {
-          steps(q, std::integral_constant<int, 8>{});
-          if (fold_here && (q + 8) % kFoldF16 == 0) fold64(acc);
-        }
-        if (fold_here && nst % kFoldF16 != 0) fold64(acc);
+      // the rest in groups of 8: in pass 2 up to three; in pass 1 at most one,
+      // with q % 16 == 0, only in a tile's last chunk (chunks span multiples
+      // of 16 steps), so it needs no B prefetch
+      if constexpr (CORR) {
+        for (; q < nst; q += 8)
+          steps(q, std::integral_constant<int, 8>{}, std::integral_constant<int, 0>{}, std::true_type{});
+      } else if (q < nst) {
+        steps(q, std::integral_constant<int, 8>{}, std::integral_constant<int, 0>{}, std::false_type{});
+        if (fold_here) fold64(acc);
       }
       if (more) put(buf ^ 1, threadIdx.x + (round1 ? 256 : 0));
       __syncthreads();
