@@ -142,7 +142,10 @@ void zgemm(rf_ctx* ctx, const double2* A, int64_t lda, int ta, int ca, const dou
 // C[M][N] = op(A)[M][K] op(B)[K][N]; op(A) = A [M][K] (ta = 0) or A^T with A
 // stored [K][M]; op(B) = B [K][N] (tb = 0) or B^T with B stored [N][K].
 // Epilogue: bias[N] added when bias != NULL; when act != NULL, C holds the
-// pre-activation and act = gelu(C).  64 x 64 tiles, 4 x 4 per thread.
+// pre-activation and act = gelu(C).  64 x 64 tiles staged through LDS in
+// 16-deep slices; each wavefront owns a 32 x 32 quarter on the FP32 matrix
+// cores (v_mfma_f32_32x32x2f32: FP32 products and sums, two k per
+// instruction).
 __device__ inline float gelu_f(float u) { return 0.5f * u * (1.f + erff(u * 0.70710678118654752f)); }
 __device__ inline float gelu_grad_f(float u) {
   return 0.5f * (1.f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
@@ -153,9 +156,10 @@ __global__ __launch_bounds__(256) void k_sgemm(const float* __restrict__ A, int 
                                                float* __restrict__ act, int M, int N, int K) {
   __shared__ float as[16][68];
   __shared__ float bs[16][68];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // the wave's quarter
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  float acc[4][4] = {};
+  floatx16 acc = {};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       const int kk = e / 64, r = e % 64;
@@ -164,31 +168,24 @@ __global__ __launch_bounds__(256) void k_sgemm(const float* __restrict__ A, int 
       bs[kk][r] = (j < N && k < K) ? (tb ? Bm[size_t(j) * K + k] : Bm[size_t(k) * N + j]) : 0.f;
     }
     __syncthreads();
+    // lane l supplies A[wr + l % 32][kk + l / 32] and B[kk + l / 32][wc + l % 32]
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) a[x] = as[kk][ty * 4 + x];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) b[y] = bs[kk][tx * 4 + y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(a[x], b[y], acc[x][y]);
-    }
+    for (int kk = 0; kk < 16; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(as[kk + (lane >> 5)][wr + (lane & 31)],
+                                                 bs[kk + (lane >> 5)][wc + (lane & 31)], acc, 0, 0, 0);
     __syncthreads();
   }
+  // accumulator element e of lane l: row acc_row(e, l), column l % 32 of the quarter
+  const int j = j0 + wc + (lane & 31);
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int i = i0 + ty * 4 + x, j = j0 + tx * 4 + y;
-      if (i < M && j < N) {
-        float v = acc[x][y] + (bias ? bias[j] : 0.f);
-        C[size_t(i) * N + j] = v;
-        if (act) act[size_t(i) * N + j] = gelu_f(v);
-      }
+  for (int e = 0; e < 16; ++e) {
+    const int i = i0 + wr + acc_row(e, lane);
+    if (i < M && j < N) {
+      const float v = acc[e] + (bias ? bias[j] : 0.f);
+      C[size_t(i) * N + j] = v;
+      if (act) act[size_t(i) * N + j] = gelu_f(v);
     }
+  }
 }
 
 void sgemm(rf_ctx* ctx, const float* A, int ta, const float* B, int tb, float* C, const float* bias,
